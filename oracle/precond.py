@@ -1,0 +1,106 @@
+"""Low-rank preconditioners applied through the matrix inversion lemma, FP64.
+
+Section 3.1 (Nystrom): with inducing set U (m rows of X),
+    P = K_XU K_UU^{-1} K_UX + lambda I,
+    P^{-1} v = lambda^{-1} [ v - K_XU (lambda K_UU + K_UX K_XU)^{-1} K_UX v ].
+The printed inverse omits the factor lambda in front of K_UU; the form above
+is the matrix inversion lemma applied to the stated P (the two agree only at
+lambda = 1).
+
+Section 3.1.1 (FITC): P = Q + diag(K - Q) + lambda I with Q = K_XU K_UU^{-1}
+K_UX.  The diagonal D = diag(K - Q) + lambda I takes the place of lambda I:
+    P^{-1} v = D^{-1} v - D^{-1} K_XU (K_UU + K_UX D^{-1} K_XU)^{-1} K_UX D^{-1} v.
+diag(K - Q) is clipped at zero against rounding.
+
+Section 3.2 (factor form): P = Phi Phi^T + lambda I,
+    P^{-1} v = lambda^{-1} [ v - Phi (lambda I + Phi^T Phi)^{-1} Phi^T v ],
+again with lambda restored in the core (printed as I + Phi^T Phi).
+
+K_UU carries a jitter delta I (the caller's value; the same on both sides),
+which changes P but never the solution of the preconditioned system.
+
+Pinned by (tests/test_oracle_precond.py): each apply against a direct solve
+with the dense P it defines; m = n Nystrom reproduces K (so PCG stops after
+one step); FITC has diag(P) = diag(K) + lambda exactly and D_u = lambda at
+inducing points; m = n FITC equals Nystrom; Phi built from the top
+eigenpairs of K leaves unit eigenvalues of P^{-1} K_y on that subspace.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .kernel import rbf_block
+
+
+class Preconditioner:
+    """P^{-1} as a callable, plus the dense P for small-n checks."""
+
+    def __init__(self, apply, dense, info=None):
+        self._apply = apply
+        self._dense = dense
+        self.info = info or {}
+
+    def __call__(self, R):
+        return self._apply(np.asarray(R, dtype=np.float64))
+
+    def dense(self):
+        return self._dense()
+
+
+def nystrom(X, sigma2, lengthscales, lam, idx, jitter=0.0):
+    X = np.asarray(X, dtype=np.float64)
+    Xu = X[np.asarray(idx)]
+    Kuu = rbf_block(Xu, Xu, sigma2, lengthscales) + jitter * np.eye(len(idx))
+    Kxu = rbf_block(X, Xu, sigma2, lengthscales)
+    core = lam * Kuu + Kxu.T @ Kxu
+
+    def apply(R):
+        return (R - Kxu @ np.linalg.solve(core, Kxu.T @ R)) / lam
+
+    def dense():
+        return Kxu @ np.linalg.solve(Kuu, Kxu.T) + lam * np.eye(X.shape[0])
+
+    return Preconditioner(apply, dense, {"Kxu": Kxu, "Kuu": Kuu})
+
+
+def fitc_diagonal(X, sigma2, lengthscales, lam, idx, jitter=0.0):
+    """D = max(diag(K - K_XU K_UU^{-1} K_UX), 0) + lambda."""
+    X = np.asarray(X, dtype=np.float64)
+    Xu = X[np.asarray(idx)]
+    Kuu = rbf_block(Xu, Xu, sigma2, lengthscales) + jitter * np.eye(len(idx))
+    Kxu = rbf_block(X, Xu, sigma2, lengthscales)
+    qdiag = np.sum(Kxu * np.linalg.solve(Kuu, Kxu.T).T, axis=1)
+    kdiag = np.full(X.shape[0], float(sigma2))   # k(x, x) = sigma^2, Eq. (1)
+    return np.maximum(kdiag - qdiag, 0.0) + lam
+
+
+def fitc(X, sigma2, lengthscales, lam, idx, jitter=0.0):
+    X = np.asarray(X, dtype=np.float64)
+    Xu = X[np.asarray(idx)]
+    Kuu = rbf_block(Xu, Xu, sigma2, lengthscales) + jitter * np.eye(len(idx))
+    Kxu = rbf_block(X, Xu, sigma2, lengthscales)
+    D = fitc_diagonal(X, sigma2, lengthscales, lam, idx, jitter)
+    core = Kuu + Kxu.T @ (Kxu / D[:, None])
+
+    def apply(R):
+        DR = R / D[:, None] if R.ndim == 2 else R / D
+        inner = Kxu @ np.linalg.solve(core, Kxu.T @ DR)
+        return DR - (inner / D[:, None] if R.ndim == 2 else inner / D)
+
+    def dense():
+        return Kxu @ np.linalg.solve(Kuu, Kxu.T) + np.diag(D)
+
+    return Preconditioner(apply, dense, {"D": D, "Kxu": Kxu, "Kuu": Kuu})
+
+
+def lowrank(Phi, lam):
+    Phi = np.asarray(Phi, dtype=np.float64)
+    core = lam * np.eye(Phi.shape[1]) + Phi.T @ Phi
+
+    def apply(R):
+        return (R - Phi @ np.linalg.solve(core, Phi.T @ R)) / lam
+
+    def dense():
+        return Phi @ Phi.T + lam * np.eye(Phi.shape[0])
+
+    return Preconditioner(apply, dense, {"Phi": Phi})

@@ -1,0 +1,77 @@
+"""Pins of the oracle's Nystrom / FITC / factor preconditioners (Sections 3.1, 3.2)."""
+import numpy as np
+
+from oracle import kernel as ok
+from oracle import precond as op
+from oracle.pcg import pcg
+from pkm_inputs import make
+
+
+def _case(n=300, m=40, seed=0):
+    p = make("block_fp32", seed=seed, n=n, m=m, n_probes=3)
+    return p
+
+
+def test_nystrom_apply_equals_dense_solve():
+    p = _case()
+    P = op.nystrom(p.X, p.sigma2, p.lengthscales, p.lam, p.idx, jitter=1e-8)
+    dense = P.dense()
+    assert np.allclose(dense, dense.T, atol=1e-12)
+    assert np.linalg.eigvalsh(dense).min() > 0
+    R = p.B
+    assert np.allclose(P(R), np.linalg.solve(dense, R), rtol=1e-8, atol=1e-8)
+
+
+def test_fitc_apply_equals_dense_solve_and_diagonal():
+    p = _case(seed=1)
+    P = op.fitc(p.X, p.sigma2, p.lengthscales, p.lam, p.idx, jitter=1e-8)
+    dense = P.dense()
+    # diag(P) = diag(K) + lambda exactly (up to the clip at zero)
+    assert np.allclose(np.diag(dense), p.sigma2 + p.lam, rtol=1e-10, atol=0)
+    D = P.info["D"]
+    assert np.all(D >= p.lam)
+    # at inducing points K - Q vanishes on the diagonal
+    assert np.allclose(D[p.idx], p.lam, rtol=0, atol=1e-6)
+    assert np.allclose(P(p.B), np.linalg.solve(dense, p.B), rtol=1e-8, atol=1e-8)
+
+
+def test_full_inducing_set_reproduces_K_and_one_step_pcg():
+    # A smooth-enough, well-conditioned case so that K_UU = K can be inverted.
+    rng = np.random.default_rng(5)
+    n, d = 64, 3
+    X = rng.random((n, d)) * 4.0
+    ls = np.array([0.3, 0.4, 0.5])
+    s2, lam = 1.0, 1e-2
+    idx = np.arange(n)
+    K = ok.kernel_matrix(X, s2, ls)
+    assert np.linalg.cond(K) < 1e6
+    Pn = op.nystrom(X, s2, ls, lam, idx)
+    assert np.allclose(Pn.dense(), K + lam * np.eye(n), rtol=1e-10, atol=1e-10)
+    Pf = op.fitc(X, s2, ls, lam, idx)
+    assert np.allclose(Pf.dense(), Pn.dense(), rtol=1e-10, atol=1e-10)
+    B = rng.standard_normal((n, 2))
+    res = pcg(lambda V: ok.kernel_mvm(X, s2, ls, lam, V), B, precond=Pn, tol=1e-9, max_iter=20)
+    assert np.all(res.iters == 1)
+
+
+def test_factor_form_with_top_eigenpairs():
+    p = _case(n=200, seed=2)
+    K = ok.kernel_matrix(p.X, p.sigma2, p.lengthscales)
+    w, V = np.linalg.eigh(K)
+    r = 12
+    Phi = V[:, -r:] * np.sqrt(w[-r:])
+    P = op.lowrank(Phi, p.lam)
+    Ky = K + p.lam * np.eye(p.n)
+    PinvKy = P(Ky)
+    # on the top-r eigenvectors P^{-1} K_y acts as the identity
+    assert np.allclose(PinvKy @ V[:, -r:], V[:, -r:], atol=1e-8)
+    assert np.allclose(P(p.B), np.linalg.solve(P.dense(), p.B), rtol=1e-8, atol=1e-8)
+
+
+def test_nystrom_reduces_iterations():
+    p = make("small_fp64", seed=0, n=1024, m=64)
+    mv = lambda V: ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, V)
+    P = op.nystrom(p.X, p.sigma2, p.lengthscales, p.lam, p.idx, jitter=1e-8)
+    plain = pcg(mv, p.y, tol=1e-8, max_iter=5000)
+    pre = pcg(mv, p.y, precond=P, tol=1e-8, max_iter=5000)
+    assert pre.iters[0] < plain.iters[0]
