@@ -1,0 +1,186 @@
+"""Benchmark: time to a 1e-6 relative-residual preconditioned CG solve on kernel
+matrices, plus kernel-product TFLOP/s, on one MI355X.
+
+One step is the whole hot path on one synthetic problem resident in HBM:
+Nystrom preconditioner setup (m inducing points), PCG on the right-hand-side
+block [y, Z] (Z: Rademacher probes) to a certified FP64 true relative
+residual of 1e-6 with FP32 MFMA kernel products and FP64 reliable updates,
+and the Hutchinson gradient pass of the log-marginal likelihood.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload block_fp32]
+
+Prints one JSON line (rank 0).  ``value`` is the median step time in seconds
+(lower is better).  The ``roofline`` object reports the FP32 kernel-product
+kernel (the dominant kernel) from HIP events around each of its launches
+during the timed steps; ``cpu_baseline`` times the FP64 CPU oracle on a
+bounded sample of the same work.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("time to 1e-6 rel. residual PCG solve (mixed/learned vs plain); "
+          "kernel-MVM TFLOP/s")
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def _describe(p, m):
+    return (f"{p.name}: n={p.n}, d={p.d}, X~U[0,1], ARD lengthscales LogU[0.1,1], "
+            f"sigma2={p.sigma2}, lambda={p.lam}, k=1+{p.Z.shape[1]} (y + Rademacher probes), "
+            f"Nystrom m={m}, tol={p.tol}, FP32 MFMA products, FP64 vectors, "
+            f"FP64 true residual every 25 steps; step = setup + solve + gradient")
+
+
+def cpu_baseline(p, gpu_iters, budget_rows=1024):
+    """FP64 oracle on a bounded sample: product rows, setup, gradient rows."""
+    from oracle import gradient as og
+    from oracle import kernel as ok
+    from oracle import precond as op
+
+    threads = int(os.environ.get("PKM_ORACLE_THREADS", os.cpu_count() or 1))
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(p.n, size=budget_rows, replace=False))
+    B = p.B
+    t0 = time.perf_counter()
+    ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, B, rows=rows, threads=threads)
+    t_rows = time.perf_counter() - t0
+    t_mvm = t_rows * p.n / budget_rows
+    t0 = time.perf_counter()
+    P = op.nystrom(p.X, p.sigma2, p.lengthscales, p.lam, p.idx, jitter=1e-8)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    P(B)
+    t_apply = time.perf_counter() - t0
+    grows = budget_rows // 4
+    t0 = time.perf_counter()
+    sub = rows[:grows]
+    # the gradient pass's work per row block, scaled to all rows
+    og.bilinear_forms(p.X[sub], p.sigma2, p.lengthscales, p.lam, B[sub], B[sub])
+    Kb_time = time.perf_counter() - t0
+    t_grad = Kb_time * (p.n / grows) * (p.n / grows)
+    total = t_setup + gpu_iters * (t_mvm + t_apply) + t_grad
+    sample = (f"oracle kernel_mvm on {budget_rows} of {p.n} rows scaled x{p.n / budget_rows:.0f} "
+              f"per product, x{gpu_iters} products (the GPU solve's step count); Nystrom setup "
+              f"and one preconditioner apply timed in full; gradient forms on a "
+              f"{grows}x{grows} block scaled by (n/{grows})^2; extrapolated, FP64")
+    return {"value": total, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": sample, "per_product_s": t_mvm, "setup_s": t_setup}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="block_fp32")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1602_06693_amd import binding as pk
+    from pkm_inputs import make
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    p = make(a.workload, seed=a.seed)
+    m = len(p.idx)
+    N = p.Z.shape[1]
+    dev = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).to("cuda:0")
+    X, y, Z, idx = dev(p.X), dev(p.y), dev(p.Z), dev(p.idx)
+    sol = torch.zeros((p.n, 1 + N), dtype=torch.float64, device="cuda:0")
+    ctx = pk.pkm_create(0, pk.current_stream_handle())
+    prob = pk.Problem(X, p.lengthscales, p.sigma2, p.lam)
+    opts = pk.make_opts(tol=p.tol, prec=pk.PKM_FP32, reliable_every=25)
+
+    def step():
+        pc = pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_NYSTROM, m, idx=idx, jitter=1e-8)
+        try:
+            g, info = pk.pkm_lml_grad(ctx, prob, y, Z, pc=pc, opts=opts, sol=sol)
+        finally:
+            pk.pkm_precond_destroy(pc)
+        return g, info
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    pk.pkm_mvm_stats_reset(ctx)
+    pk.pkm_timing_enable(ctx, True)
+    times, infos = [], []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(a.steps):
+        t0 = time.perf_counter()
+        g, info = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        infos.append(info)
+        print(f"step {len(times)}: {times[-1]:.3f} s, iters {info.total_iters}, "
+              f"true residuals {info.true_residuals}, max relres {info.relres_true.max():.2e}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t_all
+    pk.pkm_timing_enable(ctx, False)
+    st = pk.pkm_mvm_stats(ctx, pk.PKM_FP32)
+    st64 = pk.pkm_mvm_stats(ctx, pk.PKM_FP64)
+    pk.pkm_destroy(ctx)
+
+    info = infos[-1]
+    assert np.all(info.col_status == pk.PKM_COL_CONVERGED), info.col_status
+    assert np.all(info.relres_true <= p.tol)
+    avg_ms = st["ms"] / max(st["launches"], 1)
+    flops_per_launch = st["flops"] / max(st["launches"], 1)
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    value = statistics.median(times)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * t_all / a.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": _describe(p, m), "n": p.n, "d": p.d, "k": 1 + N, "m": m,
+                   "preconditioner": "nystrom", "parallelism": "single GPU"},
+        "iters": int(info.total_iters),
+        "true_residual_products": int(info.true_residuals),
+        "max_true_relres": float(info.relres_true.max()),
+        "mvm_tflops": achieved,
+        "mvm_ms": avg_ms,
+        "fp64_true_residual_ms": st64["ms"] / max(st64["launches"], 1),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+                     "traffic": None,
+                     "kernel": "k_mvm_f32 (fused FP32 MFMA distance + exp2 + K V)",
+                     "flops_per_launch": flops_per_launch,
+                     "flop_count": "n^2 (2 d + 2 k) per product"},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, int(info.total_iters))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

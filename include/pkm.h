@@ -1,0 +1,198 @@
+/*
+ * pkm -- preconditioned conjugate gradients on kernel matrices, MI355X (gfx950).
+ *
+ * C ABI of the library libpkm.so.  Operations follow "Preconditioning Kernel
+ * Matrices" (Cutajar, Osborne, Cunningham, Filippone, ICML 2016):
+ *
+ *   kernel          ARD-RBF, Eq. (1):
+ *                   k(x_i, x_j) = sigma2 * exp(-1/2 sum_r (x_ir - x_jr)^2 / l_r^2)
+ *   system matrix   K_y = K + lambda I (Section 2.1)
+ *   solver          preconditioned CG, Algorithm 1 (textbook reading, see
+ *                   pkm_solve), applied independently to every column of a
+ *                   right-hand-side block [y, r_1 .. r_N]
+ *   preconditioners Nystrom (Section 3.1), FITC (Section 3.1.1) and a
+ *                   caller-given factor Phi (Section 3.2), all applied through
+ *                   the matrix inversion lemma
+ *   gradient        log-marginal-likelihood gradient, Eq. (2), with the trace
+ *                   estimated from Rademacher probes (Section 2.1)
+ *
+ * K is never stored: every product regenerates kernel tiles from X.
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are row-major.  An "n x k block" has element (i, c) at
+ *     offset i * k + c.
+ *   - "device" pointers are HIP device memory on the context's device,
+ *     owned by the caller, and must stay valid until the context's stream
+ *     has passed the call.  "host" pointers are ordinary host memory.
+ *   - Calls are enqueued on the context's stream.  Calls with host outputs
+ *     (pkm_solve's info, gradients, statistics) synchronise that stream
+ *     before they return.
+ *   - Return value: PKM_OK (0), a positive warning, or a negative error.
+ *     On error nothing has been launched unless stated otherwise, and
+ *     pkm_last_error() describes the cause.  No C++ exception or abort
+ *     crosses this interface.
+ *   - Objects created by the library (pkm_ctx, pkm_precond) are owned by it
+ *     and released by the matching *_destroy call.
+ */
+#ifndef PKM_H
+#define PKM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define PKM_OK               0
+#define PKM_NOT_CONVERGED    1   /* warning: some column hit max_iter      */
+#define PKM_ERR_INVALID     -1   /* bad argument; nothing launched          */
+#define PKM_ERR_BREAKDOWN   -2   /* p^T K_y p <= 0, r^T z <= 0, or NaN/Inf  */
+#define PKM_ERR_HIP         -3   /* a HIP runtime call failed               */
+#define PKM_ERR_OOM         -4   /* device allocation failed                */
+#define PKM_ERR_UNSUPPORTED -5   /* valid request this build cannot serve   */
+
+/* ---- arithmetic of the kernel product ---------------------------------- */
+#define PKM_FP64   0   /* FP64 distances, exp and accumulation             */
+#define PKM_FP32   1   /* FP32 MFMA distances and K x V, FP32 accumulation  */
+
+/* ---- preconditioner kinds ---------------------------------------------- */
+#define PKM_PC_NONE     0
+#define PKM_PC_NYSTROM  1   /* P = K_XU K_UU^-1 K_UX + lambda I  (Section 3.1)   */
+#define PKM_PC_FITC     2   /* P = Q + diag(K - Q) + lambda I   (Section 3.1.1) */
+#define PKM_PC_LOWRANK  3   /* P = Phi Phi^T + lambda I         (Section 3.2)   */
+
+/* ---- per-column solver status ------------------------------------------ */
+#define PKM_COL_CONVERGED  0
+#define PKM_COL_MAX_ITER   1
+#define PKM_COL_BREAKDOWN  2
+
+typedef struct pkm_ctx pkm_ctx;
+typedef struct pkm_precond pkm_precond;
+
+/* One GP regression problem (Section 2): inputs X, kernel hyperparameters
+ * theta = (sigma2, l_1 .. l_d) of Eq. (1), and noise variance lambda.
+ *   n >= 1, 1 <= d <= 64, sigma2 > 0, lambda > 0, every l_r > 0.          */
+typedef struct {
+    int64_t       n;
+    int32_t       d;
+    int32_t       reserved;      /* must be 0 */
+    const double* X;             /* device, n x d, FP64                        */
+    const double* lengthscales;  /* host, d values l_r                         */
+    double        sigma2;
+    double        lambda;
+} pkm_problem;
+
+/* Solver options.  Zero-initialised fields take the documented default.   */
+typedef struct {
+    double  tol;             /* relative residual |b - K_y x|_2 / |b|_2 per
+                                column; default 1e-6                         */
+    int64_t max_iter;        /* default 100000 (the paper's cap, Section 4)  */
+    int32_t prec;            /* PKM_FP64 or PKM_FP32 for the product inside
+                                the loop; default PKM_FP32                  */
+    int32_t reliable_every;  /* FP64 true-residual replacement period (FP32
+                                products only); default 25                  */
+    int32_t check_every;     /* host convergence poll period; default 1     */
+    int32_t use_x0;          /* nonzero: X holds x0 on entry; else x0 = 0    */
+} pkm_solve_opts;
+
+/* Solver report.  Array fields are host arrays of k entries provided by the
+ * caller (any may be NULL); scalar fields are written by the library.      */
+typedef struct {
+    int64_t* iters;          /* CG steps per column                          */
+    double*  relres_true;    /* final FP64 |b - K_y x| / |b| per column      */
+    double*  relres_rec;     /* final recursive residual per column          */
+    int32_t* col_status;     /* PKM_COL_* per column                         */
+    int64_t  total_iters;    /* steps of the shared loop                     */
+    int64_t  true_residuals; /* FP64 true-residual products performed        */
+    double   solve_ms;       /* wall time of the solve on the stream         */
+} pkm_solve_info;
+
+/* ---- context ------------------------------------------------------------
+ * Binds a HIP device and stream (a hipStream_t passed as void*, NULL for the
+ * null stream).  The context owns its scratch buffers.  Not thread-safe: one
+ * host thread per context.                                                  */
+int pkm_create(pkm_ctx** out, int device, void* stream);
+int pkm_destroy(pkm_ctx* ctx);
+/* Message for the last failing call on ctx (or on any context when ctx is
+ * NULL, per host thread).  Never NULL.                                      */
+const char* pkm_last_error(const pkm_ctx* ctx);
+/* Library build string (architecture and version).                          */
+const char* pkm_version(void);
+
+/* ---- kernel product (Section 2.1: the O(n^2) operation of every CG step) --
+ * Y = (K + lambda I) V for V, Y device n x k FP64 (k >= 1).  prec selects
+ * the arithmetic of the K V part (the lambda V term is always FP64).
+ * Y may not alias V.                                                         */
+int pkm_kernel_mvm(pkm_ctx* ctx, const pkm_problem* prob, int32_t k,
+                   int32_t prec, const double* V, double* Y);
+
+/* ---- preconditioner setup (Sections 3.1, 3.1.1, 3.2) ----------------------
+ * NYSTROM / FITC: inducing points U = X[idx], idx a device array of m
+ *   distinct indices in [0, n); jitter >= 0 is added to the diagonal of K_UU.
+ * LOWRANK: factor Phi given as a device n x m FP64 array (idx ignored).
+ * The result represents P^-1 = D^-1 - Psi Psi^T (matrix inversion lemma with
+ * the noise, or noise plus FITC diagonal, as D); it is owned by the library.
+ * 1 <= m <= min(n, 4096).                                                    */
+int pkm_precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int32_t kind,
+                      int32_t m, const int32_t* idx, const double* Phi,
+                      double jitter, pkm_precond** out);
+/* Z = P^-1 R for R, Z device n x k FP64 (may not alias).                   */
+int pkm_precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int32_t k,
+                      const double* R, double* Z);
+/* Host copy of the preconditioner's diagonal part D (n values).           */
+int pkm_precond_diag(pkm_ctx* ctx, const pkm_precond* pc, double* D_host);
+int pkm_precond_destroy(pkm_precond* pc);
+
+/* ---- PCG solve (Algorithm 1) --------------------------------------------
+ * Solves K_y X = B for every column of the device n x k FP64 block B; X is a
+ * device n x k FP64 block (x0 on entry when opts->use_x0).  pc may be NULL
+ * (plain CG).  Textbook recurrences per column; the solution accumulates in
+ * FP64.  A column whose recursive residual meets tol stops stepping until
+ * an FP64 true residual b - K_y x certifies it (that check runs once every
+ * live column has stopped); if it fails, r is replaced by the true residual
+ * and the column resumes.  With PKM_FP32 products the same replacement also
+ * runs every reliable_every steps.  A column converges when its FP64 true
+ * relative residual is <= tol.  Returns PKM_NOT_CONVERGED if a column reached max_iter and
+ * PKM_ERR_BREAKDOWN if one broke down; X holds the last iterate either way. */
+int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
+              int32_t k, const double* B, double* X,
+              const pkm_solve_opts* opts, pkm_solve_info* info);
+
+/* ---- gradient pass (Eq. (2) with the trace estimate of Section 2.1) -------
+ * Given alpha = K_y^-1 y and S = K_y^-1 Z for N Rademacher probes Z, writes
+ * the d + 2 host values
+ *   g_i = 1/2 alpha^T dK_y_i alpha - 1/(2N) sum_c s_c^T dK_y_i z_c
+ * for theta = (log sigma2, log l_1 .. log l_d, log lambda), i.e.
+ *   dK_y/dlog sigma2 = K,  dK_y/dlog l_r = K o (x_ir - x_jr)^2 / l_r^2,
+ *   dK_y/dlog lambda = lambda I.
+ * AS = [alpha, S] and YZ = [y-solution alpha, Z] are device n x (1 + N) FP64
+ * blocks: column 0 of both is alpha; columns 1..N are s_c and z_c.  N >= 0
+ * (N = 0 gives the data-fit term only).  Arithmetic is FP64.               */
+int pkm_grad_pass(pkm_ctx* ctx, const pkm_problem* prob, int32_t N,
+                  const double* AS, const double* YZ, double* grad_host);
+
+/* ---- solve + gradient --------------------------------------------------
+ * Solves K_y [alpha, S] = [y, Z] with pc and opts, then runs the gradient
+ * pass.  y is device n, Z device n x N (N >= 1).  Solutions are written to
+ * sol (device n x (1 + N), may be NULL).  info arrays, if given, hold
+ * 1 + N entries.                                                           */
+int pkm_lml_grad(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
+                 const double* y, int32_t N, const double* Z,
+                 const pkm_solve_opts* opts, double* grad_host, double* sol,
+                 pkm_solve_info* info);
+
+/* ---- measurement ----------------------------------------------------------
+ * When enabled, every kernel-product launch is bracketed by HIP events on
+ * the context's stream.  pkm_mvm_stats returns, since the last reset, the
+ * launch count, the summed launch time in ms, and the summed algorithmic
+ * work: kernel entries n^2 and flops n^2 (2d + 2k) of the products.        */
+int pkm_timing_enable(pkm_ctx* ctx, int32_t on);
+int pkm_mvm_stats(pkm_ctx* ctx, int32_t prec, int64_t* launches, double* ms,
+                  double* pairs, double* flops);
+int pkm_mvm_stats_reset(pkm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PKM_H */

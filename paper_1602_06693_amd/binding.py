@@ -1,0 +1,297 @@
+"""ctypes binding of libpkm (include/pkm.h).  Argument marshalling only.
+
+Every function keeps the C name and forwards to the library; torch is used
+only to own device memory and to name the current HIP stream.  Tensors must
+be float64 (int32 for inducing indices), contiguous and on the context's
+device.  Errors raise ``PkmError`` carrying the library's status and message.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpkm.so")
+
+PKM_OK = 0
+PKM_NOT_CONVERGED = 1
+PKM_ERR_INVALID = -1
+PKM_ERR_BREAKDOWN = -2
+PKM_ERR_HIP = -3
+PKM_ERR_OOM = -4
+PKM_ERR_UNSUPPORTED = -5
+
+PKM_FP64 = 0
+PKM_FP32 = 1
+
+PKM_PC_NONE = 0
+PKM_PC_NYSTROM = 1
+PKM_PC_FITC = 2
+PKM_PC_LOWRANK = 3
+
+PKM_COL_CONVERGED = 0
+PKM_COL_MAX_ITER = 1
+PKM_COL_BREAKDOWN = 2
+
+# every symbol include/pkm.h declares
+EXPORTS = (
+    "pkm_create", "pkm_destroy", "pkm_last_error", "pkm_version", "pkm_kernel_mvm",
+    "pkm_precond_setup", "pkm_precond_apply", "pkm_precond_diag", "pkm_precond_destroy",
+    "pkm_solve", "pkm_grad_pass", "pkm_lml_grad", "pkm_timing_enable", "pkm_mvm_stats",
+    "pkm_mvm_stats_reset",
+)
+
+
+class pkm_problem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("reserved", C.c_int32),
+                ("X", C.c_void_p), ("lengthscales", C.POINTER(C.c_double)),
+                ("sigma2", C.c_double), ("lambda_", C.c_double)]
+
+
+class pkm_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("prec", C.c_int32),
+                ("reliable_every", C.c_int32), ("check_every", C.c_int32),
+                ("use_x0", C.c_int32)]
+
+
+class pkm_solve_info(C.Structure):
+    _fields_ = [("iters", C.POINTER(C.c_int64)), ("relres_true", C.POINTER(C.c_double)),
+                ("relres_rec", C.POINTER(C.c_double)), ("col_status", C.POINTER(C.c_int32)),
+                ("total_iters", C.c_int64), ("true_residuals", C.c_int64),
+                ("solve_ms", C.c_double)]
+
+
+class PkmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pkm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libpkm.so (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_1602_06693_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    sig = {
+        "pkm_create": (C.c_int, [P(vp), C.c_int, vp]),
+        "pkm_destroy": (C.c_int, [vp]),
+        "pkm_last_error": (C.c_char_p, [vp]),
+        "pkm_version": (C.c_char_p, []),
+        "pkm_kernel_mvm": (C.c_int, [vp, P(pkm_problem), i32, i32, vp, vp]),
+        "pkm_precond_setup": (C.c_int, [vp, P(pkm_problem), i32, i32, vp, vp, dbl, P(vp)]),
+        "pkm_precond_apply": (C.c_int, [vp, vp, i32, vp, vp]),
+        "pkm_precond_diag": (C.c_int, [vp, vp, P(dbl)]),
+        "pkm_precond_destroy": (C.c_int, [vp]),
+        "pkm_solve": (C.c_int, [vp, P(pkm_problem), vp, i32, vp, vp, P(pkm_solve_opts),
+                                P(pkm_solve_info)]),
+        "pkm_grad_pass": (C.c_int, [vp, P(pkm_problem), i32, vp, vp, P(dbl)]),
+        "pkm_lml_grad": (C.c_int, [vp, P(pkm_problem), vp, vp, i32, vp, P(pkm_solve_opts),
+                                   P(dbl), vp, P(pkm_solve_info)]),
+        "pkm_timing_enable": (C.c_int, [vp, i32]),
+        "pkm_mvm_stats": (C.c_int, [vp, i32, P(i64), P(dbl), P(dbl), P(dbl)]),
+        "pkm_mvm_stats_reset": (C.c_int, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc, ctx=None, allow=(PKM_OK,)):
+    if rc in allow:
+        return rc
+    lib = load()
+    msg = lib.pkm_last_error(ctx).decode()
+    raise PkmError(rc, msg)
+
+
+def _ptr(t, dtype="float64"):
+    if t is None:
+        return None
+    import torch
+    want = {"float64": torch.float64, "int32": torch.int32}[dtype]
+    if t.dtype != want:
+        raise TypeError(f"expected {want}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if t.device.type != "cuda":
+        raise ValueError("tensor must live on the GPU")
+    return C.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """pkm_problem plus the host array it points to (kept alive here)."""
+
+    def __init__(self, X, lengthscales, sigma2, lam):
+        self.X = X
+        self.ls = np.ascontiguousarray(np.asarray(lengthscales, dtype=np.float64))
+        self.struct = pkm_problem(
+            n=X.shape[0], d=X.shape[1], reserved=0, X=_ptr(X),
+            lengthscales=self.ls.ctypes.data_as(C.POINTER(C.c_double)),
+            sigma2=float(sigma2), lambda_=float(lam))
+
+    @property
+    def n(self):
+        return self.struct.n
+
+    @property
+    def d(self):
+        return self.struct.d
+
+    @property
+    def ref(self):
+        return C.byref(self.struct)
+
+
+def pkm_version():
+    return load().pkm_version().decode()
+
+
+def pkm_create(device=0, stream=None):
+    """Create a context bound to ``device`` and a HIP stream handle (int or None)."""
+    lib = load()
+    out = C.c_void_p()
+    s = C.c_void_p(stream) if stream else None
+    _check(lib.pkm_create(C.byref(out), int(device), s))
+    return out
+
+
+def current_stream_handle():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def pkm_destroy(ctx):
+    return load().pkm_destroy(ctx)
+
+
+def pkm_kernel_mvm(ctx, prob: Problem, V, prec=PKM_FP32, Y=None):
+    import torch
+    if Y is None:
+        Y = torch.empty_like(V)
+    k = V.shape[1] if V.dim() == 2 else 1
+    _check(load().pkm_kernel_mvm(ctx, prob.ref, k, prec, _ptr(V), _ptr(Y)), ctx)
+    return Y
+
+
+def pkm_precond_setup(ctx, prob: Problem, kind, m, idx=None, Phi=None, jitter=0.0):
+    out = C.c_void_p()
+    _check(load().pkm_precond_setup(ctx, prob.ref, kind, int(m), _ptr(idx, "int32"),
+                                    _ptr(Phi), float(jitter), C.byref(out)), ctx)
+    return out
+
+
+def pkm_precond_apply(ctx, pc, R, Z=None):
+    import torch
+    if Z is None:
+        Z = torch.empty_like(R)
+    k = R.shape[1] if R.dim() == 2 else 1
+    _check(load().pkm_precond_apply(ctx, pc, k, _ptr(R), _ptr(Z)), ctx)
+    return Z
+
+
+def pkm_precond_diag(ctx, pc, n):
+    D = np.empty(n)
+    _check(load().pkm_precond_diag(ctx, pc, D.ctypes.data_as(C.POINTER(C.c_double))), ctx)
+    return D
+
+
+def pkm_precond_destroy(pc):
+    return load().pkm_precond_destroy(pc)
+
+
+class SolveInfo:
+    def __init__(self, k):
+        self.iters = np.zeros(k, np.int64)
+        self.relres_true = np.zeros(k)
+        self.relres_rec = np.zeros(k)
+        self.col_status = np.zeros(k, np.int32)
+        self.struct = pkm_solve_info(
+            iters=self.iters.ctypes.data_as(C.POINTER(C.c_int64)),
+            relres_true=self.relres_true.ctypes.data_as(C.POINTER(C.c_double)),
+            relres_rec=self.relres_rec.ctypes.data_as(C.POINTER(C.c_double)),
+            col_status=self.col_status.ctypes.data_as(C.POINTER(C.c_int32)))
+        self.rc = 0
+
+    @property
+    def total_iters(self):
+        return self.struct.total_iters
+
+    @property
+    def true_residuals(self):
+        return self.struct.true_residuals
+
+    @property
+    def solve_ms(self):
+        return self.struct.solve_ms
+
+
+def make_opts(tol=1e-6, max_iter=100000, prec=PKM_FP32, reliable_every=25, check_every=1,
+              use_x0=False):
+    return pkm_solve_opts(tol=tol, max_iter=max_iter, prec=prec, reliable_every=reliable_every,
+                          check_every=check_every, use_x0=1 if use_x0 else 0)
+
+
+def pkm_solve(ctx, prob: Problem, B, pc=None, X=None, opts=None, allow_warning=True):
+    """Returns (X, SolveInfo); PKM_NOT_CONVERGED is returned in info.rc when allowed."""
+    import torch
+    if X is None:
+        X = torch.zeros_like(B)
+    k = B.shape[1] if B.dim() == 2 else 1
+    info = SolveInfo(k)
+    opts = opts or make_opts()
+    rc = load().pkm_solve(ctx, prob.ref, pc, k, _ptr(B), _ptr(X), C.byref(opts),
+                          C.byref(info.struct))
+    info.rc = rc
+    _check(rc, ctx, allow=(PKM_OK, PKM_NOT_CONVERGED) if allow_warning else (PKM_OK,))
+    return X, info
+
+
+def pkm_grad_pass(ctx, prob: Problem, N, AS, YZ):
+    g = np.zeros(prob.d + 2)
+    _check(load().pkm_grad_pass(ctx, prob.ref, int(N), _ptr(AS), _ptr(YZ),
+                                g.ctypes.data_as(C.POINTER(C.c_double))), ctx)
+    return g
+
+
+def pkm_lml_grad(ctx, prob: Problem, y, Z, pc=None, opts=None, sol=None):
+    N = Z.shape[1]
+    g = np.zeros(prob.d + 2)
+    info = SolveInfo(1 + N)
+    opts = opts or make_opts()
+    rc = load().pkm_lml_grad(ctx, prob.ref, pc, _ptr(y), int(N), _ptr(Z), C.byref(opts),
+                             g.ctypes.data_as(C.POINTER(C.c_double)), _ptr(sol),
+                             C.byref(info.struct))
+    info.rc = rc
+    _check(rc, ctx, allow=(PKM_OK, PKM_NOT_CONVERGED))
+    return g, info
+
+
+def pkm_timing_enable(ctx, on=True):
+    _check(load().pkm_timing_enable(ctx, 1 if on else 0), ctx)
+
+
+def pkm_mvm_stats(ctx, prec):
+    launches = C.c_int64()
+    ms, pairs, flops = C.c_double(), C.c_double(), C.c_double()
+    _check(load().pkm_mvm_stats(ctx, prec, C.byref(launches), C.byref(ms), C.byref(pairs),
+                                C.byref(flops)), ctx)
+    return {"launches": launches.value, "ms": ms.value, "pairs": pairs.value,
+            "flops": flops.value}
+
+
+def pkm_mvm_stats_reset(ctx):
+    _check(load().pkm_mvm_stats_reset(ctx), ctx)

@@ -1,0 +1,307 @@
+// C ABI of libpkm: argument validation, context and object lifetime, and the
+// translation of internal failures into status codes.  No exception crosses
+// this boundary.
+
+#include "pkm_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace pkm {
+void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const int32_t* idx,
+                   const double* Phi, double jitter, pkm_precond* pc);
+int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, const double* B,
+          double* X, const pkm_solve_opts* o, pkm_solve_info* info);
+void grad_pass(pkm_ctx* ctx, const pkm_problem* prob, int N, const double* AS,
+               const double* YZ, double* grad);
+}  // namespace pkm
+
+using namespace pkm;
+
+static thread_local std::string g_last_error = "no error";
+static constexpr size_t PKM_PINNED_BYTES = 1 << 16;
+
+template <class F>
+static int guarded(pkm_ctx* ctx, F&& f) {
+    try {
+        if (ctx) PKM_HIP(hipSetDevice(ctx->device));
+        return f();
+    } catch (const pkm::Error& e) {
+        g_last_error = e.what();
+        if (ctx) ctx->err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        if (ctx) ctx->err = g_last_error;
+        return PKM_ERR_OOM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        if (ctx) ctx->err = e.what();
+        return PKM_ERR_HIP;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        if (ctx) ctx->err = g_last_error;
+        return PKM_ERR_HIP;
+    }
+}
+
+static void require_dev(const void* p, const char* what) {
+    PKM_REQUIRE(p != nullptr, std::string(what) + " is NULL");
+    PKM_REQUIRE((reinterpret_cast<uintptr_t>(p) & 7) == 0, std::string(what) + " must be 8-byte aligned");
+}
+
+extern "C" {
+
+const char* pkm_version(void) { return "pkm 0.1 gfx950"; }
+
+const char* pkm_last_error(const pkm_ctx* ctx) {
+    if (ctx) return ctx->err.c_str();
+    return g_last_error.c_str();
+}
+
+int pkm_create(pkm_ctx** out, int device, void* stream) {
+    if (!out) {
+        g_last_error = "out is NULL";
+        return PKM_ERR_INVALID;
+    }
+    *out = nullptr;
+    pkm_ctx* ctx = nullptr;
+    int rc = guarded(nullptr, [&] {
+        int count = 0;
+        PKM_HIP(hipGetDeviceCount(&count));
+        PKM_REQUIRE(device >= 0 && device < count, "device index out of range");
+        PKM_HIP(hipSetDevice(device));
+        ctx = new pkm_ctx();
+        ctx->device = device;
+        ctx->stream = static_cast<hipStream_t>(stream);
+        PKM_HIP(hipEventCreate(&ctx->ev0));
+        PKM_HIP(hipEventCreate(&ctx->ev1));
+        PKM_HIP(hipHostMalloc(&ctx->pinned, PKM_PINNED_BYTES, hipHostMallocDefault));
+        return PKM_OK;
+    });
+    if (rc != PKM_OK) {
+        if (ctx) pkm_destroy(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return PKM_OK;
+}
+
+int pkm_destroy(pkm_ctx* ctx) {
+    if (!ctx) return PKM_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    ctx->prep.xs64.release();
+    ctx->prep.jside.release();
+    ctx->prep.iside.release();
+    for (DevBuf* b : {&ctx->v32, &ctx->y32, &ctx->v64pad, &ctx->y64pad, &ctx->red, &ctx->red2,
+                      &ctx->scal, &ctx->state, &ctx->grad, &ctx->ws_split, &ctx->ws_tmp})
+        b->release();
+    for (auto& b : ctx->pcg) b.release();
+    for (auto& b : ctx->ws_setup) b.release();
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+    return PKM_OK;
+}
+
+int pkm_kernel_mvm(pkm_ctx* ctx, const pkm_problem* prob, int32_t k, int32_t prec,
+                   const double* V, double* Y) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        validate_problem(prob);
+        PKM_REQUIRE(k >= 1 && k <= 4096, "k must be in [1, 4096]");
+        PKM_REQUIRE(prec == PKM_FP64 || prec == PKM_FP32, "unknown precision");
+        PKM_REQUIRE(prec == PKM_FP64 || prob->d <= 34, "FP32 product supports d <= 34");
+        require_dev(V, "V");
+        require_dev(Y, "Y");
+        PKM_REQUIRE(V != Y, "Y may not alias V");
+        prepare(ctx, prob, prec == PKM_FP64, prec == PKM_FP32);
+        mvm(ctx, prec, k, V, Y);
+        return PKM_OK;
+    });
+}
+
+int pkm_precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int32_t kind, int32_t m,
+                      const int32_t* idx, const double* Phi, double jitter, pkm_precond** out) {
+    if (!ctx) return PKM_ERR_INVALID;
+    if (out) *out = nullptr;
+    pkm_precond* pc = nullptr;
+    int rc = guarded(ctx, [&] {
+        PKM_REQUIRE(out != nullptr, "out is NULL");
+        validate_problem(prob);
+        PKM_REQUIRE(kind == PKM_PC_NYSTROM || kind == PKM_PC_FITC || kind == PKM_PC_LOWRANK,
+                    "unknown preconditioner kind");
+        PKM_REQUIRE(m >= 1 && m <= 4096 && m <= prob->n, "m must be in [1, min(n, 4096)]");
+        PKM_REQUIRE(std::isfinite(jitter) && jitter >= 0.0, "jitter must be >= 0");
+        if (kind == PKM_PC_LOWRANK) require_dev(Phi, "Phi");
+        else {
+            PKM_REQUIRE(idx != nullptr, "idx is NULL");
+            PKM_REQUIRE((reinterpret_cast<uintptr_t>(idx) & 3) == 0, "idx must be 4-byte aligned");
+        }
+        pc = new pkm_precond();
+        precond_setup(ctx, prob, kind, m, idx, Phi, jitter, pc);
+        return PKM_OK;
+    });
+    if (rc != PKM_OK) {
+        if (pc) pkm_precond_destroy(pc);
+        return rc;
+    }
+    *out = pc;
+    return PKM_OK;
+}
+
+int pkm_precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int32_t k, const double* R,
+                      double* Z) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        PKM_REQUIRE(pc != nullptr, "preconditioner is NULL");
+        PKM_REQUIRE(pc->device == ctx->device, "preconditioner belongs to another device");
+        PKM_REQUIRE(k >= 1 && k <= 4096, "k must be in [1, 4096]");
+        require_dev(R, "R");
+        require_dev(Z, "Z");
+        PKM_REQUIRE(R != Z, "Z may not alias R");
+        precond_apply(ctx, pc, k, R, Z);
+        return PKM_OK;
+    });
+}
+
+int pkm_precond_diag(pkm_ctx* ctx, const pkm_precond* pc, double* D_host) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        PKM_REQUIRE(pc != nullptr && D_host != nullptr, "NULL argument");
+        std::vector<double> dinv(pc->n);
+        PKM_HIP(hipMemcpyAsync(dinv.data(), pc->dinv.p, sizeof(double) * pc->n,
+                               hipMemcpyDeviceToHost, ctx->stream));
+        PKM_HIP(hipStreamSynchronize(ctx->stream));
+        for (int64_t i = 0; i < pc->n; ++i) D_host[i] = 1.0 / dinv[i];
+        return PKM_OK;
+    });
+}
+
+int pkm_precond_destroy(pkm_precond* pc) {
+    if (!pc) return PKM_OK;
+    (void)hipSetDevice(pc->device);
+    (void)hipDeviceSynchronize();
+    pc->psi.release();
+    pc->dinv.release();
+    delete pc;
+    return PKM_OK;
+}
+
+static void fill_opts(const pkm_solve_opts* in, pkm_solve_opts* o) {
+    *o = in ? *in : pkm_solve_opts{};
+    if (o->tol == 0.0) o->tol = 1e-6;
+    if (o->max_iter == 0) o->max_iter = 100000;
+    if (o->reliable_every == 0) o->reliable_every = 25;
+    if (o->check_every == 0) o->check_every = 1;
+    if (!in) o->prec = PKM_FP32;
+    PKM_REQUIRE(std::isfinite(o->tol) && o->tol > 0.0, "tol must be > 0");
+    PKM_REQUIRE(o->max_iter >= 1, "max_iter must be >= 1");
+    PKM_REQUIRE(o->prec == PKM_FP64 || o->prec == PKM_FP32, "unknown precision");
+    PKM_REQUIRE(o->reliable_every >= 1 && o->check_every >= 1, "periods must be >= 1");
+}
+
+int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int32_t k,
+              const double* B, double* X, const pkm_solve_opts* opts, pkm_solve_info* info) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        validate_problem(prob);
+        pkm_solve_opts o;
+        fill_opts(opts, &o);
+        PKM_REQUIRE(k >= 1 && k <= 256, "k must be in [1, 256]");
+        PKM_REQUIRE(o.prec == PKM_FP64 || prob->d <= 34, "FP32 product supports d <= 34");
+        require_dev(B, "B");
+        require_dev(X, "X");
+        PKM_REQUIRE(B != X, "X may not alias B");
+        if (pc) {
+            PKM_REQUIRE(pc->n == prob->n, "preconditioner was built for another n");
+            PKM_REQUIRE(pc->device == ctx->device, "preconditioner belongs to another device");
+        }
+        return solve(ctx, prob, pc, k, B, X, &o, info);
+    });
+}
+
+int pkm_grad_pass(pkm_ctx* ctx, const pkm_problem* prob, int32_t N, const double* AS,
+                  const double* YZ, double* grad_host) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        validate_problem(prob);
+        PKM_REQUIRE(prob->d <= 32, "gradient pass supports d <= 32");
+        PKM_REQUIRE(N >= 0 && N <= 4095, "N must be in [0, 4095]");
+        require_dev(AS, "AS");
+        require_dev(YZ, "YZ");
+        PKM_REQUIRE(grad_host != nullptr, "grad is NULL");
+        grad_pass(ctx, prob, N, AS, YZ, grad_host);
+        return PKM_OK;
+    });
+}
+
+int pkm_lml_grad(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, const double* y,
+                 int32_t N, const double* Z, const pkm_solve_opts* opts, double* grad_host,
+                 double* sol, pkm_solve_info* info) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        validate_problem(prob);
+        PKM_REQUIRE(prob->d <= 32, "gradient pass supports d <= 32");
+        PKM_REQUIRE(N >= 1 && N <= 255, "N must be in [1, 255]");
+        require_dev(y, "y");
+        require_dev(Z, "Z");
+        PKM_REQUIRE(grad_host != nullptr, "grad is NULL");
+        pkm_solve_opts o;
+        fill_opts(opts, &o);
+        const int64_t n = prob->n;
+        const int k = 1 + N;
+        // [y, Z] and [alpha, Z] blocks (row-major n x k), solutions in S
+        ctx->pcg[5].ensure(sizeof(double) * n * k);
+        ctx->pcg[6].ensure(sizeof(double) * n * k);
+        ctx->pcg[7].ensure(sizeof(double) * n * k);
+        double* Bk = ctx->pcg[5].as<double>();
+        double* S = ctx->pcg[6].as<double>();
+        double* AZ = ctx->pcg[7].as<double>();
+        hipStream_t s = ctx->stream;
+        PKM_HIP(hipMemcpy2DAsync(Bk, sizeof(double) * k, y, sizeof(double), sizeof(double), n,
+                                 hipMemcpyDeviceToDevice, s));
+        PKM_HIP(hipMemcpy2DAsync(Bk + 1, sizeof(double) * k, Z, sizeof(double) * N,
+                                 sizeof(double) * N, n, hipMemcpyDeviceToDevice, s));
+        int rc = solve(ctx, prob, pc, k, Bk, S, &o, info);
+        if (rc < 0) return rc;
+        PKM_HIP(hipMemcpyAsync(AZ, Bk, sizeof(double) * n * k, hipMemcpyDeviceToDevice, s));
+        PKM_HIP(hipMemcpy2DAsync(AZ, sizeof(double) * k, S, sizeof(double) * k, sizeof(double), n,
+                                 hipMemcpyDeviceToDevice, s));
+        grad_pass(ctx, prob, N, S, AZ, grad_host);
+        if (sol)
+            PKM_HIP(hipMemcpyAsync(sol, S, sizeof(double) * n * k, hipMemcpyDeviceToDevice, s));
+        PKM_HIP(hipStreamSynchronize(s));
+        return rc;
+    });
+}
+
+int pkm_timing_enable(pkm_ctx* ctx, int32_t on) {
+    if (!ctx) return PKM_ERR_INVALID;
+    ctx->timing = on != 0;
+    return PKM_OK;
+}
+
+int pkm_mvm_stats(pkm_ctx* ctx, int32_t prec, int64_t* launches, double* ms, double* pairs,
+                  double* flops) {
+    if (!ctx || (prec != PKM_FP64 && prec != PKM_FP32)) return PKM_ERR_INVALID;
+    const MvmStats& s = ctx->stats[prec];
+    if (launches) *launches = s.launches;
+    if (ms) *ms = s.ms;
+    if (pairs) *pairs = s.pairs;
+    if (flops) *flops = s.flops;
+    return PKM_OK;
+}
+
+int pkm_mvm_stats_reset(pkm_ctx* ctx) {
+    if (!ctx) return PKM_ERR_INVALID;
+    ctx->stats[0] = MvmStats{};
+    ctx->stats[1] = MvmStats{};
+    return PKM_OK;
+}
+
+}  // extern "C"

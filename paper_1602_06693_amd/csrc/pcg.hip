@@ -1,0 +1,401 @@
+// Preconditioned CG on a block of right-hand sides (Algorithm 1, textbook
+// reading: alpha = r^T z / p^T K_y p, r <- r - alpha K_y p,
+// beta = r'^T z' / r^T z, p <- z + beta p), every column an independent
+// recurrence sharing one kernel product per step.
+//
+// All vectors (x, r, z, p, K_y p) are FP64, row-major n x k, resident on the
+// device; per-column scalars live in a device array of ColState and are
+// computed by single-work-group kernels, so the host only polls a two-word
+// flag every few steps.  Dot products reduce in a fixed order (block
+// partials, then one pass), so results are deterministic.
+//
+// A column whose recursive residual meets the tolerance is parked (it stops
+// taking steps) until the next FP64 true-residual check, which runs as soon
+// as every live column is parked.  A parked column whose true residual
+// b - K_y x (x is always FP64) meets the tolerance is accepted; otherwise r
+// is replaced by that true residual and the column resumes.  With FP32
+// kernel products the recursive residual drifts from the true one, so the
+// same replacement also runs every reliable_every steps.
+
+#include "pkm_internal.h"
+
+#include <chrono>
+#include <cmath>
+
+namespace pkm {
+
+struct ColState {
+    double rz, alpha, beta, bnorm, rec, tru, rr;
+    int32_t active, status;   // active: not yet accepted / failed
+    int32_t parked, pad;      // parked: recursive residual met tol, awaiting check
+    int64_t iters;
+};
+
+struct Flags {
+    int32_t live;      // active columns
+    int32_t pending;   // active columns that are not parked
+    int32_t broke;     // columns that broke down
+    int32_t pad;
+};
+
+__device__ inline bool stepping(const ColState& s) { return s.active && !s.parked; }
+
+constexpr int NRED = 256;   // blocks of a dot-product reduction
+
+// Per-block partial sums of u o v over columns (k <= 256).  Thread t always
+// sees column t % k because the thread stride is a multiple of k.
+__global__ __launch_bounds__(256) void k_dot_part(const double* __restrict__ u,
+                                                  const double* __restrict__ v, int64_t n,
+                                                  int k, double* __restrict__ part) {
+    __shared__ double sh[256];
+    const int per = 256 / k;
+    const int T = per * k;
+    const int64_t tot = n * k;
+    const int64_t chunk = round_up(cdiv(tot, NRED), k);
+    const int64_t beg = blockIdx.x * chunk, end = min(tot, beg + chunk);
+    double acc = 0.0;
+    if (threadIdx.x < T)
+        for (int64_t e = beg + threadIdx.x; e < end; e += T) acc = fma(u[e], v[e], acc);
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double s = 0.0;
+        for (int q = 0; q < per; ++q) s += sh[threadIdx.x + q * k];
+        part[blockIdx.x * k + threadIdx.x] = s;
+    }
+}
+
+__device__ inline double sum_parts(const double* part, int k, int c) {
+    double s = 0.0;
+    for (int b = 0; b < NRED; ++b) s += part[b * k + c];
+    return s;
+}
+
+// initial state: bnorm, rz = r^T z
+__global__ void k_init_state(const double* __restrict__ pbb, const double* __restrict__ prz,
+                             int k, ColState* __restrict__ st) {
+    int c = threadIdx.x;
+    if (c >= k) return;
+    double bb = sum_parts(pbb, k, c);
+    ColState s{};
+    s.bnorm = sqrt(bb);
+    s.rz = sum_parts(prz, k, c);
+    s.active = bb > 0.0 ? 1 : 0;
+    s.parked = 0;
+    s.status = PKM_COL_CONVERGED;
+    s.iters = 0;
+    s.rec = bb > 0.0 ? 1.0 : 0.0;
+    s.tru = s.rec;
+    if (s.active && !(s.rz > 0.0)) {   // P not positive definite or NaN input
+        s.active = 0;
+        s.status = PKM_COL_BREAKDOWN;
+    }
+    st[c] = s;
+}
+
+__global__ void k_alpha(const double* __restrict__ ppap, int k, ColState* __restrict__ st) {
+    int c = threadIdx.x;
+    if (c >= k) return;
+    ColState s = st[c];
+    if (stepping(s)) {
+        double pap = sum_parts(ppap, k, c);
+        if (!(pap > 0.0) || !isfinite(pap)) {
+            s.active = 0;
+            s.status = PKM_COL_BREAKDOWN;
+            s.alpha = 0.0;
+        } else {
+            s.alpha = s.rz / pap;
+            s.iters += 1;
+        }
+    } else {
+        s.alpha = 0.0;
+    }
+    st[c] = s;
+}
+
+// x += alpha p; r -= alpha Ap
+__global__ void k_update_xr(int64_t n, int k, const ColState* __restrict__ st,
+                            const double* __restrict__ p, const double* __restrict__ Ap,
+                            double* __restrict__ x, double* __restrict__ r) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= n * k) return;
+    int c = int(e % k);
+    double a = st[c].alpha;
+    if (a != 0.0) {
+        x[e] = fma(a, p[e], x[e]);
+        r[e] = fma(-a, Ap[e], r[e]);
+    }
+}
+
+// recursive residual norms and flags
+__global__ void k_rr(const double* __restrict__ prr, int k, double tol, ColState* __restrict__ st,
+                     Flags* __restrict__ fl) {
+    __shared__ int live, pending, broke;
+    if (threadIdx.x == 0) live = pending = broke = 0;
+    __syncthreads();
+    int c = threadIdx.x;
+    if (c < k) {
+        ColState s = st[c];
+        double rr = sum_parts(prr, k, c);
+        s.rr = rr;
+        s.rec = s.bnorm > 0.0 ? sqrt(rr) / s.bnorm : 0.0;
+        if (s.active && !isfinite(rr)) {
+            s.active = 0;
+            s.status = PKM_COL_BREAKDOWN;
+        }
+        if (stepping(s) && s.rec <= tol) s.parked = 1;
+        if (s.active) {
+            atomicAdd(&live, 1);
+            if (!s.parked) atomicAdd(&pending, 1);
+        }
+        if (s.status == PKM_COL_BREAKDOWN) atomicAdd(&broke, 1);
+        st[c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        fl->live = live;
+        fl->pending = pending;
+        fl->broke = broke;
+    }
+}
+
+// r = b - Ax (true residual) for live columns
+__global__ void k_true_res(int64_t n, int k, const ColState* __restrict__ st,
+                           const double* __restrict__ b, const double* __restrict__ Ax,
+                           double* __restrict__ r) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= n * k) return;
+    int c = int(e % k);
+    if (st[c].active) r[e] = b[e] - Ax[e];
+}
+
+// true residual norms (k_dot_part over the new r), acceptance
+__global__ void k_true_final(const double* __restrict__ prr, int k, double tol,
+                             ColState* __restrict__ st, Flags* __restrict__ fl) {
+    __shared__ int live, broke;
+    if (threadIdx.x == 0) live = broke = 0;
+    __syncthreads();
+    int c = threadIdx.x;
+    if (c < k) {
+        ColState s = st[c];
+        if (s.active) {
+            double rr = sum_parts(prr, k, c);
+            s.rr = rr;
+            s.tru = s.bnorm > 0.0 ? sqrt(rr) / s.bnorm : 0.0;
+            s.rec = s.tru;
+            if (!isfinite(rr)) {
+                s.active = 0;
+                s.status = PKM_COL_BREAKDOWN;
+            } else if (s.tru <= tol) {
+                s.active = 0;
+                s.status = PKM_COL_CONVERGED;
+            }
+            s.parked = 0;
+        }
+        if (s.active) atomicAdd(&live, 1);
+        if (s.status == PKM_COL_BREAKDOWN) atomicAdd(&broke, 1);
+        st[c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        fl->live = live;
+        fl->pending = live;
+        fl->broke = broke;
+    }
+}
+
+// true residual of every column, for the report (no state change)
+__global__ void k_report_true(const double* __restrict__ prr, int k, ColState* __restrict__ st) {
+    int c = threadIdx.x;
+    if (c >= k) return;
+    double rr = sum_parts(prr, k, c);
+    st[c].tru = st[c].bnorm > 0.0 ? sqrt(rr) / st[c].bnorm : 0.0;
+}
+
+__global__ void k_beta(const double* __restrict__ prz, int k, ColState* __restrict__ st) {
+    int c = threadIdx.x;
+    if (c >= k) return;
+    ColState s = st[c];
+    if (stepping(s)) {
+        double rz = sum_parts(prz, k, c);
+        if (rz < 0.0 || !isfinite(rz)) {
+            s.active = 0;
+            s.status = PKM_COL_BREAKDOWN;
+            s.beta = 0.0;
+        } else {
+            s.beta = s.rz > 0.0 ? rz / s.rz : 0.0;
+            s.rz = rz;
+        }
+    } else {
+        s.beta = 0.0;
+    }
+    st[c] = s;
+}
+
+// p = z + beta p (live columns)
+__global__ void k_update_p(int64_t n, int k, const ColState* __restrict__ st,
+                           const double* __restrict__ z, double* __restrict__ p) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= n * k) return;
+    int c = int(e % k);
+    if (stepping(st[c])) p[e] = fma(st[c].beta, p[e], z[e]);
+}
+
+__global__ void k_mark_maxiter(int k, ColState* __restrict__ st) {
+    int c = threadIdx.x;
+    if (c < k && st[c].active) {
+        st[c].active = 0;
+        st[c].status = PKM_COL_MAX_ITER;
+    }
+}
+
+__global__ void k_sub(int64_t tot, const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ out) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e < tot) out[e] = a[e] - b[e];
+}
+
+static void dot_part(pkm_ctx* ctx, const double* u, const double* v, int64_t n, int k,
+                     double* part) {
+    k_dot_part<<<NRED, 256, 0, ctx->stream>>>(u, v, n, k, part);
+    PKM_CHECK_LAUNCH();
+}
+
+int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, const double* B,
+          double* X, const pkm_solve_opts* o, pkm_solve_info* info) {
+    const int64_t n = prob->n;
+    hipStream_t s = ctx->stream;
+    const int prec = o->prec;
+    prepare(ctx, prob, true, prec == PKM_FP32);
+    auto t_start = std::chrono::steady_clock::now();
+
+    const size_t vec = sizeof(double) * n * k;
+    for (int i = 0; i < 5; ++i) ctx->pcg[i].ensure(vec);
+    double* r = ctx->pcg[0].as<double>();
+    double* z = ctx->pcg[1].as<double>();
+    double* p = ctx->pcg[2].as<double>();
+    double* Ap = ctx->pcg[3].as<double>();
+    double* tmp = ctx->pcg[4].as<double>();
+    ctx->red.ensure(sizeof(double) * NRED * k * 2);
+    double* partA = ctx->red.as<double>();
+    double* partB = partA + NRED * k;
+    ctx->state.ensure(sizeof(ColState) * k + sizeof(Flags) + 64);
+    ColState* st = ctx->state.as<ColState>();
+    Flags* fl = reinterpret_cast<Flags*>(st + k);
+    Flags* hfl = static_cast<Flags*>(ctx->pinned);
+    const int64_t tot = n * k;
+    const unsigned gb = unsigned(cdiv(tot, 256));
+
+    auto precond = [&](const double* R, double* Zo) {
+        if (pc) precond_apply(ctx, pc, k, R, Zo);
+        else PKM_HIP(hipMemcpyAsync(Zo, R, vec, hipMemcpyDeviceToDevice, s));
+    };
+    auto poll = [&]() {
+        PKM_HIP(hipMemcpyAsync(hfl, fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
+        PKM_HIP(hipStreamSynchronize(s));
+        return *hfl;
+    };
+    int64_t true_count = 0;
+    auto true_residual = [&]() {   // r <- b - K_y x in FP64 for live columns
+        mvm(ctx, PKM_FP64, k, X, tmp);
+        k_true_res<<<gb, 256, 0, s>>>(n, k, st, B, tmp, r);
+        PKM_CHECK_LAUNCH();
+        dot_part(ctx, r, r, n, k, partA);
+        k_true_final<<<1, 256, 0, s>>>(partA, k, o->tol, st, fl);
+        PKM_CHECK_LAUNCH();
+        ++true_count;
+    };
+
+    // r0 = b - K_y x0, z0 = P^-1 r0, p0 = z0
+    if (o->use_x0) {
+        mvm(ctx, PKM_FP64, k, X, tmp);
+        k_sub<<<gb, 256, 0, s>>>(tot, B, tmp, r);
+        PKM_CHECK_LAUNCH();
+        ++true_count;
+    } else {
+        PKM_HIP(hipMemsetAsync(X, 0, vec, s));
+        PKM_HIP(hipMemcpyAsync(r, B, vec, hipMemcpyDeviceToDevice, s));
+    }
+    precond(r, z);
+    PKM_HIP(hipMemcpyAsync(p, z, vec, hipMemcpyDeviceToDevice, s));
+    dot_part(ctx, B, B, n, k, partA);
+    dot_part(ctx, r, z, n, k, partB);
+    k_init_state<<<1, 256, 0, s>>>(partA, partB, k, st);
+    PKM_CHECK_LAUNCH();
+    // x0 may already satisfy the tolerance
+    dot_part(ctx, r, r, n, k, partA);
+    k_rr<<<1, 256, 0, s>>>(partA, k, o->tol, st, fl);
+    PKM_CHECK_LAUNCH();
+    Flags f = poll();
+    if (f.live > 0 && f.pending == 0) {
+        true_residual();
+        f = poll();
+    }
+
+    int64_t it = 0;
+    const int check = o->check_every;
+    const int reliable = o->reliable_every;
+    while (f.live > 0 && it < o->max_iter) {
+        mvm(ctx, prec, k, p, Ap);
+        dot_part(ctx, p, Ap, n, k, partA);
+        k_alpha<<<1, 256, 0, s>>>(partA, k, st);
+        PKM_CHECK_LAUNCH();
+        k_update_xr<<<gb, 256, 0, s>>>(n, k, st, p, Ap, X, r);
+        PKM_CHECK_LAUNCH();
+        dot_part(ctx, r, r, n, k, partA);
+        k_rr<<<1, 256, 0, s>>>(partA, k, o->tol, st, fl);
+        PKM_CHECK_LAUNCH();
+        ++it;
+        bool do_true = prec == PKM_FP32 && reliable > 0 && it % reliable == 0;
+        if (!do_true && (it % check == 0 || it == o->max_iter)) {
+            f = poll();
+            if (f.live == 0) break;
+            if (f.pending == 0) do_true = true;
+        }
+        if (do_true) {
+            true_residual();
+            f = poll();
+            if (f.live == 0) break;
+        }
+        if (it == o->max_iter) break;
+        precond(r, z);
+        dot_part(ctx, r, z, n, k, partB);
+        k_beta<<<1, 256, 0, s>>>(partB, k, st);
+        PKM_CHECK_LAUNCH();
+        k_update_p<<<gb, 256, 0, s>>>(n, k, st, z, p);
+        PKM_CHECK_LAUNCH();
+    }
+    k_mark_maxiter<<<1, 256, 0, s>>>(k, st);
+    PKM_CHECK_LAUNCH();
+    // final FP64 true residual of every column for the report
+    mvm(ctx, PKM_FP64, k, X, tmp);
+    k_sub<<<gb, 256, 0, s>>>(tot, B, tmp, tmp);
+    PKM_CHECK_LAUNCH();
+    dot_part(ctx, tmp, tmp, n, k, partA);
+    k_report_true<<<1, 256, 0, s>>>(partA, k, st);
+    PKM_CHECK_LAUNCH();
+    std::vector<ColState> hs(k);
+    PKM_HIP(hipMemcpyAsync(hs.data(), st, sizeof(ColState) * k, hipMemcpyDeviceToHost, s));
+    PKM_HIP(hipStreamSynchronize(s));
+    auto t_end = std::chrono::steady_clock::now();
+
+    int code = PKM_OK;
+    for (int c = 0; c < k; ++c) {
+        if (hs[c].status == PKM_COL_BREAKDOWN) code = PKM_ERR_BREAKDOWN;
+        else if (hs[c].status == PKM_COL_MAX_ITER && code == PKM_OK) code = PKM_NOT_CONVERGED;
+    }
+    if (info) {
+        for (int c = 0; c < k; ++c) {
+            if (info->iters) info->iters[c] = hs[c].iters;
+            if (info->relres_true) info->relres_true[c] = hs[c].tru;
+            if (info->relres_rec) info->relres_rec[c] = hs[c].rec;
+            if (info->col_status) info->col_status[c] = hs[c].status;
+        }
+        info->total_iters = it;
+        info->true_residuals = true_count;
+        info->solve_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+    }
+    return code;
+}
+
+}  // namespace pkm

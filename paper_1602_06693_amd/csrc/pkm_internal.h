@@ -1,0 +1,164 @@
+// Internal declarations shared by the translation units of libpkm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pkm.h"
+
+namespace pkm {
+
+// Internal failures travel as exceptions and become status codes at the ABI.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(int code, const std::string& msg) { throw Error(code, msg); }
+
+#define PKM_HIP(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            ::pkm::fail(e_ == hipErrorOutOfMemory ? PKM_ERR_OOM : PKM_ERR_HIP,     \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+#define PKM_CHECK_LAUNCH() PKM_HIP(hipGetLastError())
+
+#define PKM_REQUIRE(cond, msg)                                                     \
+    do {                                                                           \
+        if (!(cond)) ::pkm::fail(PKM_ERR_INVALID, msg);                            \
+    } while (0)
+
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t want) {
+        if (want <= bytes) return;
+        if (p) {
+            // work queued earlier may still read the old allocation
+            PKM_HIP(hipDeviceSynchronize());
+            PKM_HIP(hipFree(p));
+        }
+        p = nullptr;
+        bytes = 0;
+        PKM_HIP(hipMalloc(&p, want));
+        bytes = want;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Accumulated timing of kernel-product launches, per arithmetic.
+struct MvmStats {
+    int64_t launches = 0;
+    double ms = 0.0, pairs = 0.0, flops = 0.0;
+};
+
+// Prepared inputs of one problem (input preparation, done once per theta).
+struct Prepared {
+    int64_t n = 0, n_pad = 0;
+    int d = 0;
+    // FP64: X scaled by 1/l_r (direct differences need no centring)
+    DevBuf xs64;            // n_pad x d
+    // FP32 MFMA operands of the augmented distance contraction.
+    int d4 = 0;             // augmented length d + 2 rounded up to 4
+    DevBuf jside;           // j-side operand tiles, MFMA lane order
+    DevBuf iside;           // i-side operand rows, n_pad x d4
+    double sigma2 = 1.0, lambda = 0.0;
+    std::vector<double> ls;
+    const double* X = nullptr;
+    bool valid64 = false, valid32 = false;
+};
+
+}  // namespace pkm
+
+struct pkm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool timing = false;
+    pkm::MvmStats stats[2];
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    pkm::Prepared prep;
+    // scratch (grow-only), by purpose
+    pkm::DevBuf v32, y32, v64pad, y64pad, red, red2, scal, state, pcg[8], grad;
+    pkm::DevBuf ws_split, ws_tmp, ws_setup[4];
+    void* pinned = nullptr;   // pinned host staging area (PKM_PINNED_BYTES)
+};
+
+struct pkm_precond {
+    int kind = 0;
+    int64_t n = 0;
+    int m = 0;
+    int device = 0;
+    pkm::DevBuf psi;    // n x m FP64: P^-1 = diag(dinv) - psi psi^T
+    pkm::DevBuf dinv;   // n FP64
+};
+
+namespace pkm {
+
+// ---- input preparation (prep.hip) ----
+void prepare(pkm_ctx* ctx, const pkm_problem* prob, bool need64, bool need32);
+void validate_problem(const pkm_problem* prob);
+
+// ---- kernel products (mvm.hip) ----
+// Y64 = (K + lambda I) V64 for row-major n x k FP64 blocks (device).
+// prec: PKM_FP64 or PKM_FP32.  Uses ctx->prep (must be prepared).
+void mvm(pkm_ctx* ctx, int prec, int k, const double* V, double* Y);
+// K V only (no lambda term) in FP64, writing into Y (n x k FP64).
+void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy);
+// FP32 product pipeline: pack V (n x k FP64, row-major) into MFMA tiles,
+// run the fused kernel, return FP32 partials pointer and layout.
+struct F32Out {
+    const float* y;   // jsplit x n_pad x kp32 FP32 partial sums of K V
+    int jsplit;
+    int64_t stride;   // elements between consecutive split planes
+    int kp;           // row stride in floats
+};
+F32Out mvm_k32(pkm_ctx* ctx, int k, const double* V, int ldv);
+
+// ---- setup BLAS (blas64.hip) ----
+// C[M x N] = alpha * op(A) op(B) + beta * C, FP64, row-major with leading
+// dimensions.  op = transpose when the flag is set.  M < 65535 * 64.
+void dgemm(pkm_ctx* ctx, bool ta, bool tb, int64_t M, int64_t N, int64_t K,
+           double alpha, const double* A, int64_t lda, const double* B,
+           int64_t ldb, double beta, double* C, int64_t ldc);
+// Same, any M (row-chunked).
+void dgemm_large(pkm_ctx* ctx, bool ta, bool tb, int64_t M, int64_t N, int64_t K,
+                 double alpha, const double* A, int64_t lda, const double* B,
+                 int64_t ldb, double beta, double* C, int64_t ldc);
+// In-place lower Cholesky of an m x m FP64 matrix (row-major, lda); the
+// upper triangle is zeroed.  winv (m x 64) receives the inverses of the
+// 64 x 64 diagonal blocks.  *dev_info (device) = first failing pivot + 1.
+void dpotrf_lower(pkm_ctx* ctx, int64_t m, double* A, int64_t lda, double* winv,
+                  int* dev_info);
+// B (n x m) <- B L^{-T}, L m x m lower (row-major), winv from dpotrf_lower.
+void dtrsm_right_lt(pkm_ctx* ctx, int64_t n, int64_t m, const double* L,
+                    int64_t ldl, const double* winv, double* B, int64_t ldb);
+
+// ---- kernel blocks for setup (prep.hip) ----
+// Out[p x q] = sigma2 exp(-1/2 |xa_i - xb_j|^2) for scaled FP64 rows.
+void rbf_cross64(hipStream_t s, const double* xa, const int32_t* ia, int64_t p,
+                 const double* xb, const int32_t* ib, int64_t q, int d,
+                 double sigma2, double* out, int64_t ldo);
+
+// ---- preconditioner apply (precond.hip) ----
+void precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int k, const double* R,
+                   double* Z);
+
+}  // namespace pkm

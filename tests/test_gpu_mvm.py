@@ -1,0 +1,88 @@
+"""Parity of the HIP kernel product (K + lambda I) V against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import GpuProblem, ctx, dev, host, rel_err  # noqa: F401
+from oracle import kernel as ok
+from paper_1602_06693_amd import binding as pk
+from pkm_inputs import make
+
+pytestmark = pytest.mark.gpu
+
+# FP64: direct differences and FP64 exp on both sides -> rounding-order level.
+TOL64 = 1e-13
+# FP32: each entry's base-2 exponent carries about 2^-24 (|a_i| + |b_j|) absolute
+# error from the FP32 contraction (|xh|^2 <= ~40 after centring), exp2 adds ~2
+# ulp, and the FP32 sum over n terms adds ~2^-24 sqrt(n) relative: < 1e-5 norm-wise.
+TOL32 = 1e-5
+
+
+@pytest.mark.parametrize("n,k", [(1000, 1), (1000, 3), (777, 17), (300, 33), (1, 2), (17, 5)])
+def test_fp64_product(ctx, n, k):
+    p = make("block_fp32", seed=11, n=n, n_probes=max(k - 1, 0))
+    g = GpuProblem(p)
+    V = p.B[:, :k]
+    want = ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, V)
+    got = host(pk.pkm_kernel_mvm(ctx, g.prob, dev(V), pk.PKM_FP64))
+    assert np.all(rel_err(got, want) < TOL64), rel_err(got, want)
+
+
+@pytest.mark.parametrize("n,k", [(1000, 1), (1000, 16), (777, 17), (600, 33), (513, 64),
+                                 (300, 65), (1, 1), (40, 2), (257, 7)])
+def test_fp32_product(ctx, n, k):
+    p = make("block_fp32", seed=12, n=n, n_probes=max(k - 1, 0))
+    g = GpuProblem(p)
+    V = p.B[:, :k]
+    want = ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, V)
+    got = host(pk.pkm_kernel_mvm(ctx, g.prob, dev(V), pk.PKM_FP32))
+    err = rel_err(got, want)
+    assert np.all(err < TOL32), err
+
+
+@pytest.mark.parametrize("d", [1, 4, 16, 32, 34])
+def test_fp32_product_dimensions(ctx, d):
+    rng = np.random.default_rng(d)
+    n, k = 700, 9
+    X = rng.random((n, d))
+    ls = np.exp(rng.uniform(np.log(0.2 * np.sqrt(d)), np.log(np.sqrt(d)), size=d))
+    V = rng.standard_normal((n, k))
+    Xd = dev(X)
+    prob = pk.Problem(Xd, ls, 1.3, 3e-3)
+    want = ok.kernel_mvm(X, 1.3, ls, 3e-3, V)
+    got = host(pk.pkm_kernel_mvm(ctx, prob, dev(V), pk.PKM_FP32))
+    assert np.all(rel_err(got, want) < TOL32)
+    got64 = host(pk.pkm_kernel_mvm(ctx, prob, dev(V), pk.PKM_FP64))
+    assert np.all(rel_err(got64, want) < TOL64)
+
+
+def test_fp32_product_full_size_sampled_rows(ctx):
+    """The 65,536-point block workload in the launch shape the solver uses;
+    64 sampled output rows recomputed by the oracle."""
+    p = make("block_fp32", seed=0)
+    g = GpuProblem(p)
+    got = host(pk.pkm_kernel_mvm(ctx, g.prob, g.B, pk.PKM_FP32))
+    rows = np.random.default_rng(5).choice(p.n, size=64, replace=False)
+    want = ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, p.B, rows=rows)
+    assert rel_err(got[rows], want, axis=None) < TOL32
+
+
+def test_product_is_deterministic(ctx):
+    p = make("block_fp32", seed=13, n=5000, n_probes=16)
+    g = GpuProblem(p)
+    a = host(pk.pkm_kernel_mvm(ctx, g.prob, g.B, pk.PKM_FP32))
+    b = host(pk.pkm_kernel_mvm(ctx, g.prob, g.B, pk.PKM_FP32))
+    assert np.array_equal(a, b)
+
+
+def test_invalid_arguments_rejected(ctx):
+    p = make("block_fp32", seed=14, n=100, n_probes=0)
+    g = GpuProblem(p)
+    bad = pk.Problem(g.X, p.lengthscales, p.sigma2, -1.0)
+    with pytest.raises(pk.PkmError) as e:
+        pk.pkm_kernel_mvm(ctx, bad, g.B, pk.PKM_FP32)
+    assert e.value.code == pk.PKM_ERR_INVALID
+    ls = p.lengthscales.copy()
+    ls[2] = 0.0
+    with pytest.raises(pk.PkmError) as e:
+        pk.pkm_kernel_mvm(ctx, pk.Problem(g.X, ls, p.sigma2, p.lam), g.B, pk.PKM_FP32)
+    assert e.value.code == pk.PKM_ERR_INVALID

@@ -1,0 +1,125 @@
+"""Parity of the HIP PCG solve against the oracle: solutions, certified FP64 true
+residuals and iteration counts."""
+import numpy as np
+import pytest
+
+from gpu_util import GpuProblem, ctx, dev, host, rel_err  # noqa: F401
+from oracle import direct as od
+from oracle import kernel as ok
+from oracle import precond as op
+from oracle.pcg import pcg
+from paper_1602_06693_amd import binding as pk
+from pkm_inputs import make
+
+pytestmark = pytest.mark.gpu
+JIT = 1e-8
+
+
+def true_relres(p, X):
+    r = p.B - ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, X)
+    return np.linalg.norm(r, axis=0) / np.linalg.norm(p.B, axis=0)
+
+
+def test_small_fp64_nystrom_full_size(ctx):
+    """The 2048-point FP64 workload end to end: Nystrom m = 64, tol 1e-8."""
+    p = make("small_fp64", seed=0, n_probes=0)
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, len(p.idx), idx=g.idx, jitter=JIT)
+    try:
+        X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc,
+                               opts=pk.make_opts(tol=1e-8, prec=pk.PKM_FP64), allow_warning=False)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    Xh = host(X)
+    assert np.all(true_relres(p, Xh) <= 1e-8)
+    assert np.all(info.relres_true <= 1e-8)
+    assert np.all(info.col_status == pk.PKM_COL_CONVERGED)
+    xs = od.solve(p.X, p.sigma2, p.lengthscales, p.lam, p.B)
+    # kappa(K_y) <= (lambda_max + lambda) / lambda ~ 2e5 here: 1e-8 residual -> <~1e-3 error
+    assert np.all(rel_err(Xh, xs) < 2e-3)
+    P = op.nystrom(p.X, p.sigma2, p.lengthscales, p.lam, p.idx, jitter=JIT)
+    mv = lambda V: ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, V)
+    ref = pcg(mv, p.B, precond=P, tol=1e-8, max_iter=100000)
+    # same recurrences in FP64: counts agree within a small band
+    assert np.all(info.iters <= 1.1 * ref.iters + 2) and np.all(info.iters >= ref.iters - 2)
+
+
+@pytest.mark.parametrize("kind", [None, pk.PKM_PC_NYSTROM, pk.PKM_PC_FITC])
+def test_fp32_products_reach_tolerance_with_reliable_updates(ctx, kind):
+    p = make("block_fp32", seed=1, n=3000, m=100, n_probes=4)
+    g = GpuProblem(p)
+    pc = None
+    if kind is not None:
+        pc = pk.pkm_precond_setup(ctx, g.prob, kind, len(p.idx), idx=g.idx, jitter=JIT)
+    try:
+        X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc,
+                               opts=pk.make_opts(tol=1e-6, prec=pk.PKM_FP32), allow_warning=False)
+    finally:
+        if pc is not None:
+            pk.pkm_precond_destroy(pc)
+    tr = true_relres(p, host(X))
+    assert np.all(tr <= 1e-6), tr
+    assert np.allclose(info.relres_true, tr, rtol=1e-6, atol=1e-12)
+    assert info.true_residuals >= 1
+
+
+def test_fp64_plain_cg_matches_oracle_iterations(ctx):
+    p = make("small_fp64", seed=2, n=1500, n_probes=3)
+    g = GpuProblem(p)
+    X, info = pk.pkm_solve(ctx, g.prob, g.B, opts=pk.make_opts(tol=1e-8, prec=pk.PKM_FP64))
+    mv = lambda V: ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, V)
+    ref = pcg(mv, p.B, tol=1e-8, max_iter=100000)
+    assert np.all(np.abs(info.iters - ref.iters) <= 0.1 * ref.iters + 2)
+    assert rel_err(host(X), ref.x, axis=None) < 1e-4
+
+
+def test_exact_preconditioner_one_step(ctx):
+    """Nystrom with every point inducing reproduces K, so one step suffices."""
+    rng = np.random.default_rng(5)
+    n, d = 96, 3
+    Xn = rng.random((n, d)) * 4.0
+    ls = np.array([0.3, 0.4, 0.5])
+    Xd = dev(Xn)
+    prob = pk.Problem(Xd, ls, 1.0, 1e-2)
+    B = dev(rng.standard_normal((n, 2)))
+    pc = pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_NYSTROM, n, idx=dev(np.arange(n, dtype=np.int32)))
+    try:
+        X, info = pk.pkm_solve(ctx, prob, B, pc=pc, opts=pk.make_opts(tol=1e-9, prec=pk.PKM_FP64))
+    finally:
+        pk.pkm_precond_destroy(pc)
+    assert np.all(info.iters == 1)
+
+
+def test_max_iter_warning_and_zero_column(ctx):
+    p = make("block_fp32", seed=3, n=500, n_probes=2)
+    g = GpuProblem(p)
+    B = p.B.copy()
+    B[:, 2] = 0.0
+    X, info = pk.pkm_solve(ctx, g.prob, dev(B), opts=pk.make_opts(tol=1e-10, max_iter=1,
+                                                                  prec=pk.PKM_FP64))
+    assert info.rc == pk.PKM_NOT_CONVERGED
+    assert list(info.col_status) == [pk.PKM_COL_MAX_ITER, pk.PKM_COL_MAX_ITER, pk.PKM_COL_CONVERGED]
+    assert np.all(host(X)[:, 2] == 0.0)
+    assert np.all(info.iters[:2] == 1)
+
+
+def test_warm_start_from_solution(ctx):
+    p = make("small_fp64", seed=4, n=700, n_probes=1)
+    g = GpuProblem(p)
+    xs = od.solve(p.X, p.sigma2, p.lengthscales, p.lam, p.B)
+    X0 = dev(xs.copy())
+    X, info = pk.pkm_solve(ctx, g.prob, g.B, X=X0, opts=pk.make_opts(tol=1e-8, prec=pk.PKM_FP64,
+                                                                     use_x0=True))
+    assert np.all(info.iters == 0)
+    assert np.all(info.col_status == pk.PKM_COL_CONVERGED)
+
+
+def test_nan_input_is_breakdown(ctx):
+    p = make("block_fp32", seed=6, n=300, n_probes=1)
+    g = GpuProblem(p)
+    B = p.B.copy()
+    B[5, 1] = np.nan
+    X, info = (None, None)
+    with pytest.raises(pk.PkmError) as e:
+        pk.pkm_solve(ctx, g.prob, dev(B), opts=pk.make_opts(tol=1e-8, prec=pk.PKM_FP64))
+    assert e.value.code == pk.PKM_ERR_BREAKDOWN
