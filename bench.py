@@ -79,6 +79,28 @@ def cpu_baseline(p, gpu_iters, budget_rows=1024):
             "sample": sample, "per_product_s": t_mvm, "setup_s": t_setup}
 
 
+def mvm_only(pk, ctx, prob, B, steps, p):
+    """Kernel products alone (for counter collection), then a calibration copy."""
+    import torch
+    Y = torch.empty_like(B)
+    pk.pkm_kernel_mvm(ctx, prob, B, pk.PKM_FP32, Y)
+    pk.pkm_mvm_stats_reset(ctx)
+    pk.pkm_timing_enable(ctx, True)
+    for _ in range(steps):
+        pk.pkm_kernel_mvm(ctx, prob, B, pk.PKM_FP32, Y)
+    torch.cuda.synchronize()
+    st = pk.pkm_mvm_stats(ctx, pk.PKM_FP32)
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    avg = st["ms"] / max(st["launches"], 1)
+    print(json.dumps({"mode": "mvm", "n": p.n, "d": p.d, "k": int(B.shape[1]),
+                      "launches": st["launches"], "avg_ms": avg,
+                      "tflops": st["flops"] / max(st["launches"], 1) / (avg * 1e-3) / 1e12,
+                      "copy_bytes": 2 * src.numel() * 8}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +109,9 @@ def main():
     ap.add_argument("--workload", default="block_fp32")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=("step", "mvm"), default="step",
+                    help="mvm: only --steps FP32 kernel products of the workload's size, "
+                         "then one 1 GiB device copy (counter calibration for profiles)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -109,6 +134,10 @@ def main():
     ctx = pk.pkm_create(0, pk.current_stream_handle())
     prob = pk.Problem(X, p.lengthscales, p.sigma2, p.lam)
     opts = pk.make_opts(tol=p.tol, prec=pk.PKM_FP32, reliable_every=25)
+    if a.mode == "mvm":
+        mvm_only(pk, ctx, prob, dev(p.B), a.steps, p)
+        pk.pkm_destroy(ctx)
+        return
 
     def step():
         pc = pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_NYSTROM, m, idx=idx, jitter=1e-8)

@@ -86,7 +86,10 @@ __global__ void k_init_state(const double* __restrict__ pbb, const double* __res
     s.iters = 0;
     s.rec = bb > 0.0 ? 1.0 : 0.0;
     s.tru = s.rec;
-    if (s.active && !(s.rz > 0.0)) {   // P not positive definite or NaN input
+    if (!isfinite(bb) || !isfinite(s.rz)) {   // NaN or Inf in b or x0
+        s.active = 0;
+        s.status = PKM_COL_BREAKDOWN;
+    } else if (s.active && !(s.rz > 0.0)) {   // P not positive definite
         s.active = 0;
         s.status = PKM_COL_BREAKDOWN;
     }

@@ -40,8 +40,9 @@ def test_small_fp64_nystrom_full_size(ctx):
     P = op.nystrom(p.X, p.sigma2, p.lengthscales, p.lam, p.idx, jitter=JIT)
     mv = lambda V: ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, V)
     ref = pcg(mv, p.B, precond=P, tol=1e-8, max_iter=100000)
-    # same recurrences in FP64: counts agree within a small band
-    assert np.all(info.iters <= 1.1 * ref.iters + 2) and np.all(info.iters >= ref.iters - 2)
+    # same recurrences in FP64, different rounding order: finite-precision CG
+    # counts drift apart slowly, so they agree within a 10% + 2 band
+    assert np.all(np.abs(info.iters - ref.iters) <= 0.1 * ref.iters + 2), (info.iters, ref.iters)
 
 
 @pytest.mark.parametrize("kind", [None, pk.PKM_PC_NYSTROM, pk.PKM_PC_FITC])
