@@ -4,15 +4,17 @@ matrices, plus kernel-product TFLOP/s, on one MI355X.
 One step is the whole hot path on one synthetic problem resident in HBM:
 Nystrom preconditioner setup (m inducing points), PCG on the right-hand-side
 block [y, Z] (Z: Rademacher probes) to a certified FP64 true relative
-residual of 1e-6 with FP32 MFMA kernel products and FP64 reliable updates,
-and the Hutchinson gradient pass of the log-marginal likelihood.
+residual of 1e-6 with mixed-precision (BF16 MFMA) kernel products and FP64
+residual replacement, and the Hutchinson gradient pass of the log-marginal
+likelihood.  The same step with plain FP32 MFMA products is timed alongside
+("plain") for the mixed-vs-plain comparison.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload block_fp32]
 
 Prints one JSON line (rank 0).  ``value`` is the median step time in seconds
-(lower is better).  The ``roofline`` object reports the FP32 kernel-product
-kernel (the dominant kernel) from HIP events around each of its launches
-during the timed steps; ``cpu_baseline`` times the FP64 CPU oracle on a
+(lower is better).  The ``roofline`` object reports the kernel product (the
+dominant kernel) from HIP events around each of its launches during the
+timed steps; ``cpu_baseline`` times the FP64 CPU oracle on a
 bounded sample of the same work.
 """
 from __future__ import annotations
@@ -33,14 +35,17 @@ if ROOT not in sys.path:
 METRIC = ("time to 1e-6 rel. residual PCG solve (mixed/learned vs plain); "
           "kernel-MVM TFLOP/s")
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0   # dense
+PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
-def _describe(p, m):
+def _describe(p, m, prec, reliable):
     return (f"{p.name}: n={p.n}, d={p.d}, X~U[0,1], ARD lengthscales LogU[0.1,1], "
             f"sigma2={p.sigma2}, lambda={p.lam}, k=1+{p.Z.shape[1]} (y + Rademacher probes), "
-            f"Nystrom m={m}, tol={p.tol}, FP32 MFMA products, FP64 vectors, "
-            f"FP64 true residual every 25 steps; step = setup + solve + gradient")
+            f"Nystrom m={m}, tol={p.tol} (certified FP64 true residual), {prec} kernel "
+            f"products, FP64 vectors, FP64 residual replacement every {reliable} steps; "
+            f"step = preconditioner setup + block PCG solve + gradient pass")
 
 
 def cpu_baseline(p, gpu_iters, budget_rows=1024):
@@ -79,26 +84,37 @@ def cpu_baseline(p, gpu_iters, budget_rows=1024):
             "sample": sample, "per_product_s": t_mvm, "setup_s": t_setup}
 
 
-def mvm_only(pk, ctx, prob, B, steps, p):
-    """Kernel products alone (for counter collection), then a calibration copy."""
+def mvm_only(pk, ctx, prob, p, steps, prec_names, ks):
+    """Kernel products alone (k-sweep per arithmetic), then a 1 GiB calibration copy."""
     import torch
-    Y = torch.empty_like(B)
-    pk.pkm_kernel_mvm(ctx, prob, B, pk.PKM_FP32, Y)
-    pk.pkm_mvm_stats_reset(ctx)
-    pk.pkm_timing_enable(ctx, True)
-    for _ in range(steps):
-        pk.pkm_kernel_mvm(ctx, prob, B, pk.PKM_FP32, Y)
-    torch.cuda.synchronize()
-    st = pk.pkm_mvm_stats(ctx, pk.PKM_FP32)
+    precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x1": pk.PKM_BF16X1,
+             "bf16x3": pk.PKM_BF16X3}
+    rng = np.random.default_rng(1)
+    for name in prec_names:
+        prec = precs[name]
+        for k in ks:
+            V = torch.from_numpy(rng.standard_normal((p.n, k))).to("cuda:0")
+            Y = torch.empty_like(V)
+            pk.pkm_kernel_mvm(ctx, prob, V, prec, Y)
+            pk.pkm_mvm_stats_reset(ctx)
+            pk.pkm_timing_enable(ctx, True)
+            for _ in range(steps):
+                pk.pkm_kernel_mvm(ctx, prob, V, prec, Y)
+            torch.cuda.synchronize()
+            pk.pkm_timing_enable(ctx, False)
+            st = pk.pkm_mvm_stats(ctx, prec)
+            avg = st["ms"] / max(st["launches"], 1)
+            print(json.dumps({"mode": "mvm", "prec": name, "n": p.n, "d": p.d, "k": k,
+                              "launches": st["launches"], "avg_ms": avg,
+                              "tflops": st["flops"] / max(st["ms"], 1e-9) * 1e-9,
+                              "frac_bf16_peak": st["flops"] / max(st["ms"], 1e-9) * 1e-9
+                              / PEAK_BF16_MFMA_TFLOPS}), flush=True)
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    avg = st["ms"] / max(st["launches"], 1)
-    print(json.dumps({"mode": "mvm", "n": p.n, "d": p.d, "k": int(B.shape[1]),
-                      "launches": st["launches"], "avg_ms": avg,
-                      "tflops": st["flops"] / max(st["launches"], 1) / (avg * 1e-3) / 1e12,
-                      "copy_bytes": 2 * src.numel() * 8}), flush=True)
+    print(json.dumps({"mode": "copy", "bytes_read": src.numel() * 8,
+                      "bytes_written": src.numel() * 8}), flush=True)
 
 
 def main():
@@ -109,6 +125,14 @@ def main():
     ap.add_argument("--workload", default="block_fp32")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--prec", default="bf16x3", choices=("fp32", "bf16x3", "bf16x1", "fp64"),
+                    help="arithmetic of the kernel product inside the loop (the mixed path)")
+    ap.add_argument("--plain", default="fp32", choices=("fp32", "none"),
+                    help="also time this product arithmetic for the mixed-vs-plain comparison")
+    ap.add_argument("--reliable", type=int, default=50)
+    ap.add_argument("--ks", default="", help="mvm mode: comma-separated column counts")
+    ap.add_argument("--mvm-precs", default="bf16x3",
+                    help="mvm mode: comma-separated arithmetics (fp64,fp32,bf16x1,bf16x3)")
     ap.add_argument("--mode", choices=("step", "mvm"), default="step",
                     help="mvm: only --steps FP32 kernel products of the workload's size, "
                          "then one 1 GiB device copy (counter calibration for profiles)")
@@ -133,51 +157,72 @@ def main():
     sol = torch.zeros((p.n, 1 + N), dtype=torch.float64, device="cuda:0")
     ctx = pk.pkm_create(0, pk.current_stream_handle())
     prob = pk.Problem(X, p.lengthscales, p.sigma2, p.lam)
-    opts = pk.make_opts(tol=p.tol, prec=pk.PKM_FP32, reliable_every=25)
     if a.mode == "mvm":
-        mvm_only(pk, ctx, prob, dev(p.B), a.steps, p)
+        ks = [int(v) for v in a.ks.split(",")] if a.ks else [1 + N]
+        mvm_only(pk, ctx, prob, p, a.steps, a.mvm_precs.split(","), ks)
         pk.pkm_destroy(ctx)
         return
 
-    def step():
-        pc = pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_NYSTROM, m, idx=idx, jitter=1e-8)
-        try:
-            g, info = pk.pkm_lml_grad(ctx, prob, y, Z, pc=pc, opts=opts, sol=sol)
-        finally:
-            pk.pkm_precond_destroy(pc)
-        return g, info
+    precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x1": pk.PKM_BF16X1,
+             "bf16x3": pk.PKM_BF16X3}
 
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    pk.pkm_mvm_stats_reset(ctx)
-    pk.pkm_timing_enable(ctx, True)
-    times, infos = [], []
-    torch.cuda.synchronize()
-    t_all = time.perf_counter()
-    for _ in range(a.steps):
-        t0 = time.perf_counter()
-        g, info = step()
+    def run_variant(prec, steps, warmup, label):
+        opts = pk.make_opts(tol=p.tol, prec=prec, reliable_every=a.reliable)
+
+        def step():
+            pc = pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_NYSTROM, m, idx=idx, jitter=1e-8)
+            try:
+                return pk.pkm_lml_grad(ctx, prob, y, Z, pc=pc, opts=opts, sol=sol)
+            finally:
+                pk.pkm_precond_destroy(pc)
+
+        for _ in range(warmup):
+            step()
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        infos.append(info)
-        print(f"step {len(times)}: {times[-1]:.3f} s, iters {info.total_iters}, "
-              f"true residuals {info.true_residuals}, max relres {info.relres_true.max():.2e}",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t_all = time.perf_counter() - t_all
-    pk.pkm_timing_enable(ctx, False)
-    st = pk.pkm_mvm_stats(ctx, pk.PKM_FP32)
-    st64 = pk.pkm_mvm_stats(ctx, pk.PKM_FP64)
+        pk.pkm_mvm_stats_reset(ctx)
+        pk.pkm_timing_enable(ctx, True)
+        times, infos = [], []
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            g, info = step()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            infos.append(info)
+            print(f"[{label}] step {len(times)}: {times[-1]:.3f} s, iters {info.total_iters}, "
+                  f"true residuals {info.true_residuals}, max relres "
+                  f"{info.relres_true.max():.2e}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t_all = time.perf_counter() - t_all
+        pk.pkm_timing_enable(ctx, False)
+        info = infos[-1]
+        assert np.all(info.col_status == pk.PKM_COL_CONVERGED), info.col_status
+        assert np.all(info.relres_true <= p.tol)
+        st = pk.pkm_mvm_stats(ctx, prec)
+        st64 = pk.pkm_mvm_stats(ctx, pk.PKM_FP64)
+        avg_ms = st["ms"] / max(st["launches"], 1)
+        return {"times": times, "t_all": t_all, "info": info, "mvm_ms": avg_ms,
+                "flops_per_launch": st["flops"] / max(st["launches"], 1),
+                "tflops": st["flops"] / max(st["launches"], 1) / (avg_ms * 1e-3) / 1e12,
+                "fp64_ms": st64["ms"] / max(st64["launches"], 1),
+                "fp64_launches": st64["launches"] // max(steps, 1)}
+
+    mixed = run_variant(precs[a.prec], a.steps, a.warmup, a.prec)
+    plain = None
+    if a.plain != "none" and a.plain != a.prec:
+        plain = run_variant(precs[a.plain], a.steps, a.warmup, a.plain)
     pk.pkm_destroy(ctx)
 
-    info = infos[-1]
-    assert np.all(info.col_status == pk.PKM_COL_CONVERGED), info.col_status
-    assert np.all(info.relres_true <= p.tol)
-    avg_ms = st["ms"] / max(st["launches"], 1)
-    flops_per_launch = st["flops"] / max(st["launches"], 1)
-    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-    value = statistics.median(times)
+    info = mixed["info"]
+    value = statistics.median(mixed["times"])
+    bf16 = a.prec.startswith("bf16")
+    peak = PEAK_BF16_MFMA_TFLOPS if bf16 else (PEAK_FP64_TFLOPS if a.prec == "fp64"
+                                                 else PEAK_FP32_MFMA_TFLOPS)
+    kname = {"fp32": "k_mvm_f32 (FP32 MFMA distance + exp2 + FP32 MFMA K V)",
+             "bf16x3": "k_mvm_bf16<NP=3> (BF16x6-split distance + exp2 + BF16x3 K V, FP32 acc)",
+             "bf16x1": "k_mvm_bf16<NP=1> (BF16x6-split distance + exp2 + BF16 K V, FP32 acc)",
+             "fp64": "k_mvm_f64 (FP64 VALU)"}[a.prec]
     out = {
         "metric": METRIC,
         "value": value,
@@ -185,27 +230,32 @@ def main():
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": 1e3 * t_all / a.steps,
+        "ms_per_step": 1e3 * mixed["t_all"] / a.steps,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if bf16 else ("f64" if a.prec == "fp64" else "f32"),
         "data": "synthetic",
-        "config": {"workload": _describe(p, m), "n": p.n, "d": p.d, "k": 1 + N, "m": m,
-                   "preconditioner": "nystrom", "parallelism": "single GPU"},
+        "config": {"workload": _describe(p, m, a.prec, a.reliable), "n": p.n, "d": p.d,
+                   "k": 1 + N, "m": m, "preconditioner": "nystrom", "product": a.prec,
+                   "parallelism": "single GPU"},
         "iters": int(info.total_iters),
         "true_residual_products": int(info.true_residuals),
         "max_true_relres": float(info.relres_true.max()),
-        "mvm_tflops": achieved,
-        "mvm_ms": avg_ms,
-        "fp64_true_residual_ms": st64["ms"] / max(st64["launches"], 1),
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-                     "traffic": None,
-                     "kernel": "k_mvm_f32 (fused FP32 MFMA distance + exp2 + K V)",
-                     "flops_per_launch": flops_per_launch,
+        "mvm_tflops": mixed["tflops"],
+        "mvm_ms": mixed["mvm_ms"],
+        "fp64_true_residual_ms": mixed["fp64_ms"],
+        "roofline": {"bound": "mfma", "achieved": mixed["tflops"], "peak": peak,
+                     "unit": "TFLOP/s", "frac": mixed["tflops"] / peak, "traffic": None,
+                     "kernel": kname, "flops_per_launch": mixed["flops_per_launch"],
                      "flop_count": "n^2 (2 d + 2 k) per product"},
     }
+    if plain is not None:
+        out["plain"] = {"product": a.plain, "value": statistics.median(plain["times"]),
+                        "iters": int(plain["info"].total_iters),
+                        "true_residual_products": int(plain["info"].true_residuals),
+                        "mvm_ms": plain["mvm_ms"], "mvm_tflops": plain["tflops"]}
+        out["speedup_vs_plain"] = out["plain"]["value"] / value
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, int(info.total_iters))
     print(json.dumps(out), flush=True)

@@ -55,6 +55,11 @@ extern "C" {
 /* ---- arithmetic of the kernel product ---------------------------------- */
 #define PKM_FP64   0   /* FP64 distances, exp and accumulation             */
 #define PKM_FP32   1   /* FP32 MFMA distances and K x V, FP32 accumulation  */
+#define PKM_BF16X1 2   /* BF16 MFMA: distances from exact 3-part BF16 splits
+                          (FP32-class exponent), K and V rounded to BF16
+                          once, FP32 accumulation                          */
+#define PKM_BF16X3 3   /* as PKM_BF16X1 with K and V split in two BF16 parts:
+                          K_h V_h + K_h V_l + K_l V_h                      */
 
 /* ---- preconditioner kinds ---------------------------------------------- */
 #define PKM_PC_NONE     0
@@ -88,9 +93,10 @@ typedef struct {
     double  tol;             /* relative residual |b - K_y x|_2 / |b|_2 per
                                 column; default 1e-6                         */
     int64_t max_iter;        /* default 100000 (the paper's cap, Section 4)  */
-    int32_t prec;            /* PKM_FP64 or PKM_FP32 for the product inside
-                                the loop; default PKM_FP32                  */
-    int32_t reliable_every;  /* FP64 true-residual replacement period (FP32
+    int32_t prec;            /* PKM_FP64, PKM_FP32, PKM_BF16X1 or PKM_BF16X3
+                                for the product inside the loop; default
+                                PKM_FP32                                    */
+    int32_t reliable_every;  /* FP64 true-residual replacement period (non-FP64
                                 products only); default 25                  */
     int32_t check_every;     /* host convergence poll period; default 1     */
     int32_t use_x0;          /* nonzero: X holds x0 on entry; else x0 = 0    */
@@ -122,7 +128,8 @@ const char* pkm_version(void);
 
 /* ---- kernel product (Section 2.1: the O(n^2) operation of every CG step) --
  * Y = (K + lambda I) V for V, Y device n x k FP64 (k >= 1).  prec selects
- * the arithmetic of the K V part (the lambda V term is always FP64).
+ * the arithmetic of the K V part (the lambda V term is always FP64): any
+ * PKM_FP64 .. PKM_BF16X3; FP32 needs d <= 34, BF16 d <= 36.
  * Y may not alias V.                                                         */
 int pkm_kernel_mvm(pkm_ctx* ctx, const pkm_problem* prob, int32_t k,
                    int32_t prec, const double* V, double* Y);
@@ -151,8 +158,8 @@ int pkm_precond_destroy(pkm_precond* pc);
  * FP64.  A column whose recursive residual meets tol stops stepping until
  * an FP64 true residual b - K_y x certifies it (that check runs once every
  * live column has stopped); if it fails, r is replaced by the true residual
- * and the column resumes.  With PKM_FP32 products the same replacement also
- * runs every reliable_every steps.  A column converges when its FP64 true
+ * and the column resumes.  With FP32 or BF16 products the same replacement
+ * also runs every reliable_every steps.  A column converges when its FP64 true
  * relative residual is <= tol.  Returns PKM_NOT_CONVERGED if a column reached max_iter and
  * PKM_ERR_BREAKDOWN if one broke down; X holds the last iterate either way. */
 int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,

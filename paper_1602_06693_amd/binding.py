@@ -25,6 +25,8 @@ PKM_ERR_UNSUPPORTED = -5
 
 PKM_FP64 = 0
 PKM_FP32 = 1
+PKM_BF16X1 = 2
+PKM_BF16X3 = 3
 
 PKM_PC_NONE = 0
 PKM_PC_NYSTROM = 1

@@ -26,7 +26,9 @@ template <class F>
 static int guarded(pkm_ctx* ctx, F&& f) {
     try {
         if (ctx) PKM_HIP(hipSetDevice(ctx->device));
-        return f();
+        int rc = f();
+        if (rc != PKM_OK && ctx) g_last_error = ctx->err;
+        return rc;
     } catch (const pkm::Error& e) {
         g_last_error = e.what();
         if (ctx) ctx->err = e.what();
@@ -44,6 +46,12 @@ static int guarded(pkm_ctx* ctx, F&& f) {
         if (ctx) ctx->err = g_last_error;
         return PKM_ERR_HIP;
     }
+}
+
+static void check_prec(int prec, int d) {
+    PKM_REQUIRE(prec >= PKM_FP64 && prec <= PKM_BF16X3, "unknown precision");
+    PKM_REQUIRE(prec != PKM_FP32 || d <= 34, "FP32 product supports d <= 34");
+    PKM_REQUIRE(prec < PKM_BF16X1 || d <= 36, "BF16 product supports d <= 36");
 }
 
 static void require_dev(const void* p, const char* what) {
@@ -96,7 +104,9 @@ int pkm_destroy(pkm_ctx* ctx) {
     ctx->prep.xs64.release();
     ctx->prep.jside.release();
     ctx->prep.iside.release();
-    for (DevBuf* b : {&ctx->v32, &ctx->y32, &ctx->v64pad, &ctx->y64pad, &ctx->red, &ctx->red2,
+    ctx->prep.jsb.release();
+    ctx->prep.isb.release();
+    for (DevBuf* b : {&ctx->vbf, &ctx->v32, &ctx->y32, &ctx->v64pad, &ctx->y64pad, &ctx->red, &ctx->red2,
                       &ctx->scal, &ctx->state, &ctx->grad, &ctx->ws_split, &ctx->ws_tmp})
         b->release();
     for (auto& b : ctx->pcg) b.release();
@@ -114,12 +124,11 @@ int pkm_kernel_mvm(pkm_ctx* ctx, const pkm_problem* prob, int32_t k, int32_t pre
     return guarded(ctx, [&] {
         validate_problem(prob);
         PKM_REQUIRE(k >= 1 && k <= 4096, "k must be in [1, 4096]");
-        PKM_REQUIRE(prec == PKM_FP64 || prec == PKM_FP32, "unknown precision");
-        PKM_REQUIRE(prec == PKM_FP64 || prob->d <= 34, "FP32 product supports d <= 34");
+        check_prec(prec, prob->d);
         require_dev(V, "V");
         require_dev(Y, "Y");
         PKM_REQUIRE(V != Y, "Y may not alias V");
-        prepare(ctx, prob, prec == PKM_FP64, prec == PKM_FP32);
+        prepare(ctx, prob, prec == PKM_FP64, prec != PKM_FP64);
         mvm(ctx, prec, k, V, Y);
         return PKM_OK;
     });
@@ -201,7 +210,7 @@ static void fill_opts(const pkm_solve_opts* in, pkm_solve_opts* o) {
     if (!in) o->prec = PKM_FP32;
     PKM_REQUIRE(std::isfinite(o->tol) && o->tol > 0.0, "tol must be > 0");
     PKM_REQUIRE(o->max_iter >= 1, "max_iter must be >= 1");
-    PKM_REQUIRE(o->prec == PKM_FP64 || o->prec == PKM_FP32, "unknown precision");
+    PKM_REQUIRE(o->prec >= PKM_FP64 && o->prec <= PKM_BF16X3, "unknown precision");
     PKM_REQUIRE(o->reliable_every >= 1 && o->check_every >= 1, "periods must be >= 1");
 }
 
@@ -213,7 +222,7 @@ int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int3
         pkm_solve_opts o;
         fill_opts(opts, &o);
         PKM_REQUIRE(k >= 1 && k <= 256, "k must be in [1, 256]");
-        PKM_REQUIRE(o.prec == PKM_FP64 || prob->d <= 34, "FP32 product supports d <= 34");
+        check_prec(o.prec, prob->d);
         require_dev(B, "B");
         require_dev(X, "X");
         PKM_REQUIRE(B != X, "X may not alias B");
@@ -288,7 +297,7 @@ int pkm_timing_enable(pkm_ctx* ctx, int32_t on) {
 
 int pkm_mvm_stats(pkm_ctx* ctx, int32_t prec, int64_t* launches, double* ms, double* pairs,
                   double* flops) {
-    if (!ctx || (prec != PKM_FP64 && prec != PKM_FP32)) return PKM_ERR_INVALID;
+    if (!ctx || prec < PKM_FP64 || prec > PKM_BF16X3) return PKM_ERR_INVALID;
     const MvmStats& s = ctx->stats[prec];
     if (launches) *launches = s.launches;
     if (ms) *ms = s.ms;
@@ -299,8 +308,7 @@ int pkm_mvm_stats(pkm_ctx* ctx, int32_t prec, int64_t* launches, double* ms, dou
 
 int pkm_mvm_stats_reset(pkm_ctx* ctx) {
     if (!ctx) return PKM_ERR_INVALID;
-    ctx->stats[0] = MvmStats{};
-    ctx->stats[1] = MvmStats{};
+    for (auto& s : ctx->stats) s = MvmStats{};
     return PKM_OK;
 }
 

@@ -415,10 +415,12 @@ void mvm(pkm_ctx* ctx, int prec, int k, const double* V, double* Y) {
         PKM_CHECK_LAUNCH();
         return;
     }
-    PKM_REQUIRE(prec == PKM_FP32, "unknown precision");
+    PKM_REQUIRE(prec == PKM_FP32 || prec == PKM_BF16X1 || prec == PKM_BF16X3,
+                "unknown precision");
     for (int c0 = 0; c0 < k; c0 += 65) {
         int kc = std::min(65, k - c0);
-        F32Out o = mvm_k32(ctx, kc, V + c0, k);
+        F32Out o = prec == PKM_FP32 ? mvm_k32(ctx, kc, V + c0, k)
+                                    : mvm_kbf16(ctx, prec, kc, V + c0, k);
         k_finish32<<<cdiv(n * kc, 256), 256, 0, s>>>(o.y, o.jsplit, o.stride, o.kp, n, kc, V + c0, k,
                                                       P.lambda, Y + c0, k);
         PKM_CHECK_LAUNCH();

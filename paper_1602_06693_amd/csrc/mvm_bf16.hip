@@ -1,0 +1,359 @@
+// Mixed-precision kernel product K V on BF16 matrix cores (FP32 accumulation).
+//
+// Distances: the augmented contraction a_i . b_j (see prep.hip) carried out
+// with every FP32 operand split exactly into three BF16 parts,
+// v = v_h + v_m + v_l.  Per input dimension six part products are kept,
+//     h.h + h.m + m.h + h.l + l.h + m.m,
+// each exact in FP32; the dropped m.l + l.m + l.l terms are below 2^-24 of
+// the product.  The exponent therefore keeps FP32-class accuracy while the
+// contraction runs on 16x16x32 BF16 MFMA: (6 d + 6) slots per entry instead of
+// the FP32 path's d + 2 slots at one eighth of the rate.  Slots:
+//     6 per dimension r:  (2 xh_ir part) x (xh_jr part) as listed above
+//     3:                  (c_i part) x 1        c_i = log2 sigma2 - |xh_i|^2
+//     3:                  1 x (c_j part)        c_j = -|xh_j|^2
+//
+// K V: K = exp2(S) in FP32 registers, rounded to BF16 (K_h) -- one product
+// K_h V_h (split 1) -- or split once more, K_l = bf16(K - K_h), for three
+// products K_h V_h + K_h V_l + K_l V_h (split 3, relative error ~2^-17).
+// The column count is padded to a multiple of 16; the vector ALUs, which
+// bound this kernel (exp2 and the splits), carry no column-dependent work.
+//
+// Lane layout: the transposed exponent tile leaves lane l holding K[i][j]
+// for i = l % 16 and j = 4 (l / 16) + r of two 16-row j-tiles; those eight
+// values are the A operand of the 16x16x32 K V MFMA, so V is packed with the
+// matching permutation of its 32 rows:
+//     element q of lane l in chunk T  <->  j = 32 T + 16 (q / 4) + 4 (l / 16) + q % 4.
+
+#include "pkm_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace pkm {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void split3(float v, __bf16& h, __bf16& m, __bf16& l) {
+    h = (__bf16)v;
+    float r1 = v - (float)h;
+    m = (__bf16)r1;
+    float r2 = r1 - (float)m;
+    l = (__bf16)r2;
+}
+
+// One thread per point: writes its 32 S6 slots on both sides.
+__global__ void k_aug_bf16(const double* __restrict__ X, int64_t n, int64_t n_pad, int d,
+                           int S6, const double* __restrict__ inv_l,
+                           const double* __restrict__ mean, double log2s2,
+                           __bf16* __restrict__ jsb, __bf16* __restrict__ isb) {
+    int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= n_pad) return;
+    const double cs = sqrt(0.5 * 1.4426950408889634);
+    const int64_t t = i >> 4;
+    const int rr = int(i & 15);
+    auto addr = [&](int sl) {
+        int s = sl >> 5, g = (sl & 31) >> 3, q = sl & 7;
+        return ((t * S6 + s) * 64 + rr + 16 * g) * 8 + q;
+    };
+    const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
+    const int nslot = 32 * S6;
+    for (int sl = 0; sl < nslot; ++sl) {
+        jsb[addr(sl)] = zero;
+        isb[addr(sl)] = zero;
+    }
+    double nrm = 0.0;
+    float ci, cj;
+    if (i < n) {
+        for (int r = 0; r < d; ++r) {
+            float xh = float((X[i * d + r] - mean[r]) * inv_l[r] * cs);
+            nrm += double(xh) * double(xh);
+            __bf16 ah, am, al, bh, bm, bl;
+            split3(2.0f * xh, ah, am, al);
+            split3(xh, bh, bm, bl);
+            const __bf16 ia[6] = {ah, ah, am, ah, al, am};
+            const __bf16 jb[6] = {bh, bm, bh, bl, bh, bm};
+            for (int q = 0; q < 6; ++q) {
+                isb[addr(6 * r + q)] = ia[q];
+                jsb[addr(6 * r + q)] = jb[q];
+            }
+        }
+        ci = float(log2s2 - nrm);
+        cj = float(-nrm);
+    } else {
+        ci = float(log2s2);
+        cj = -1.0e30f;
+    }
+    __bf16 h, m, l;
+    split3(ci, h, m, l);
+    const __bf16 cp[3] = {h, m, l};
+    for (int q = 0; q < 3; ++q) {
+        isb[addr(6 * d + q)] = cp[q];
+        jsb[addr(6 * d + q)] = one;
+    }
+    split3(cj, h, m, l);
+    const __bf16 dp[3] = {h, m, l};
+    for (int q = 0; q < 3; ++q) {
+        isb[addr(6 * d + 3 + q)] = one;
+        jsb[addr(6 * d + 3 + q)] = dp[q];
+    }
+}
+
+// Pack V (n x k FP64) for split NP: parts h (and l when NP == 3) in the
+// permuted 32-row chunk order, plus the FP32 remainder columns.
+//   vb[((T KT + qt) NPV + part) 64 + lane][q]
+//   yr[((T KR + e) 4 + g) 8 + q]
+__global__ void k_pack_v_bf16(const double* __restrict__ V, int64_t ldv, int64_t n, int k,
+                              int nchunk, int KT, int KR, int NPV, __bf16* __restrict__ vb,
+                              float* __restrict__ yr) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int64_t per_chunk_v = int64_t(KT) * 64 * 8;   // one part
+    const int64_t per_chunk_y = int64_t(KR) * 32;
+    const int64_t tot = int64_t(nchunk) * (per_chunk_v + per_chunk_y);
+    if (e >= tot) return;
+    int64_t T = e / (per_chunk_v + per_chunk_y);
+    int64_t w = e - T * (per_chunk_v + per_chunk_y);
+    if (w < per_chunk_v) {
+        int qt = int(w / 512);
+        int rem = int(w % 512);
+        int lane = rem >> 3, q = rem & 7;
+        int g = lane >> 4;
+        int64_t j = 32 * T + 16 * (q >> 2) + 4 * g + (q & 3);
+        int col = 16 * qt + (lane & 15);
+        float v = (j < n && col < k) ? float(V[j * ldv + col]) : 0.0f;
+        __bf16 h = (__bf16)v;
+        int64_t base = ((T * KT + qt) * NPV) * 512 + lane * 8 + q;
+        vb[base] = h;
+        if (NPV == 2) vb[base + 512] = (__bf16)(v - (float)h);
+    } else {
+        int64_t w2 = w - per_chunk_v;
+        int ee = int(w2 / 32);
+        int rem = int(w2 % 32);
+        int g = rem >> 3, q = rem & 7;
+        int64_t j = 32 * T + 16 * (q >> 2) + 4 * g + (q & 3);
+        int col = 16 * KT + ee;
+        yr[((T * KR + ee) * 4 + g) * 8 + q] = (j < n && col < k) ? float(V[j * ldv + col]) : 0.0f;
+    }
+}
+
+// Two floats -> one dword of two BF16 (round to nearest even).
+__device__ inline uint32_t pack_bf16x2(float a, float b) {
+    f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
+// K (8 floats) -> K_h (and K_l = bf16(K - K_h) when NP == 3) as MFMA operands.
+// The FP32 value of each rounded half is read back from the packed dword
+// with one shift or mask instead of a second conversion.
+template <int NP>
+__device__ inline void split_k(const float (&kf)[8], bf16x8& kh, bf16x8& kl) {
+    u32x4 h, l;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const uint32_t w = pack_bf16x2(kf[2 * p], kf[2 * p + 1]);
+        h[p] = w;
+        if (NP == 3) {
+            const float a = __builtin_bit_cast(float, w << 16);
+            const float b = __builtin_bit_cast(float, w & 0xffff0000u);
+            l[p] = pack_bf16x2(kf[2 * p] - a, kf[2 * p + 1] - b);
+        }
+    }
+    kh = __builtin_bit_cast(bf16x8, h);
+    if (NP == 3) kl = __builtin_bit_cast(bf16x8, l);
+}
+
+// Work-group: 4 waves x U i-tiles of 16 rows; loops over 32-row j-chunks of
+// its j-split.  All k columns (padded to 16 KT) run on the matrix cores.
+template <int S6, int KT, int U, int NP>
+__global__ __launch_bounds__(256) void k_mvm_bf16(
+    const bf16x8* __restrict__ jsb, const bf16x8* __restrict__ isb,
+    const bf16x8* __restrict__ vb, float* __restrict__ yout, int nchunk, int nrb, int jsplit,
+    int chunks_per_split, int64_t split_stride) {
+    constexpr int KP = 16 * KT;
+    constexpr int NPV = NP == 1 ? 1 : 2;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, slot = b >> 3;
+    const int group = 8 / jsplit;
+    const int split = xcd % jsplit;
+    const int rb = slot * group + xcd / jsplit;
+    if (rb >= nrb) return;
+    const int itile0 = (rb * 4 + wave) * U;
+    const int g = lane >> 4;
+
+    bf16x8 bi[U][S6];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int s = 0; s < S6; ++s) bi[u][s] = isb[(int64_t(itile0 + u) * S6 + s) * 64 + lane];
+
+    f32x4 acc[U][KT];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < KT; ++q) acc[u][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int T0 = split * chunks_per_split;
+    const int T1 = min(nchunk, T0 + chunks_per_split);
+    const bf16x8* pa = jsb + int64_t(2 * T0) * S6 * 64 + lane;
+    const bf16x8* pv = vb + int64_t(T0) * KT * NPV * 64 + lane;
+    for (int T = T0; T < T1; ++T, pa += 2 * S6 * 64, pv += KT * NPV * 64) {
+        bf16x8 a0[S6], a1[S6];
+#pragma unroll
+        for (int s = 0; s < S6; ++s) {
+            a0[s] = pa[s * 64];
+            a1[s] = pa[(S6 + s) * 64];
+        }
+        bf16x8 vv[KT][NPV];
+#pragma unroll
+        for (int qt = 0; qt < KT; ++qt)
+#pragma unroll
+            for (int pp = 0; pp < NPV; ++pp) vv[qt][pp] = pv[(qt * NPV + pp) * 64];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < S6; ++s) {
+                s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[s], bi[u][s], s0, 0, 0, 0);
+                s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[s], bi[u][s], s1, 0, 0, 0);
+            }
+            float kf[8];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                kf[r] = __builtin_amdgcn_exp2f(s0[r]);
+                kf[4 + r] = __builtin_amdgcn_exp2f(s1[r]);
+            }
+            bf16x8 kh, kl;
+            split_k<NP>(kf, kh, kl);
+#pragma unroll
+            for (int qt = 0; qt < KT; ++qt) {
+                acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vv[qt][0], acc[u][qt], 0, 0, 0);
+                if (NP == 3) {
+                    acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vv[qt][NPV - 1], acc[u][qt], 0, 0, 0);
+                    acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl, vv[qt][0], acc[u][qt], 0, 0, 0);
+                }
+            }
+        }
+    }
+
+    float* yo = yout + int64_t(split) * split_stride;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t row0 = int64_t(itile0 + u) * 16;
+#pragma unroll
+        for (int qt = 0; qt < KT; ++qt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                yo[(row0 + 4 * g + r) * KP + 16 * qt + (lane & 15)] = acc[u][qt][r];
+    }
+}
+
+void prepare_bf16(pkm_ctx* ctx) {
+    Prepared& P = ctx->prep;
+    if (P.validb) return;
+    PKM_REQUIRE(P.valid32, "internal: FP32 preparation must precede BF16 preparation");
+    P.s6 = int(cdiv(6 * P.d + 6, 32));
+    const int64_t ntiles = P.n_pad / 16;
+    P.jsb.ensure(sizeof(__bf16) * ntiles * P.s6 * 64 * 8);
+    P.isb.ensure(sizeof(__bf16) * ntiles * P.s6 * 64 * 8);
+    const double* inv_l = ctx->scal.as<double>();
+    const double* mean = inv_l + 64;
+    k_aug_bf16<<<cdiv(P.n_pad, 128), 128, 0, ctx->stream>>>(
+        P.X, P.n, P.n_pad, P.d, P.s6, inv_l, mean, std::log2(P.sigma2), P.jsb.as<__bf16>(),
+        P.isb.as<__bf16>());
+    PKM_CHECK_LAUNCH();
+    P.validb = true;
+}
+
+template <int S6, int NP>
+static void launch_bf16_s(int KT, dim3 grid, hipStream_t s, const bf16x8* js, const bf16x8* is,
+                          const bf16x8* vb, float* y, int nchunk, int nrb, int jsplit, int cps,
+                          int64_t stride) {
+#define PKM_B_CASE(kt)                                                                         \
+    if (KT == kt) {                                                                            \
+        k_mvm_bf16<S6, kt, 4, NP><<<grid, 256, 0, s>>>(js, is, vb, y, nchunk, nrb, jsplit, cps, \
+                                                        stride);                               \
+        return;                                                                                \
+    }
+    PKM_B_CASE(1) PKM_B_CASE(2) PKM_B_CASE(3) PKM_B_CASE(4) PKM_B_CASE(5)
+#undef PKM_B_CASE
+    fail(PKM_ERR_UNSUPPORTED, "BF16 product: unsupported column count");
+}
+
+template <int NP>
+static void launch_bf16(int S6, int KT, dim3 grid, hipStream_t s, const bf16x8* js,
+                        const bf16x8* is, const bf16x8* vb, float* y, int nchunk, int nrb,
+                        int jsplit, int cps, int64_t stride) {
+    switch (S6) {
+        case 1: launch_bf16_s<1, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
+        case 2: launch_bf16_s<2, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
+        case 3: launch_bf16_s<3, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
+        case 4: launch_bf16_s<4, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
+        case 5: launch_bf16_s<5, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
+        case 6: launch_bf16_s<6, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
+        case 7: launch_bf16_s<7, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
+        default: fail(PKM_ERR_UNSUPPORTED, "BF16 product: d must be <= 36");
+    }
+}
+
+F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
+    Prepared& P = ctx->prep;
+    prepare_bf16(ctx);
+    PKM_REQUIRE(k >= 1 && k <= 80, "BF16 product supports 1 <= k <= 80 columns per call");
+    const int NP = prec == PKM_BF16X3 ? 3 : 1;
+    const int NPV = NP == 1 ? 1 : 2;
+    const int KT = int(cdiv(k, 16));   // every column on the matrix cores
+    const int KR = 0;
+    const int KP = 16 * KT;
+    const int nchunk = int(P.n_pad / 32);
+    hipStream_t s = ctx->stream;
+    const int64_t vb_elems = int64_t(nchunk) * KT * NPV * 512;
+    const int64_t yr_elems = int64_t(nchunk) * KR * 32;
+    ctx->vbf.ensure(sizeof(__bf16) * std::max<int64_t>(vb_elems, 8) +
+                    sizeof(float) * std::max<int64_t>(yr_elems, 4) + 256);
+    __bf16* vb = ctx->vbf.as<__bf16>();
+    float* yrp = reinterpret_cast<float*>(
+        reinterpret_cast<char*>(vb) + round_up(sizeof(__bf16) * std::max<int64_t>(vb_elems, 8), 256));
+    const int64_t tot = int64_t(nchunk) * (int64_t(KT) * 512 + int64_t(KR) * 32);
+    k_pack_v_bf16<<<cdiv(tot, 256), 256, 0, s>>>(V, ldv, P.n, k, nchunk, KT, KR, NPV, vb, yrp);
+    PKM_CHECK_LAUNCH();
+
+    constexpr int U = 4;
+    const int64_t nrb = cdiv(P.n_pad, 64 * U);
+    int jsplit = 1;
+    while (jsplit < 8 && nrb * jsplit < 2048 && nchunk / (jsplit * 2) >= 8) jsplit <<= 1;
+    const int cps = int(cdiv(nchunk, jsplit));
+    const int group = 8 / jsplit;
+    const int64_t nrb_pad = round_up(nrb, group);
+    dim3 grid((unsigned)(nrb_pad * jsplit));
+    const int64_t stride = P.n_pad * KP;
+    ctx->y32.ensure(sizeof(float) * stride * jsplit);
+    float* y = ctx->y32.as<float>();
+
+    if (ctx->timing) PKM_HIP(hipEventRecord(ctx->ev0, s));
+    const bf16x8* js = P.jsb.as<bf16x8>();
+    const bf16x8* is = P.isb.as<bf16x8>();
+    const bf16x8* vbv = reinterpret_cast<const bf16x8*>(vb);
+    if (NP == 1) launch_bf16<1>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride);
+    else launch_bf16<3>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride);
+    PKM_CHECK_LAUNCH();
+    if (ctx->timing) {
+        PKM_HIP(hipEventRecord(ctx->ev1, s));
+        PKM_HIP(hipEventSynchronize(ctx->ev1));
+        float ms = 0.f;
+        PKM_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        MvmStats& st = ctx->stats[prec];
+        st.launches += 1;
+        st.ms += ms;
+        const double pairs = double(P.n) * double(P.n);
+        st.pairs += pairs;
+        st.flops += pairs * (2.0 * P.d + 2.0 * k);
+    }
+    return F32Out{y, jsplit, stride, KP};
+}
+
+}  // namespace pkm

@@ -269,7 +269,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     const int64_t n = prob->n;
     hipStream_t s = ctx->stream;
     const int prec = o->prec;
-    prepare(ctx, prob, true, prec == PKM_FP32);
+    prepare(ctx, prob, true, prec != PKM_FP64);
     auto t_start = std::chrono::steady_clock::now();
 
     const size_t vec = sizeof(double) * n * k;
@@ -349,7 +349,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         k_rr<<<1, 256, 0, s>>>(partA, k, o->tol, st, fl);
         PKM_CHECK_LAUNCH();
         ++it;
-        bool do_true = prec == PKM_FP32 && reliable > 0 && it % reliable == 0;
+        bool do_true = prec != PKM_FP64 && reliable > 0 && it % reliable == 0;
         if (!do_true && (it % check == 0 || it == o->max_iter)) {
             f = poll();
             if (f.live == 0) break;
@@ -383,10 +383,23 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     auto t_end = std::chrono::steady_clock::now();
 
     int code = PKM_OK;
+    int nbreak = 0, nmax = 0, first_break = -1;
     for (int c = 0; c < k; ++c) {
-        if (hs[c].status == PKM_COL_BREAKDOWN) code = PKM_ERR_BREAKDOWN;
-        else if (hs[c].status == PKM_COL_MAX_ITER && code == PKM_OK) code = PKM_NOT_CONVERGED;
+        if (hs[c].status == PKM_COL_BREAKDOWN) {
+            code = PKM_ERR_BREAKDOWN;
+            if (nbreak++ == 0) first_break = c;
+        } else if (hs[c].status == PKM_COL_MAX_ITER) {
+            ++nmax;
+            if (code == PKM_OK) code = PKM_NOT_CONVERGED;
+        }
     }
+    if (nbreak > 0)
+        ctx->err = std::to_string(nbreak) + " column(s) broke down (first: column " +
+                   std::to_string(first_break) + "): p^T K_y p <= 0, r^T z < 0 or a non-finite "
+                   "value; with BF16 products this means the rounded K + lambda I is not "
+                   "positive definite (use a more accurate product)";
+    else if (nmax > 0)
+        ctx->err = std::to_string(nmax) + " column(s) reached max_iter";
     if (info) {
         for (int c = 0; c < k; ++c) {
             if (info->iters) info->iters[c] = hs[c].iters;

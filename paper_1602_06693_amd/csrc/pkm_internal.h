@@ -79,6 +79,10 @@ struct Prepared {
     int d4 = 0;             // augmented length d + 2 rounded up to 4
     DevBuf jside;           // j-side operand tiles, MFMA lane order
     DevBuf iside;           // i-side operand rows, n_pad x d4
+    // BF16 split operands of the same contraction (mvm_bf16.hip)
+    int s6 = 0;             // 16x16x32 MFMAs per tile: ceil((6 d + 6) / 32)
+    DevBuf jsb, isb;
+    bool validb = false;
     double sigma2 = 1.0, lambda = 0.0;
     std::vector<double> ls;
     const double* X = nullptr;
@@ -92,11 +96,11 @@ struct pkm_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     bool timing = false;
-    pkm::MvmStats stats[2];
+    pkm::MvmStats stats[4];
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     pkm::Prepared prep;
     // scratch (grow-only), by purpose
-    pkm::DevBuf v32, y32, v64pad, y64pad, red, red2, scal, state, pcg[8], grad;
+    pkm::DevBuf vbf, v32, y32, v64pad, y64pad, red, red2, scal, state, pcg[8], grad;
     pkm::DevBuf ws_split, ws_tmp, ws_setup[4];
     void* pinned = nullptr;   // pinned host staging area (PKM_PINNED_BYTES)
 };
@@ -118,7 +122,7 @@ void validate_problem(const pkm_problem* prob);
 
 // ---- kernel products (mvm.hip) ----
 // Y64 = (K + lambda I) V64 for row-major n x k FP64 blocks (device).
-// prec: PKM_FP64 or PKM_FP32.  Uses ctx->prep (must be prepared).
+// prec: PKM_FP64 .. PKM_BF16X3.  Uses ctx->prep (must be prepared).
 void mvm(pkm_ctx* ctx, int prec, int k, const double* V, double* Y);
 // K V only (no lambda term) in FP64, writing into Y (n x k FP64).
 void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy);
@@ -131,6 +135,9 @@ struct F32Out {
     int kp;           // row stride in floats
 };
 F32Out mvm_k32(pkm_ctx* ctx, int k, const double* V, int ldv);
+// BF16 products (prec PKM_BF16X1 / PKM_BF16X3), same partial-sum layout.
+F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv);
+void prepare_bf16(pkm_ctx* ctx);
 
 // ---- setup BLAS (blas64.hip) ----
 // C[M x N] = alpha * op(A) op(B) + beta * C, FP64, row-major with leading

@@ -16,6 +16,7 @@
 
 #include "pkm_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace pkm {
@@ -153,18 +154,155 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const
     PKM_HIP(hipStreamSynchronize(s));
 }
 
-void precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int k, const double* R, double* Z) {
+// ---------------------------------------------------------------------------
+// Apply: Z = D^-1 R - Psi (Psi^T R).  Both phases stream Psi from HBM once.
+// ---------------------------------------------------------------------------
+constexpr int AT = 64;   // Psi columns per work-group (phase 1), rows (phase 2)
+
+// Phase 1: part[chunk][j][c] = sum_{i in chunk} Psi[i][j] R[i][c].
+// Work-group: 64 Psi columns x one row chunk; wave w takes rows i = w mod 4,
+// lane l owns Psi column j0 + l and all KC right-hand-side columns.
+template <int KC>
+__global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, int m,
+                                                const double* __restrict__ R, int k, int c0,
+                                                int64_t n, int64_t rows_per_chunk,
+                                                double* __restrict__ part) {
+    __shared__ double sr[AT][KC];
+    __shared__ double red[4][AT];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = blockIdx.x * AT + lane;
+    const int64_t i0 = int64_t(blockIdx.y) * rows_per_chunk;
+    const int64_t i1 = min(n, i0 + rows_per_chunk);
+    double acc[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+    for (int64_t ib = i0; ib < i1; ib += AT) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < AT * KC; e += 256) {
+            int rr = e / KC, c = e % KC;
+            int64_t i = ib + rr;
+            sr[rr][c] = (i < i1 && c0 + c < k) ? R[i * k + c0 + c] : 0.0;
+        }
+        __syncthreads();
+        const int rn = int(min<int64_t>(AT, i1 - ib));
+        for (int rr = w; rr < rn; rr += 4) {
+            const double v = j < m ? psi[(ib + rr) * m + j] : 0.0;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) acc[c] = fma(v, sr[rr][c], acc[c]);
+        }
+    }
+    // cross-wave sum, one right-hand-side column at a time
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+        __syncthreads();
+        red[w][lane] = acc[c];
+        __syncthreads();
+        if (w == 0 && j < m && c0 + c < k)
+            part[(int64_t(blockIdx.y) * m + j) * k + c0 + c] =
+                red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    }
+}
+
+// T[j][c] = sum over chunks of part, written zero-padded as an m_pad x ldt
+// block (m_pad = m rounded up to 16, ldt = 16 KT) for the phase-2 MFMA.
+__global__ void k_sum_chunks(const double* __restrict__ part, int nchunk, int m, int k, int c0,
+                             int kc, int m_pad, int ldt, double* __restrict__ T) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= int64_t(m_pad) * ldt) return;
+    const int j = int(e / ldt), c = int(e % ldt);
+    double s = 0.0;
+    if (j < m && c < kc && c0 + c < k)
+        for (int q = 0; q < nchunk; ++q) s += part[(int64_t(q) * m + j) * k + c0 + c];
+    T[e] = s;
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Phase 2: Z = D^-1 R - Psi T for columns [c0, c0 + 16 KT).  Each wave owns
+// 16 rows; lane l reads Psi[row0 + l % 16][m0 + 4 (l / 16) + q], q = 0..3,
+// so four lanes cover a 128-byte line of a row, and feeds 16x16x4 FP64 MFMAs
+// whose reduction index q pairs with the matching rows of T.
+template <int KT>
+__global__ __launch_bounds__(256) void k_apply_z(const double* __restrict__ psi, int m,
+                                                 const double* __restrict__ T, int ldt,
+                                                 const double* __restrict__ dinv,
+                                                 const double* __restrict__ R, int k, int c0,
+                                                 int64_t n, double* __restrict__ Z) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, rr = lane & 15;
+    const int64_t row0 = (int64_t(blockIdx.x) * 4 + w) * 16;
+    if (row0 >= n) return;
+    const int64_t row = row0 + rr;
+    const bool rv = row < n;
+    const double* prow = psi + (rv ? row : 0) * m;
+    f64x4 acc[KT];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) acc[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int m0 = 0; m0 < m; m0 += 16) {
+        double a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int mm = m0 + 4 * g + q;
+            a[q] = (rv && mm < m) ? prow[mm] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double* trow = T + int64_t(m0 + 4 * g + q) * ldt + rr;
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+                acc[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], trow[16 * kt], acc[kt], 0, 0, 0);
+        }
+    }
+    // FP64 16x16x4 results: lane l holds rows l / 16 + 4 r of column l % 16
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = row0 + g + 4 * r;
+            const int c = c0 + 16 * kt + rr;
+            if (i < n && c < k) Z[i * k + c] = dinv[i] * R[i * k + c] - acc[kt][r];
+        }
+}
+
+template <int KC>
+static void apply_chunk(pkm_ctx* ctx, const pkm_precond* pc, int k, int c0, const double* R,
+                        double* Z) {
     hipStream_t s = ctx->stream;
     const int64_t n = pc->n;
     const int m = pc->m;
-    // T = Psi^T R  (m x k)
-    ctx->red2.ensure(sizeof(double) * int64_t(m) * k);
-    double* T = ctx->red2.as<double>();
-    dgemm(ctx, true, false, m, k, n, 1.0, pc->psi.as<double>(), m, R, k, 0.0, T, k);
-    // Z = D^-1 R - Psi T
-    k_diag_apply<<<cdiv(n * k, 256), 256, 0, s>>>(n, k, pc->dinv.as<double>(), R, Z);
+    const int mt = int(cdiv(m, AT));
+    const int kc = std::min(KC, k - c0);
+    constexpr int KT = (KC + 15) / 16;
+    const int ldt = 16 * KT;
+    const int m_pad = int(round_up(m, 16));
+    // row chunks: a few work-groups per CU in phase 1
+    int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(cdiv(n, AT), 1024 / mt));
+    nchunk = std::min<int64_t>(nchunk, 64);
+    int64_t rpc = round_up(cdiv(n, nchunk), AT);
+    nchunk = cdiv(n, rpc);
+    ctx->red2.ensure(sizeof(double) * (nchunk * int64_t(m) * k + int64_t(m_pad) * ldt));
+    double* part = ctx->red2.as<double>();
+    double* T = part + nchunk * int64_t(m) * k;
+    k_psit_r<KC><<<dim3((unsigned)mt, (unsigned)nchunk), 256, 0, s>>>(
+        pc->psi.as<double>(), m, R, k, c0, n, rpc, part);
     PKM_CHECK_LAUNCH();
-    dgemm_large(ctx, false, false, n, k, m, -1.0, pc->psi.as<double>(), m, T, k, 1.0, Z, k);
+    k_sum_chunks<<<cdiv(int64_t(m_pad) * ldt, 256), 256, 0, s>>>(part, int(nchunk), m, k, c0, kc,
+                                                                 m_pad, ldt, T);
+    PKM_CHECK_LAUNCH();
+    k_apply_z<KT><<<(unsigned)cdiv(n, 64), 256, 0, s>>>(pc->psi.as<double>(), m, T, ldt,
+                                                        pc->dinv.as<double>(), R, k, c0, n, Z);
+    PKM_CHECK_LAUNCH();
+}
+
+void precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int k, const double* R, double* Z) {
+    for (int c0 = 0; c0 < k;) {
+        int rem = k - c0;
+        if (rem > 17) { apply_chunk<33>(ctx, pc, k, c0, R, Z); c0 += 33; }
+        else if (rem > 9) { apply_chunk<17>(ctx, pc, k, c0, R, Z); c0 += 17; }
+        else if (rem > 4) { apply_chunk<9>(ctx, pc, k, c0, R, Z); c0 += 9; }
+        else if (rem > 1) { apply_chunk<4>(ctx, pc, k, c0, R, Z); c0 += 4; }
+        else { apply_chunk<1>(ctx, pc, k, c0, R, Z); c0 += 1; }
+    }
 }
 
 }  // namespace pkm

@@ -86,3 +86,56 @@ def test_invalid_arguments_rejected(ctx):
     with pytest.raises(pk.PkmError) as e:
         pk.pkm_kernel_mvm(ctx, pk.Problem(g.X, ls, p.sigma2, p.lam), g.B, pk.PKM_FP32)
     assert e.value.code == pk.PKM_ERR_INVALID
+
+
+# BF16 products.  Exponents keep FP32-class accuracy (exact 3-part splits);
+# K and V are rounded to BF16: relative 2^-9 per entry (split 1), or carried
+# as two parts with ~2^-17 relative error (split 3).  Norm-wise bounds with
+# margin for the random-sign probe columns: 1e-2 and 1e-4.
+@pytest.mark.parametrize("prec,tol", [(pk.PKM_BF16X1, 1e-2), (pk.PKM_BF16X3, 1e-4)])
+@pytest.mark.parametrize("n,k", [(1000, 1), (777, 17), (600, 33), (513, 64), (300, 65), (1, 1),
+                                 (40, 2), (257, 7)])
+def test_bf16_product(ctx, prec, tol, n, k):
+    p = make("block_fp32", seed=15, n=n, n_probes=max(k - 1, 0))
+    g = GpuProblem(p)
+    V = p.B[:, :k]
+    want = ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, V)
+    got = host(pk.pkm_kernel_mvm(ctx, g.prob, dev(V), prec))
+    err = rel_err(got, want)
+    assert np.all(err < tol), err
+
+
+@pytest.mark.parametrize("d", [1, 4, 16, 32, 36])
+def test_bf16x3_product_dimensions(ctx, d):
+    rng = np.random.default_rng(100 + d)
+    n, k = 700, 9
+    X = rng.random((n, d))
+    ls = np.exp(rng.uniform(np.log(0.2 * np.sqrt(d)), np.log(np.sqrt(d)), size=d))
+    V = rng.standard_normal((n, k))
+    prob = pk.Problem(dev(X), ls, 0.7, 1e-3)
+    want = ok.kernel_mvm(X, 0.7, ls, 1e-3, V)
+    got = host(pk.pkm_kernel_mvm(ctx, prob, dev(V), pk.PKM_BF16X3))
+    assert np.all(rel_err(got, want) < 1e-4)
+
+
+def test_bf16_exponent_matches_fp32_path(ctx):
+    """With V = e_j the product returns a kernel column; BF16X3 and FP32 share
+    the exponent's accuracy, so the column entries agree to ~2^-16 relative."""
+    p = make("block_fp32", seed=16, n=640, n_probes=0)
+    g = GpuProblem(p)
+    V = np.zeros((p.n, 2))
+    V[17, 0] = 1.0
+    V[600, 1] = 1.0
+    a = host(pk.pkm_kernel_mvm(ctx, g.prob, dev(V), pk.PKM_BF16X3))
+    want = ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, V)
+    big = np.abs(want) > 1e-3
+    assert np.max(np.abs(a - want)[big] / np.abs(want)[big]) < 2e-5
+
+
+def test_bf16_full_size_sampled_rows(ctx):
+    p = make("block_fp32", seed=0)
+    g = GpuProblem(p)
+    got = host(pk.pkm_kernel_mvm(ctx, g.prob, g.B, pk.PKM_BF16X3))
+    rows = np.random.default_rng(6).choice(p.n, size=64, replace=False)
+    want = ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, p.B, rows=rows)
+    assert rel_err(got[rows], want, axis=None) < 1e-4

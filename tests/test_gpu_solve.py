@@ -124,3 +124,23 @@ def test_nan_input_is_breakdown(ctx):
     with pytest.raises(pk.PkmError) as e:
         pk.pkm_solve(ctx, g.prob, dev(B), opts=pk.make_opts(tol=1e-8, prec=pk.PKM_FP64))
     assert e.value.code == pk.PKM_ERR_BREAKDOWN
+
+
+@pytest.mark.parametrize("prec,lam", [(pk.PKM_BF16X3, None), (pk.PKM_BF16X1, 0.1)])
+def test_bf16_products_reach_tolerance_with_reliable_updates(ctx, prec, lam):
+    """Mixed precision inside the loop, FP64 x and FP64 true residuals: the
+    returned solution meets 1e-6 in FP64 against the exact K.  Split-1 BF16
+    perturbs K by ~2^-9 relative, which stays below lambda only for larger
+    noise; it is gated at lambda = 0.1 here."""
+    p = make("block_fp32", seed=8, n=3000, m=100, n_probes=4)
+    if lam is not None:
+        p.lam = lam
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, len(p.idx), idx=g.idx, jitter=JIT)
+    try:
+        X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc,
+                               opts=pk.make_opts(tol=1e-6, prec=prec), allow_warning=False)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    tr = true_relres(p, host(X))
+    assert np.all(tr <= 1e-6), tr
