@@ -300,6 +300,93 @@ __global__ __launch_bounds__(256) void k_mvm_f64(const double* __restrict__ xs, 
     }
 }
 
+// FP64 product with K V on 16x16x4 FP64 MFMA (d <= 16).  Wave: U i-tiles of
+// 16 rows; per 16-row j-tile each lane computes, with direct FP64
+// differences and exp on the vector ALUs, the four kernel entries
+// K[i0 + l % 16][j0 + 4 s + l / 16], s = 0..3 -- the A operands of four MFMAs
+// whose B operands are V[j0 + 4 s + l / 16][16 kt + l % 16].
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int DP, int KT, int U>
+__global__ __launch_bounds__(256) void k_mvm_f64m(const double* __restrict__ xs, int d,
+                                                  const double* __restrict__ V, int64_t ldv,
+                                                  int kcols, int64_t n, double sigma2,
+                                                  double* __restrict__ part, int64_t ldp,
+                                                  int64_t split_stride, int64_t j_per_split) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, cc = lane & 15;
+    const int64_t itile0 = (int64_t(blockIdx.x) * 4 + w) * U;
+    const int split = blockIdx.y;
+    const int64_t j0s = split * j_per_split;
+    const int64_t j1 = min(n, j0s + j_per_split);
+    double xi[U][DP];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = (itile0 + u) * 16 + cc;
+#pragma unroll
+        for (int r = 0; r < DP; ++r) xi[u][r] = (i < n && r < d) ? xs[i * d + r] : 0.0;
+    }
+    f64x4 acc[U][KT];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) acc[u][kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const double ls2 = log(sigma2);
+    for (int64_t jb = j0s; jb < j1; jb += 16) {
+#pragma unroll
+        for (int sidx = 0; sidx < 4; ++sidx) {
+            const int64_t j = jb + 4 * sidx + g;
+            const bool jv = j < j1;
+            double xj[DP], vb[KT];
+#pragma unroll
+            for (int r = 0; r < DP; ++r) xj[r] = (jv && r < d) ? xs[j * d + r] : 0.0;
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) {
+                const int c = 16 * kt + cc;
+                vb[kt] = (jv && c < kcols) ? V[j * ldv + c] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                double sq = 0.0;
+#pragma unroll
+                for (int r = 0; r < DP; ++r) {
+                    const double t = xi[u][r] - xj[r];
+                    sq = fma(t, t, sq);
+                }
+                const double kij = exp(fma(-0.5, sq, ls2));
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt)
+                    acc[u][kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(kij, vb[kt], acc[u][kt], 0, 0, 0);
+            }
+        }
+    }
+    // FP64 16x16x4 results: lane l holds rows l / 16 + 4 r, column l % 16
+    double* po = part + split * split_stride;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = (itile0 + u) * 16 + g + 4 * r;
+                const int c = 16 * kt + cc;
+                if (i < n && c < kcols) po[i * ldp + c] = acc[u][kt][r];
+            }
+}
+
+template <int DP>
+static void launch_f64m(int KT, dim3 grid, hipStream_t s, const double* xs, int d, const double* V,
+                        int64_t ldv, int k, int64_t n, double sigma2, double* part, int64_t ldp,
+                        int64_t sstride, int64_t jps) {
+    switch (KT) {
+        case 1: k_mvm_f64m<DP, 1, 2><<<grid, 256, 0, s>>>(xs, d, V, ldv, k, n, sigma2, part, ldp, sstride, jps); break;
+        case 2: k_mvm_f64m<DP, 2, 2><<<grid, 256, 0, s>>>(xs, d, V, ldv, k, n, sigma2, part, ldp, sstride, jps); break;
+        case 3: k_mvm_f64m<DP, 3, 2><<<grid, 256, 0, s>>>(xs, d, V, ldv, k, n, sigma2, part, ldp, sstride, jps); break;
+        case 4: k_mvm_f64m<DP, 4, 2><<<grid, 256, 0, s>>>(xs, d, V, ldv, k, n, sigma2, part, ldp, sstride, jps); break;
+        default: fail(PKM_ERR_UNSUPPORTED, "FP64 MFMA product: bad column tiling");
+    }
+}
+
 template <int DP>
 static void launch_f64_d(int kc, dim3 grid, hipStream_t s, const double* xs, int d,
                          const double* V, int64_t ldv, int col0, int k, int64_t n,
@@ -337,9 +424,12 @@ void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy) 
     hipStream_t s = ctx->stream;
     const int64_t n = P.n;
     const int d = P.d;
-    int64_t nrb = cdiv(n, 256);
+    const bool use_mfma = d <= 16 && k >= 4;
+    // rows per work-group: 128 on the MFMA path (4 waves x 2 tiles x 16), 256 otherwise
+    const int64_t rows_wg = use_mfma ? 128 : 256;
+    int64_t nrb = cdiv(n, rows_wg);
     int jsplit = 1;
-    while (jsplit < 64 && nrb * jsplit < 1024 && n / (jsplit * 2) >= 256) jsplit <<= 1;
+    while (jsplit < 64 && nrb * jsplit < 2048 && n / (jsplit * 2) >= 256) jsplit <<= 1;
     int64_t jps = round_up(cdiv(n, jsplit), 64);
     jsplit = int(cdiv(n, jps));
     int64_t sstride = n * int64_t(k);
@@ -349,24 +439,35 @@ void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy) 
 
     hipEvent_t e0 = ctx->ev0, e1 = ctx->ev1;
     if (ctx->timing) PKM_HIP(hipEventRecord(e0, s));
-    for (int col0 = 0; col0 < k;) {
-        int rem = k - col0;
-        int kc;
-        if (rem > 24) kc = 24;
-        else if (rem > 17) kc = 24;
-        else if (rem > 12) kc = 17;
-        else if (rem > 8) kc = 12;
-        else if (rem > 4) kc = 8;
-        else if (rem > 2) kc = 4;
-        else kc = rem;
-        const double* xs = P.xs64.as<double>();
-        if (d <= 4) launch_f64_d<4>(kc, grid, s, xs, d, V, ldv, col0, k, n, P.sigma2, part, k, sstride, jps);
-        else if (d <= 8) launch_f64_d<8>(kc, grid, s, xs, d, V, ldv, col0, k, n, P.sigma2, part, k, sstride, jps);
-        else if (d <= 16) launch_f64_d<16>(kc, grid, s, xs, d, V, ldv, col0, k, n, P.sigma2, part, k, sstride, jps);
-        else if (d <= 32) launch_f64_d<32>(kc, grid, s, xs, d, V, ldv, col0, k, n, P.sigma2, part, k, sstride, jps);
-        else launch_f64_d<64>(kc, grid, s, xs, d, V, ldv, col0, k, n, P.sigma2, part, k, sstride, jps);
-        PKM_CHECK_LAUNCH();
-        col0 += kc;
+    const double* xs = P.xs64.as<double>();
+    if (use_mfma) {
+        for (int col0 = 0; col0 < k; col0 += 64) {
+            const int kc = std::min(64, k - col0);
+            const int KT = int(cdiv(kc, 16));
+            if (d <= 4) launch_f64m<4>(KT, grid, s, xs, d, V + col0, ldv, kc, n, P.sigma2, part + col0, k, sstride, jps);
+            else if (d <= 8) launch_f64m<8>(KT, grid, s, xs, d, V + col0, ldv, kc, n, P.sigma2, part + col0, k, sstride, jps);
+            else launch_f64m<16>(KT, grid, s, xs, d, V + col0, ldv, kc, n, P.sigma2, part + col0, k, sstride, jps);
+            PKM_CHECK_LAUNCH();
+        }
+    } else {
+        for (int col0 = 0; col0 < k;) {
+            int rem = k - col0;
+            int kc;
+            if (rem > 24) kc = 24;
+            else if (rem > 17) kc = 24;
+            else if (rem > 12) kc = 17;
+            else if (rem > 8) kc = 12;
+            else if (rem > 4) kc = 8;
+            else if (rem > 2) kc = 4;
+            else kc = rem;
+            if (d <= 4) launch_f64_d<4>(kc, grid, s, xs, d, V, ldv, col0, k, n, P.sigma2, part, k, sstride, jps);
+            else if (d <= 8) launch_f64_d<8>(kc, grid, s, xs, d, V, ldv, col0, k, n, P.sigma2, part, k, sstride, jps);
+            else if (d <= 16) launch_f64_d<16>(kc, grid, s, xs, d, V, ldv, col0, k, n, P.sigma2, part, k, sstride, jps);
+            else if (d <= 32) launch_f64_d<32>(kc, grid, s, xs, d, V, ldv, col0, k, n, P.sigma2, part, k, sstride, jps);
+            else launch_f64_d<64>(kc, grid, s, xs, d, V, ldv, col0, k, n, P.sigma2, part, k, sstride, jps);
+            PKM_CHECK_LAUNCH();
+            col0 += kc;
+        }
     }
     if (ctx->timing) {
         PKM_HIP(hipEventRecord(e1, s));

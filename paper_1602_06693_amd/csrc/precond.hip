@@ -159,64 +159,79 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const
 // ---------------------------------------------------------------------------
 constexpr int AT = 64;   // Psi columns per work-group (phase 1), rows (phase 2)
 
-// Phase 1: part[chunk][j][c] = sum_{i in chunk} Psi[i][j] R[i][c].
-// Work-group: 64 Psi columns x one row chunk; wave w takes rows i = w mod 4,
-// lane l owns Psi column j0 + l and all KC right-hand-side columns.
-template <int KC>
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Phase 1: part[chunk][j][c] = sum_{i in chunk} Psi[i][j] R[i][c] on 16x16x4
+// FP64 MFMA.  Wave w owns the 16 Psi columns j0 .. j0 + 15; lane l feeds
+// A[j0 + l % 16][i] = Psi[i][j0 + l % 16] and B[i][c] = R[i][c0 + 16 kt + l % 16]
+// for rows i = ib + 4 (l / 16) + q, so each load instruction reads four rows
+// of 16 consecutive doubles (whole 128-byte lines of Psi).
+template <int KT>
 __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, int m,
                                                 const double* __restrict__ R, int k, int c0,
-                                                int64_t n, int64_t rows_per_chunk,
+                                                int kc, int64_t n, int64_t rows_per_chunk,
                                                 double* __restrict__ part) {
-    __shared__ double sr[AT][KC];
-    __shared__ double red[4][AT];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int j = blockIdx.x * AT + lane;
+    const int g = lane >> 4, cc = lane & 15;
+    const int j0 = (blockIdx.x * 4 + w) * 16;
+    if (j0 >= m) return;
     const int64_t i0 = int64_t(blockIdx.y) * rows_per_chunk;
     const int64_t i1 = min(n, i0 + rows_per_chunk);
-    double acc[KC];
+    const int jj = j0 + cc;
+    const bool jv = jj < m;
+    bool cv[KT];
 #pragma unroll
-    for (int c = 0; c < KC; ++c) acc[c] = 0.0;
-    for (int64_t ib = i0; ib < i1; ib += AT) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < AT * KC; e += 256) {
-            int rr = e / KC, c = e % KC;
-            int64_t i = ib + rr;
-            sr[rr][c] = (i < i1 && c0 + c < k) ? R[i * k + c0 + c] : 0.0;
+    for (int kt = 0; kt < KT; ++kt) cv[kt] = 16 * kt + cc < kc;
+    f64x4 acc[KT];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) acc[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t ib = i0; ib < i1; ib += 16) {
+        double a[4], b[4][KT];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = ib + 4 * g + q;
+            const bool iv = i < i1;
+            a[q] = (iv && jv) ? psi[i * m + jj] : 0.0;
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+                b[q][kt] = (iv && cv[kt]) ? R[i * k + c0 + 16 * kt + cc] : 0.0;
         }
-        __syncthreads();
-        const int rn = int(min<int64_t>(AT, i1 - ib));
-        for (int rr = w; rr < rn; rr += 4) {
-            const double v = j < m ? psi[(ib + rr) * m + j] : 0.0;
 #pragma unroll
-            for (int c = 0; c < KC; ++c) acc[c] = fma(v, sr[rr][c], acc[c]);
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+                acc[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q][kt], acc[kt], 0, 0, 0);
+    }
+    // FP64 16x16x4 results: lane l holds rows l / 16 + 4 r (here: Psi columns)
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = j0 + g + 4 * r;
+            if (j < m && cv[kt])
+                part[(int64_t(blockIdx.y) * m + j) * k + c0 + 16 * kt + cc] = acc[kt][r];
         }
-    }
-    // cross-wave sum, one right-hand-side column at a time
-#pragma unroll
-    for (int c = 0; c < KC; ++c) {
-        __syncthreads();
-        red[w][lane] = acc[c];
-        __syncthreads();
-        if (w == 0 && j < m && c0 + c < k)
-            part[(int64_t(blockIdx.y) * m + j) * k + c0 + c] =
-                red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-    }
 }
 
 // T[j][c] = sum over chunks of part, written zero-padded as an m_pad x ldt
 // block (m_pad = m rounded up to 16, ldt = 16 KT) for the phase-2 MFMA.
-__global__ void k_sum_chunks(const double* __restrict__ part, int nchunk, int m, int k, int c0,
-                             int kc, int m_pad, int ldt, double* __restrict__ T) {
-    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (e >= int64_t(m_pad) * ldt) return;
-    const int j = int(e / ldt), c = int(e % ldt);
+// 64 outputs per work-group; its four waves each sum a quarter of the chunks
+// (fixed order), then one wave adds the four partial sums.
+__global__ __launch_bounds__(256) void k_sum_chunks(const double* __restrict__ part, int nchunk,
+                                                    int m, int k, int c0, int kc, int m_pad,
+                                                    int ldt, double* __restrict__ T) {
+    __shared__ double sh[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t e = blockIdx.x * int64_t(64) + lane;
+    const bool ev = e < int64_t(m_pad) * ldt;
+    const int j = ev ? int(e / ldt) : 0, c = ev ? int(e % ldt) : 0;
     double s = 0.0;
-    if (j < m && c < kc && c0 + c < k)
-        for (int q = 0; q < nchunk; ++q) s += part[(int64_t(q) * m + j) * k + c0 + c];
-    T[e] = s;
+    if (ev && j < m && c < kc && c0 + c < k)
+        for (int q = w; q < nchunk; q += 4) s += part[(int64_t(q) * m + j) * k + c0 + c];
+    sh[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && ev) T[e] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
 }
-
-typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Phase 2: Z = D^-1 R - Psi T for columns [c0, c0 + 16 KT).  Each wave owns
 // 16 rows; lane l reads Psi[row0 + l % 16][m0 + 4 (l / 16) + q], q = 0..3,
@@ -275,19 +290,18 @@ static void apply_chunk(pkm_ctx* ctx, const pkm_precond* pc, int k, int c0, cons
     constexpr int KT = (KC + 15) / 16;
     const int ldt = 16 * KT;
     const int m_pad = int(round_up(m, 16));
-    // row chunks: a few work-groups per CU in phase 1
-    int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(cdiv(n, AT), 1024 / mt));
-    nchunk = std::min<int64_t>(nchunk, 64);
-    int64_t rpc = round_up(cdiv(n, nchunk), AT);
+    // row chunks: ~1024 work-groups in phase 1, each at least 256 rows
+    int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 1024 / mt));
+    int64_t rpc = round_up(cdiv(n, nchunk), 16);
     nchunk = cdiv(n, rpc);
     ctx->red2.ensure(sizeof(double) * (nchunk * int64_t(m) * k + int64_t(m_pad) * ldt));
     double* part = ctx->red2.as<double>();
     double* T = part + nchunk * int64_t(m) * k;
-    k_psit_r<KC><<<dim3((unsigned)mt, (unsigned)nchunk), 256, 0, s>>>(
-        pc->psi.as<double>(), m, R, k, c0, n, rpc, part);
+    k_psit_r<KT><<<dim3((unsigned)mt, (unsigned)nchunk), 256, 0, s>>>(
+        pc->psi.as<double>(), m, R, k, c0, kc, n, rpc, part);
     PKM_CHECK_LAUNCH();
-    k_sum_chunks<<<cdiv(int64_t(m_pad) * ldt, 256), 256, 0, s>>>(part, int(nchunk), m, k, c0, kc,
-                                                                 m_pad, ldt, T);
+    k_sum_chunks<<<cdiv(int64_t(m_pad) * ldt, 64), 256, 0, s>>>(part, int(nchunk), m, k, c0, kc,
+                                                                m_pad, ldt, T);
     PKM_CHECK_LAUNCH();
     k_apply_z<KT><<<(unsigned)cdiv(n, 64), 256, 0, s>>>(pc->psi.as<double>(), m, T, ldt,
                                                         pc->dinv.as<double>(), R, k, c0, n, Z);
