@@ -66,6 +66,9 @@ extern "C" {
 #define PKM_PC_NYSTROM  1   /* P = K_XU K_UU^-1 K_UX + lambda I  (Section 3.1)   */
 #define PKM_PC_FITC     2   /* P = Q + diag(K - Q) + lambda I   (Section 3.1.1) */
 #define PKM_PC_LOWRANK  3   /* P = Phi Phi^T + lambda I         (Section 3.2)   */
+#define PKM_PC_SKETCH   4   /* P = K S (S^T K S)^-1 S^T K + lambda I: Nystrom
+                               with a general n x m sketch S (Section 3.1 is the
+                               case S = columns of I at the inducing points)   */
 
 /* ---- per-column solver status ------------------------------------------ */
 #define PKM_COL_CONVERGED  0
@@ -74,6 +77,7 @@ extern "C" {
 
 typedef struct pkm_ctx pkm_ctx;
 typedef struct pkm_precond pkm_precond;
+typedef struct pkm_mlp pkm_mlp;
 
 /* One GP regression problem (Section 2): inputs X, kernel hyperparameters
  * theta = (sigma2, l_1 .. l_d) of Eq. (1), and noise variance lambda.
@@ -138,9 +142,13 @@ int pkm_kernel_mvm(pkm_ctx* ctx, const pkm_problem* prob, int32_t k,
  * NYSTROM / FITC: inducing points U = X[idx], idx a device array of m
  *   distinct indices in [0, n); jitter >= 0 is added to the diagonal of K_UU.
  * LOWRANK: factor Phi given as a device n x m FP64 array (idx ignored).
+ * SKETCH: sketch S given in Phi (device n x m FP64); K S is formed with one
+ *   FP32 kernel product, S^T K S gets jitter * (mean of its diagonal) added
+ *   before its FP64 Cholesky, and the factor is K S L^-T, so the low-rank
+ *   part never exceeds K (P <= K_y in the positive semi-definite order).
  * The result represents P^-1 = D^-1 - Psi Psi^T (matrix inversion lemma with
  * the noise, or noise plus FITC diagonal, as D); it is owned by the library.
- * 1 <= m <= min(n, 4096).                                                    */
+ * 1 <= m <= min(n, 4096); SKETCH needs d <= 34.                            */
 int pkm_precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int32_t kind,
                       int32_t m, const int32_t* idx, const double* Phi,
                       double jitter, pkm_precond** out);
@@ -188,6 +196,34 @@ int pkm_lml_grad(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
                  const double* y, int32_t N, const double* Z,
                  const pkm_solve_opts* opts, double* grad_host, double* sol,
                  pkm_solve_info* info);
+
+/* ---- learned low-rank factor (Section 3.2 form P = U U^T + lambda I) -------
+ * A network maps each scaled input row x_i / l to a row of U (n x rank):
+ *   a1 = x W1 + b1, h1 = gelu(a1), a2 = h1 W2 + b2, h2 = gelu(a2),
+ *   U = h2 W3 + b3, gelu(a) = a (1 + erf(a / sqrt 2)) / 2,
+ * hidden width 128, BF16 weights in the products with FP32 accumulation,
+ * FP32 master weights.  params (host, FP32) are laid out W1 (d_in x 128,
+ * row-major), b1 (128), W2 (128 x 128), b2, W3 (128 x rank), b3 (rank);
+ * 1 <= d_in <= 32, rank a multiple of 16 in [16, 128].  The object owns its
+ * device buffers; pkm_mlp_destroy releases them.                            */
+int pkm_mlp_create(pkm_ctx* ctx, int32_t d_in, int32_t hidden, int32_t rank,
+                   const float* params, pkm_mlp** out);
+int pkm_mlp_destroy(pkm_mlp* net);
+/* Host copy of the FP32 master weights (same layout as params).             */
+int pkm_mlp_params(pkm_ctx* ctx, const pkm_mlp* net, float* params);
+/* U = net(X / l) for the problem's inputs (prob->d == d_in); U device
+ * n x rank FP64, ready for pkm_precond_setup(PKM_PC_LOWRANK).               */
+int pkm_mlp_forward(pkm_ctx* ctx, pkm_mlp* net, const pkm_problem* prob, double* U);
+/* Training loss on probe pairs (Z, KZ = K Z), Z and KZ device n x nz FP64:
+ *   L = |U (U^T Z) - K Z|_F^2 / |K Z|_F^2
+ * (unbiased for |U U^T - K|_F^2 up to the normaliser since E[Z Z^T] = I).
+ * pkm_mlp_loss_grad writes L and, if grads is non-NULL, dL/dparams (host,
+ * params layout); pkm_mlp_train_step also applies one Adam step (beta1 0.9,
+ * beta2 0.999, eps 1e-8) with learning rate lr.                             */
+int pkm_mlp_loss_grad(pkm_ctx* ctx, pkm_mlp* net, const pkm_problem* prob, int32_t nz,
+                      const double* Z, const double* KZ, double* loss, float* grads);
+int pkm_mlp_train_step(pkm_ctx* ctx, pkm_mlp* net, const pkm_problem* prob, int32_t nz,
+                       const double* Z, const double* KZ, double lr, double* loss);
 
 /* ---- measurement ----------------------------------------------------------
  * When enabled, every kernel-product launch is bracketed by HIP events on

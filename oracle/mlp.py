@@ -98,8 +98,8 @@ def backward(params, cache, dU):
     return g
 
 
-def loss_and_grad(params, X, Z, KZ):
-    U, cache = forward(params, X)
+def loss_and_grad(params, X, Z, KZ, bf16=False):
+    U, cache = forward(params, X, bf16=bf16)
     L, dU = loss_grad_U(U, Z, KZ)
     return L, backward(params, cache, dU)
 

@@ -93,6 +93,30 @@ def fitc(X, sigma2, lengthscales, lam, idx, jitter=0.0):
     return Preconditioner(apply, dense, {"D": D, "Kxu": Kxu, "Kuu": Kuu})
 
 
+def sketch(X, sigma2, lengthscales, lam, S, jitter=0.0):
+    """Nystrom with a general sketch S (n x m): P = K S C^{-1} S^T K + lambda I,
+    C = S^T K S + jitter * mean(diag(S^T K S)) I.  With S = columns of the
+    identity at the inducing indices (and the jitter scaled alike) this is the
+    Section 3.1 preconditioner; inverted by the same matrix inversion lemma,
+    P^{-1} v = lambda^{-1} [ v - A (lambda C + A^T A)^{-1} A^T v ],  A = K S."""
+    X = np.asarray(X, dtype=np.float64)
+    S = np.asarray(S, dtype=np.float64)
+    K = rbf_block(X, X, sigma2, lengthscales)
+    A = K @ S
+    C = S.T @ A
+    C = 0.5 * (C + C.T)
+    C = C + jitter * np.mean(np.diag(C)) * np.eye(S.shape[1])
+    core = lam * C + A.T @ A
+
+    def apply(R):
+        return (R - A @ np.linalg.solve(core, A.T @ R)) / lam
+
+    def dense():
+        return A @ np.linalg.solve(C, A.T) + lam * np.eye(X.shape[0])
+
+    return Preconditioner(apply, dense, {"C": C, "A": A})
+
+
 def lowrank(Phi, lam):
     Phi = np.asarray(Phi, dtype=np.float64)
     core = lam * np.eye(Phi.shape[1]) + Phi.T @ Phi

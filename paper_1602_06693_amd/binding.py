@@ -32,6 +32,7 @@ PKM_PC_NONE = 0
 PKM_PC_NYSTROM = 1
 PKM_PC_FITC = 2
 PKM_PC_LOWRANK = 3
+PKM_PC_SKETCH = 4
 
 PKM_COL_CONVERGED = 0
 PKM_COL_MAX_ITER = 1
@@ -42,7 +43,8 @@ EXPORTS = (
     "pkm_create", "pkm_destroy", "pkm_last_error", "pkm_version", "pkm_kernel_mvm",
     "pkm_precond_setup", "pkm_precond_apply", "pkm_precond_diag", "pkm_precond_destroy",
     "pkm_solve", "pkm_grad_pass", "pkm_lml_grad", "pkm_timing_enable", "pkm_mvm_stats",
-    "pkm_mvm_stats_reset",
+    "pkm_mvm_stats_reset", "pkm_mlp_create", "pkm_mlp_destroy", "pkm_mlp_params",
+    "pkm_mlp_forward", "pkm_mlp_loss_grad", "pkm_mlp_train_step",
 )
 
 
@@ -103,6 +105,13 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "pkm_timing_enable": (C.c_int, [vp, i32]),
         "pkm_mvm_stats": (C.c_int, [vp, i32, P(i64), P(dbl), P(dbl), P(dbl)]),
         "pkm_mvm_stats_reset": (C.c_int, [vp]),
+        "pkm_mlp_create": (C.c_int, [vp, i32, i32, i32, P(C.c_float), P(vp)]),
+        "pkm_mlp_destroy": (C.c_int, [vp]),
+        "pkm_mlp_params": (C.c_int, [vp, vp, P(C.c_float)]),
+        "pkm_mlp_forward": (C.c_int, [vp, vp, P(pkm_problem), vp]),
+        "pkm_mlp_loss_grad": (C.c_int, [vp, vp, P(pkm_problem), i32, vp, vp, P(dbl),
+                                        P(C.c_float)]),
+        "pkm_mlp_train_step": (C.c_int, [vp, vp, P(pkm_problem), i32, vp, vp, dbl, P(dbl)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -297,3 +306,66 @@ def pkm_mvm_stats(ctx, prec):
 
 def pkm_mvm_stats_reset(ctx):
     _check(load().pkm_mvm_stats_reset(ctx), ctx)
+
+
+MLP_PARAM_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def mlp_flatten(params):
+    """Concatenate a dict of weights into the library's FP32 parameter layout."""
+    return np.ascontiguousarray(np.concatenate(
+        [np.asarray(params[k], dtype=np.float32).reshape(-1) for k in MLP_PARAM_NAMES]))
+
+
+def mlp_unflatten(flat, d_in, hidden, rank):
+    shapes = {"W1": (d_in, hidden), "b1": (hidden,), "W2": (hidden, hidden), "b2": (hidden,),
+              "W3": (hidden, rank), "b3": (rank,)}
+    out, o = {}, 0
+    for k in MLP_PARAM_NAMES:
+        size = int(np.prod(shapes[k]))
+        out[k] = np.asarray(flat[o:o + size], dtype=np.float64).reshape(shapes[k])
+        o += size
+    return out
+
+
+def pkm_mlp_create(ctx, params, d_in, hidden, rank):
+    flat = mlp_flatten(params)
+    out = C.c_void_p()
+    _check(load().pkm_mlp_create(ctx, int(d_in), int(hidden), int(rank),
+                                 flat.ctypes.data_as(C.POINTER(C.c_float)), C.byref(out)), ctx)
+    return out
+
+
+def pkm_mlp_destroy(net):
+    return load().pkm_mlp_destroy(net)
+
+
+def pkm_mlp_params(ctx, net, d_in, hidden, rank):
+    n = d_in * hidden + hidden + hidden * hidden + hidden + hidden * rank + rank
+    flat = np.zeros(n, np.float32)
+    _check(load().pkm_mlp_params(ctx, net, flat.ctypes.data_as(C.POINTER(C.c_float))), ctx)
+    return mlp_unflatten(flat, d_in, hidden, rank)
+
+
+def pkm_mlp_forward(ctx, net, prob: Problem, rank, U=None):
+    import torch
+    if U is None:
+        U = torch.empty((prob.n, rank), dtype=torch.float64, device=prob.X.device)
+    _check(load().pkm_mlp_forward(ctx, net, prob.ref, _ptr(U)), ctx)
+    return U
+
+
+def pkm_mlp_loss_grad(ctx, net, prob: Problem, Z, KZ, d_in, hidden, rank):
+    n = d_in * hidden + hidden + hidden * hidden + hidden + hidden * rank + rank
+    g = np.zeros(n, np.float32)
+    loss = C.c_double()
+    _check(load().pkm_mlp_loss_grad(ctx, net, prob.ref, int(Z.shape[1]), _ptr(Z), _ptr(KZ),
+                                    C.byref(loss), g.ctypes.data_as(C.POINTER(C.c_float))), ctx)
+    return loss.value, mlp_unflatten(g, d_in, hidden, rank)
+
+
+def pkm_mlp_train_step(ctx, net, prob: Problem, Z, KZ, lr):
+    loss = C.c_double()
+    _check(load().pkm_mlp_train_step(ctx, net, prob.ref, int(Z.shape[1]), _ptr(Z), _ptr(KZ),
+                                     float(lr), C.byref(loss)), ctx)
+    return loss.value

@@ -15,6 +15,18 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
           double* X, const pkm_solve_opts* o, pkm_solve_info* info);
 void grad_pass(pkm_ctx* ctx, const pkm_problem* prob, int N, const double* AS,
                const double* YZ, double* grad);
+void mlp_create(pkm_ctx* ctx, int d_in, int hidden, int rank, const float* params_host,
+                pkm_mlp* net);
+void mlp_forward(pkm_ctx* ctx, pkm_mlp* net, int64_t n, const double* xs, double* U);
+double mlp_loss_grad(pkm_ctx* ctx, pkm_mlp* net, int64_t n, const double* xs, int nz,
+                     const double* Z, const double* KZ);
+double mlp_train_step(pkm_ctx* ctx, pkm_mlp* net, int64_t n, const double* xs, int nz,
+                      const double* Z, const double* KZ, double lr);
+void mlp_release(pkm_mlp* net);
+int64_t mlp_nparams(const pkm_mlp* net);
+float* mlp_grad_ptr(pkm_mlp* net);
+const float* mlp_param_ptr(const pkm_mlp* net);
+int mlp_d_in(const pkm_mlp* net);
 }  // namespace pkm
 
 using namespace pkm;
@@ -142,11 +154,12 @@ int pkm_precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int32_t kind, int32
     int rc = guarded(ctx, [&] {
         PKM_REQUIRE(out != nullptr, "out is NULL");
         validate_problem(prob);
-        PKM_REQUIRE(kind == PKM_PC_NYSTROM || kind == PKM_PC_FITC || kind == PKM_PC_LOWRANK,
+        PKM_REQUIRE(kind >= PKM_PC_NYSTROM && kind <= PKM_PC_SKETCH,
                     "unknown preconditioner kind");
+        PKM_REQUIRE(kind != PKM_PC_SKETCH || prob->d <= 34, "sketch preconditioner needs d <= 34");
         PKM_REQUIRE(m >= 1 && m <= 4096 && m <= prob->n, "m must be in [1, min(n, 4096)]");
         PKM_REQUIRE(std::isfinite(jitter) && jitter >= 0.0, "jitter must be >= 0");
-        if (kind == PKM_PC_LOWRANK) require_dev(Phi, "Phi");
+        if (kind == PKM_PC_LOWRANK || kind == PKM_PC_SKETCH) require_dev(Phi, "Phi");
         else {
             PKM_REQUIRE(idx != nullptr, "idx is NULL");
             PKM_REQUIRE((reinterpret_cast<uintptr_t>(idx) & 3) == 0, "idx must be 4-byte aligned");
@@ -286,6 +299,95 @@ int pkm_lml_grad(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, c
             PKM_HIP(hipMemcpyAsync(sol, S, sizeof(double) * n * k, hipMemcpyDeviceToDevice, s));
         PKM_HIP(hipStreamSynchronize(s));
         return rc;
+    });
+}
+
+int pkm_mlp_create(pkm_ctx* ctx, int32_t d_in, int32_t hidden, int32_t rank,
+                   const float* params, pkm_mlp** out) {
+    if (!ctx) return PKM_ERR_INVALID;
+    if (out) *out = nullptr;
+    pkm_mlp* net = nullptr;
+    int rc = guarded(ctx, [&] {
+        PKM_REQUIRE(out != nullptr && params != nullptr, "NULL argument");
+        net = new pkm_mlp();
+        mlp_create(ctx, d_in, hidden, rank, params, net);
+        return PKM_OK;
+    });
+    if (rc != PKM_OK) {
+        if (net) pkm_mlp_destroy(net);
+        return rc;
+    }
+    *out = net;
+    return PKM_OK;
+}
+
+int pkm_mlp_destroy(pkm_mlp* net) {
+    if (!net) return PKM_OK;
+    (void)hipDeviceSynchronize();
+    mlp_release(net);
+    delete net;
+    return PKM_OK;
+}
+
+int pkm_mlp_params(pkm_ctx* ctx, const pkm_mlp* net, float* params) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        PKM_REQUIRE(net != nullptr && params != nullptr, "NULL argument");
+        PKM_HIP(hipMemcpyAsync(params, mlp_param_ptr(net), sizeof(float) * mlp_nparams(net),
+                               hipMemcpyDeviceToHost, ctx->stream));
+        PKM_HIP(hipStreamSynchronize(ctx->stream));
+        return PKM_OK;
+    });
+}
+
+static void mlp_check(pkm_ctx* ctx, const pkm_mlp* net, const pkm_problem* prob) {
+    PKM_REQUIRE(net != nullptr, "network is NULL");
+    validate_problem(prob);
+    PKM_REQUIRE(prob->d == mlp_d_in(net), "problem dimension differs from the network input width");
+    prepare(ctx, prob, true, false);
+}
+
+int pkm_mlp_forward(pkm_ctx* ctx, pkm_mlp* net, const pkm_problem* prob, double* U) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        require_dev(U, "U");
+        mlp_check(ctx, net, prob);
+        mlp_forward(ctx, net, prob->n, ctx->prep.xs64.as<double>(), U);
+        return PKM_OK;
+    });
+}
+
+int pkm_mlp_loss_grad(pkm_ctx* ctx, pkm_mlp* net, const pkm_problem* prob, int32_t nz,
+                      const double* Z, const double* KZ, double* loss, float* grads) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        PKM_REQUIRE(nz >= 1 && nz <= 4096, "nz must be in [1, 4096]");
+        require_dev(Z, "Z");
+        require_dev(KZ, "KZ");
+        PKM_REQUIRE(loss != nullptr, "loss is NULL");
+        mlp_check(ctx, net, prob);
+        *loss = mlp_loss_grad(ctx, net, prob->n, ctx->prep.xs64.as<double>(), nz, Z, KZ);
+        if (grads) {
+            PKM_HIP(hipMemcpyAsync(grads, mlp_grad_ptr(net), sizeof(float) * mlp_nparams(net),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+            PKM_HIP(hipStreamSynchronize(ctx->stream));
+        }
+        return PKM_OK;
+    });
+}
+
+int pkm_mlp_train_step(pkm_ctx* ctx, pkm_mlp* net, const pkm_problem* prob, int32_t nz,
+                       const double* Z, const double* KZ, double lr, double* loss) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        PKM_REQUIRE(nz >= 1 && nz <= 4096, "nz must be in [1, 4096]");
+        PKM_REQUIRE(std::isfinite(lr) && lr > 0.0, "lr must be > 0");
+        require_dev(Z, "Z");
+        require_dev(KZ, "KZ");
+        mlp_check(ctx, net, prob);
+        double L = mlp_train_step(ctx, net, prob->n, ctx->prep.xs64.as<double>(), nz, Z, KZ, lr);
+        if (loss) *loss = L;
+        return PKM_OK;
     });
 }
 

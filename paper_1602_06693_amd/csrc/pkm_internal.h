@@ -114,6 +114,19 @@ struct pkm_precond {
     pkm::DevBuf dinv;   // n FP64
 };
 
+// Learned factor network (mlp.hip).
+struct pkm_mlp {
+    int device = 0;
+    int d_in = 0, hidden = 0, rank = 0;
+    int64_t nparams = 0;
+    int64_t t = 0;                 // Adam step count
+    pkm::DevBuf p32, m32, v32;     // master weights and Adam moments (FP32)
+    pkm::DevBuf g32;               // gradient (FP32)
+    pkm::DevBuf wpack;             // BF16 packed W1, W2, W3
+    pkm::DevBuf act[8];            // activations and work buffers
+    pkm::DevBuf ones, scal, split;
+};
+
 namespace pkm {
 
 // ---- input preparation (prep.hip) ----

@@ -18,12 +18,32 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace pkm {
 
 __global__ void k_add_diag(int64_t m, double* __restrict__ A, int64_t lda, double v) {
     int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i < m) A[i * lda + i] += v;
+}
+
+// Y -= lambda V (n x m)
+__global__ void k_axpy_neg(int64_t tot, double lambda, const double* __restrict__ V,
+                           double* __restrict__ Y) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e < tot) Y[e] -= lambda * V[e];
+}
+
+// A <- (A + A^T) / 2 for an m x m matrix
+__global__ void k_symmetrize(int64_t m, double* __restrict__ A) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= m * m) return;
+    int64_t i = e / m, j = e - i * m;
+    if (j < i) {
+        double v = 0.5 * (A[e] + A[j * m + i]);
+        A[e] = v;
+        A[j * m + i] = v;
+    }
 }
 
 __global__ void k_identity_plus(int64_t m, double* __restrict__ A) {
@@ -129,6 +149,34 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const
         dtrsm_right_lt(ctx, n, m, core, m, winv, psi, m);
         k_diag_d<<<cdiv(n, 256), 256, 0, s>>>(psi, n, m, kind == PKM_PC_FITC, prob->sigma2,
                                               prob->lambda, D);
+        PKM_CHECK_LAUNCH();
+    } else if (kind == PKM_PC_SKETCH) {
+        // K S with the FP32 product (K S = (K + lambda I) S - lambda S)
+        prepare(ctx, prob, true, true);
+        mvm(ctx, PKM_FP32, m, Phi, psi);
+        k_axpy_neg<<<cdiv(n * m, 256), 256, 0, s>>>(n * m, prob->lambda, Phi, psi);
+        PKM_CHECK_LAUNCH();
+        // C = S^T K S (+ jitter * mean diagonal), L = chol(C), factor = K S L^-T
+        dgemm(ctx, true, false, m, m, n, 1.0, Phi, m, psi, m, 0.0, core, m);
+        k_symmetrize<<<cdiv(int64_t(m) * m, 256), 256, 0, s>>>(m, core);
+        PKM_CHECK_LAUNCH();
+        std::vector<double> diag(m);
+        PKM_HIP(hipMemcpy2DAsync(diag.data(), sizeof(double), core, sizeof(double) * (m + 1),
+                                 sizeof(double), m, hipMemcpyDeviceToHost, s));
+        PKM_HIP(hipStreamSynchronize(s));
+        double mean = 0.0;
+        for (double v : diag) mean += v;
+        mean /= m;
+        PKM_REQUIRE(std::isfinite(mean) && mean > 0.0, "sketch: S^T K S has no positive diagonal");
+        k_add_diag<<<cdiv(m, 256), 256, 0, s>>>(m, core, m, jitter * mean);
+        PKM_CHECK_LAUNCH();
+        dpotrf_lower(ctx, m, core, m, winv, dinfo);
+        read_info(ctx, dinfo, &hinfo);
+        if (hinfo != 0)
+            fail(PKM_ERR_BREAKDOWN, "sketch: S^T K S + jitter I is not positive definite "
+                                    "(dependent sketch columns need jitter > 0)");
+        dtrsm_right_lt(ctx, n, m, core, m, winv, psi, m);
+        k_diag_d<<<cdiv(n, 256), 256, 0, s>>>(psi, n, m, 0, prob->sigma2, prob->lambda, D);
         PKM_CHECK_LAUNCH();
     } else {
         PKM_HIP(hipMemcpyAsync(psi, Phi, sizeof(double) * n * m, hipMemcpyDeviceToDevice, s));

@@ -36,7 +36,7 @@ import math
 import numpy as np
 
 __all__ = ["Problem", "make", "WORKLOADS", "rademacher", "inducing_indices",
-           "batched_problems"]
+           "batched_problems", "mlp_params"]
 
 
 @dataclasses.dataclass
@@ -150,6 +150,19 @@ def batched_problems(seed: int = 0, count: int = 64, n_lo: int = 1000,
         out.append(Problem(f"batched[{b}]", np.ascontiguousarray(X), ls, 1.0, lam,
                            y, Z, idx, 1e-6))
     return out
+
+
+def mlp_params(seed: int = 0, d_in: int = 8, hidden: int = 128, rank: int = 128) -> dict:
+    """Initial weights of the factor network: W ~ N(0, 1/fan_in), zero biases."""
+    rng = np.random.default_rng(seed)
+    return {
+        "W1": rng.standard_normal((d_in, hidden)) / math.sqrt(d_in),
+        "b1": np.zeros(hidden),
+        "W2": rng.standard_normal((hidden, hidden)) / math.sqrt(hidden),
+        "b2": np.zeros(hidden),
+        "W3": rng.standard_normal((hidden, rank)) / math.sqrt(hidden),
+        "b3": np.zeros(rank),
+    }
 
 
 WORKLOADS = ("small_fp64", "block_fp32", "mixed", "learned")

@@ -90,3 +90,22 @@ def test_out_of_range_index_is_invalid(ctx):
     with pytest.raises(pk.PkmError) as e:
         pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, 2, idx=idx, jitter=JIT)
     assert e.value.code == pk.PKM_ERR_INVALID
+
+
+@pytest.mark.parametrize("n,m", [(700, 48), (333, 20)])
+def test_sketch_apply_matches_oracle(ctx, n, m):
+    rng = np.random.default_rng(n)
+    p = make("block_fp32", seed=26, n=n, n_probes=3)
+    S = rng.standard_normal((n, m))
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_SKETCH, m, Phi=dev(S), jitter=1e-10)
+    try:
+        got = host(pk.pkm_precond_apply(ctx, pc, g.B))
+    finally:
+        pk.pkm_precond_destroy(pc)
+    P = op.sketch(p.X, p.sigma2, p.lengthscales, p.lam, S, jitter=1e-10)
+    want = P(p.B)
+    # K S comes from the FP32 product (relative error <= 1e-5): the factor and
+    # hence P^-1 inherit that level, amplified by at most cond(P)
+    tol = 1e-5 * np.linalg.cond(P.dense()) ** 0.5
+    assert np.all(rel_err(got, want) < tol), (rel_err(got, want), tol)

@@ -75,3 +75,31 @@ def test_nystrom_reduces_iterations():
     plain = pcg(mv, p.y, tol=1e-8, max_iter=5000)
     pre = pcg(mv, p.y, precond=P, tol=1e-8, max_iter=5000)
     assert pre.iters[0] < plain.iters[0]
+
+
+def test_sketch_with_identity_columns_is_nystrom():
+    p = _case(n=250, m=30, seed=3)
+    S = np.zeros((p.n, len(p.idx)))
+    S[p.idx, np.arange(len(p.idx))] = 1.0
+    Ps = op.sketch(p.X, p.sigma2, p.lengthscales, p.lam, S, jitter=0.0)
+    Pn = op.nystrom(p.X, p.sigma2, p.lengthscales, p.lam, p.idx, jitter=0.0)
+    assert np.allclose(Ps.dense(), Pn.dense(), rtol=1e-8, atol=1e-8)
+    assert np.allclose(Ps(p.B), Pn(p.B), rtol=1e-7, atol=1e-7)
+
+
+def test_sketch_never_exceeds_K_and_full_sketch_is_exact():
+    rng = np.random.default_rng(4)
+    p = _case(n=120, m=10, seed=4)
+    S = rng.standard_normal((p.n, 15))
+    Ps = op.sketch(p.X, p.sigma2, p.lengthscales, p.lam, S, jitter=0.0)
+    K = ok.kernel_matrix(p.X, p.sigma2, p.lengthscales)
+    # K_y - P = K - K S C^-1 S^T K is positive semi-definite
+    gap = K + p.lam * np.eye(p.n) - Ps.dense()
+    assert np.linalg.eigvalsh(0.5 * (gap + gap.T)).min() > -1e-8
+    # a full-rank sketch reproduces K_y: one PCG step
+    X2 = rng.random((40, 3))
+    Pf = op.sketch(X2, 1.0, np.array([0.3, 0.4, 0.5]), 1e-2, np.eye(40), jitter=0.0)
+    B = rng.standard_normal((40, 2))
+    res = pcg(lambda V: ok.kernel_mvm(X2, 1.0, np.array([0.3, 0.4, 0.5]), 1e-2, V), B,
+              precond=Pf, tol=1e-9, max_iter=20)
+    assert np.all(res.iters == 1)
