@@ -117,6 +117,45 @@ def mvm_only(pk, ctx, prob, p, steps, prec_names, ks):
                       "bytes_written": src.numel() * 8}), flush=True)
 
 
+def hyper_mode(pk, ctx, p, a):
+    """Section 5 loop: ADAGRAD steps on (log sigma2, log l); at every step the
+    Nystrom arm (fresh m inducing points) and the learned arm (factor network
+    fine-tuned on K Z probe pairs, sketch-Nystrom factor) solve the same
+    systems; the Nystrom arm's gradient drives theta."""
+    import torch
+
+    from paper_1602_06693_amd import hyper
+    from pkm_inputs import mlp_params
+    dev = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).to("cuda:0")
+    precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x1": pk.PKM_BF16X1,
+             "bf16x3": pk.PKM_BF16X3}
+    opts = pk.make_opts(tol=p.tol, prec=precs[a.prec], reliable_every=a.reliable)
+    theta0 = hyper.theta_of(p.sigma2, p.lengthscales)
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    learned = hyper.LearnedArm(ctx, mlp_params(a.seed, d_in=p.d, rank=a.rank), p.d, a.rank,
+                               log=log)
+    arms = [hyper.NystromArm(p.n, len(p.idx), seed=a.seed), learned]
+    t0 = time.perf_counter()
+    try:
+        traj, rec = hyper.run(ctx, dev(p.X), dev(p.y), dev(p.Z), theta0, p.lam, arms,
+                              a.hyper_steps, eta=1.0, opts=opts, log=log)
+    finally:
+        learned.close()
+    wall = time.perf_counter() - t0
+    out = {"mode": "hyper", "workload": p.name, "n": p.n, "d": p.d, "k": 1 + p.Z.shape[1],
+           "lambda": p.lam, "steps": a.hyper_steps, "product": a.prec, "wall_s": wall,
+           "theta_final": [float(v) for v in traj[-1]], "learned_rank": a.rank,
+           "nystrom_m": len(p.idx), "mlp_train_s": learned.train_s,
+           "mlp_loss_first_last": [learned.losses[0], learned.losses[-1]]}
+    for name, rs in rec.items():
+        out[name] = {"iters": [r["iters"] for r in rs],
+                     "solve_grad_s": sum(r["solve_grad_s"] for r in rs),
+                     "setup_s": sum(r["setup_s"] for r in rs),
+                     "all_converged": all(r["converged"] for r in rs),
+                     "max_relres": max(r["max_relres"] for r in rs)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,7 +172,10 @@ def main():
     ap.add_argument("--ks", default="", help="mvm mode: comma-separated column counts")
     ap.add_argument("--mvm-precs", default="bf16x3",
                     help="mvm mode: comma-separated arithmetics (fp64,fp32,bf16x1,bf16x3)")
-    ap.add_argument("--mode", choices=("step", "mvm"), default="step",
+    ap.add_argument("--hyper-steps", type=int, default=20)
+    ap.add_argument("--n", type=int, default=None, help="override the workload's n")
+    ap.add_argument("--rank", type=int, default=128)
+    ap.add_argument("--mode", choices=("step", "mvm", "hyper"), default="step",
                     help="mvm: only --steps FP32 kernel products of the workload's size, "
                          "then one 1 GiB device copy (counter calibration for profiles)")
     a = ap.parse_args()
@@ -149,7 +191,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    p = make(a.workload, seed=a.seed)
+    p = make(a.workload, seed=a.seed, n=a.n)
     m = len(p.idx)
     N = p.Z.shape[1]
     dev = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).to("cuda:0")
@@ -157,6 +199,10 @@ def main():
     sol = torch.zeros((p.n, 1 + N), dtype=torch.float64, device="cuda:0")
     ctx = pk.pkm_create(0, pk.current_stream_handle())
     prob = pk.Problem(X, p.lengthscales, p.sigma2, p.lam)
+    if a.mode == "hyper":
+        hyper_mode(pk, ctx, p, a)
+        pk.pkm_destroy(ctx)
+        return
     if a.mode == "mvm":
         ks = [int(v) for v in a.ks.split(",")] if a.ks else [1 + N]
         mvm_only(pk, ctx, prob, p, a.steps, a.mvm_precs.split(","), ks)

@@ -116,6 +116,10 @@ typedef struct {
     int64_t  total_iters;    /* steps of the shared loop                     */
     int64_t  true_residuals; /* FP64 true-residual products performed        */
     double   solve_ms;       /* wall time of the solve on the stream         */
+    int32_t  prec_final;     /* product arithmetic in use at the end: the
+                                requested one, or a more accurate one if the
+                                solve escalated (see pkm_solve)             */
+    int32_t  reserved;
 } pkm_solve_info;
 
 /* ---- context ------------------------------------------------------------
@@ -137,6 +141,10 @@ const char* pkm_version(void);
  * Y may not alias V.                                                         */
 int pkm_kernel_mvm(pkm_ctx* ctx, const pkm_problem* prob, int32_t k,
                    int32_t prec, const double* V, double* Y);
+/* Y = (K + shift I) V with any shift >= 0 (shift = 0: the plain K V, e.g.
+ * the probe pairs (Z, K Z) that train the learned factor).                 */
+int pkm_kernel_mvm_shift(pkm_ctx* ctx, const pkm_problem* prob, int32_t k,
+                         int32_t prec, double shift, const double* V, double* Y);
 
 /* ---- preconditioner setup (Sections 3.1, 3.1.1, 3.2) ----------------------
  * NYSTROM / FITC: inducing points U = X[idx], idx a device array of m
@@ -167,12 +175,33 @@ int pkm_precond_destroy(pkm_precond* pc);
  * an FP64 true residual b - K_y x certifies it (that check runs once every
  * live column has stopped); if it fails, r is replaced by the true residual
  * and the column resumes.  With FP32 or BF16 products the same replacement
- * also runs every reliable_every steps.  A column converges when its FP64 true
+ * also runs every reliable_every steps.  A reduced-precision product whose
+ * error is too large for lambda shows as a column breakdown or as a largest
+ * true residual that fails to decrease over two replacement periods; the
+ * solve then raises the product arithmetic (BF16 -> FP32 -> FP64), resumes
+ * broken columns and restarts every column's directions from its FP64 true
+ * residual (reported in prec_final).  A column converges when its FP64 true
  * relative residual is <= tol.  Returns PKM_NOT_CONVERGED if a column reached max_iter and
  * PKM_ERR_BREAKDOWN if one broke down; X holds the last iterate either way. */
 int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
               int32_t k, const double* B, double* X,
               const pkm_solve_opts* opts, pkm_solve_info* info);
+
+/* ---- batched solve ----------------------------------------------------------
+ * P independent problems (own X, theta, lambda, n and d), each with its own
+ * k-column right-hand side B[b] and solution X[b] (device n_b x k FP64;
+ * B and X are host arrays of P device pointers) and preconditioner pcs[b]
+ * (pcs NULL or pcs[b] NULL: none).  Same recurrences, tolerance handling
+ * and per-column reports as pkm_solve (infos: host array of P reports, or
+ * NULL).  Every PCG phase runs as one launch over all problems; the kernel
+ * product is a work-queue launch per input-dimension class whose tile
+ * shape is autotuned on first use (cached in memory and, if the
+ * environment variable PKM_TUNE_CACHE names a file, there as JSON lines).
+ * prec PKM_FP32 (with FP64 residual replacement) or PKM_FP64;
+ * 1 <= k <= 33, every d <= 34 for PKM_FP32.                                */
+int pkm_solve_batched(pkm_ctx* ctx, int32_t P, const pkm_problem* probs,
+                      const pkm_precond* const* pcs, int32_t k, const double* const* B,
+                      double* const* X, const pkm_solve_opts* opts, pkm_solve_info* infos);
 
 /* ---- gradient pass (Eq. (2) with the trace estimate of Section 2.1) -------
  * Given alpha = K_y^-1 y and S = K_y^-1 Z for N Rademacher probes Z, writes
@@ -224,6 +253,15 @@ int pkm_mlp_loss_grad(pkm_ctx* ctx, pkm_mlp* net, const pkm_problem* prob, int32
                       const double* Z, const double* KZ, double* loss, float* grads);
 int pkm_mlp_train_step(pkm_ctx* ctx, pkm_mlp* net, const pkm_problem* prob, int32_t nz,
                        const double* Z, const double* KZ, double lr, double* loss);
+
+/* ---- hyperparameter step (Section 5) ----------------------------------------
+ * ADAGRAD ascent on p host values (log hyperparameters), elementwise:
+ *   G <- G + g^2,   theta <- theta + eta g / (sqrt(G) + eps).
+ * theta and G are updated in place (G starts at zero); host-only, no device
+ * work, no context.  Returns PKM_ERR_INVALID for p < 1, NULL pointers,
+ * eta <= 0 or eps < 0, or a non-finite gradient (nothing is updated).      */
+int pkm_adagrad_step(int32_t p, double* theta, const double* g, double* G, double eta,
+                     double eps);
 
 /* ---- measurement ----------------------------------------------------------
  * When enabled, every kernel-product launch is bracketed by HIP events on

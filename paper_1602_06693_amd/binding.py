@@ -41,10 +41,11 @@ PKM_COL_BREAKDOWN = 2
 # every symbol include/pkm.h declares
 EXPORTS = (
     "pkm_create", "pkm_destroy", "pkm_last_error", "pkm_version", "pkm_kernel_mvm",
+    "pkm_kernel_mvm_shift",
     "pkm_precond_setup", "pkm_precond_apply", "pkm_precond_diag", "pkm_precond_destroy",
-    "pkm_solve", "pkm_grad_pass", "pkm_lml_grad", "pkm_timing_enable", "pkm_mvm_stats",
+    "pkm_solve", "pkm_solve_batched", "pkm_grad_pass", "pkm_lml_grad", "pkm_timing_enable", "pkm_mvm_stats",
     "pkm_mvm_stats_reset", "pkm_mlp_create", "pkm_mlp_destroy", "pkm_mlp_params",
-    "pkm_mlp_forward", "pkm_mlp_loss_grad", "pkm_mlp_train_step",
+    "pkm_mlp_forward", "pkm_mlp_loss_grad", "pkm_mlp_train_step", "pkm_adagrad_step",
 )
 
 
@@ -64,7 +65,7 @@ class pkm_solve_info(C.Structure):
     _fields_ = [("iters", C.POINTER(C.c_int64)), ("relres_true", C.POINTER(C.c_double)),
                 ("relres_rec", C.POINTER(C.c_double)), ("col_status", C.POINTER(C.c_int32)),
                 ("total_iters", C.c_int64), ("true_residuals", C.c_int64),
-                ("solve_ms", C.c_double)]
+                ("solve_ms", C.c_double), ("prec_final", C.c_int32), ("reserved", C.c_int32)]
 
 
 class PkmError(RuntimeError):
@@ -93,12 +94,15 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "pkm_last_error": (C.c_char_p, [vp]),
         "pkm_version": (C.c_char_p, []),
         "pkm_kernel_mvm": (C.c_int, [vp, P(pkm_problem), i32, i32, vp, vp]),
+        "pkm_kernel_mvm_shift": (C.c_int, [vp, P(pkm_problem), i32, i32, dbl, vp, vp]),
         "pkm_precond_setup": (C.c_int, [vp, P(pkm_problem), i32, i32, vp, vp, dbl, P(vp)]),
         "pkm_precond_apply": (C.c_int, [vp, vp, i32, vp, vp]),
         "pkm_precond_diag": (C.c_int, [vp, vp, P(dbl)]),
         "pkm_precond_destroy": (C.c_int, [vp]),
         "pkm_solve": (C.c_int, [vp, P(pkm_problem), vp, i32, vp, vp, P(pkm_solve_opts),
                                 P(pkm_solve_info)]),
+        "pkm_solve_batched": (C.c_int, [vp, i32, P(pkm_problem), P(vp), i32, P(vp), P(vp),
+                                        P(pkm_solve_opts), P(pkm_solve_info)]),
         "pkm_grad_pass": (C.c_int, [vp, P(pkm_problem), i32, vp, vp, P(dbl)]),
         "pkm_lml_grad": (C.c_int, [vp, P(pkm_problem), vp, vp, i32, vp, P(pkm_solve_opts),
                                    P(dbl), vp, P(pkm_solve_info)]),
@@ -112,6 +116,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "pkm_mlp_loss_grad": (C.c_int, [vp, vp, P(pkm_problem), i32, vp, vp, P(dbl),
                                         P(C.c_float)]),
         "pkm_mlp_train_step": (C.c_int, [vp, vp, P(pkm_problem), i32, vp, vp, dbl, P(dbl)]),
+        "pkm_adagrad_step": (C.c_int, [i32, P(dbl), P(dbl), P(dbl), dbl, dbl]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -198,6 +203,15 @@ def pkm_kernel_mvm(ctx, prob: Problem, V, prec=PKM_FP32, Y=None):
     return Y
 
 
+def pkm_kernel_mvm_shift(ctx, prob: Problem, V, shift, prec=PKM_FP32, Y=None):
+    import torch
+    if Y is None:
+        Y = torch.empty_like(V)
+    k = V.shape[1] if V.dim() == 2 else 1
+    _check(load().pkm_kernel_mvm_shift(ctx, prob.ref, k, prec, float(shift), _ptr(V), _ptr(Y)), ctx)
+    return Y
+
+
 def pkm_precond_setup(ctx, prob: Problem, kind, m, idx=None, Phi=None, jitter=0.0):
     out = C.c_void_p()
     _check(load().pkm_precond_setup(ctx, prob.ref, kind, int(m), _ptr(idx, "int32"),
@@ -248,6 +262,10 @@ class SolveInfo:
     @property
     def solve_ms(self):
         return self.struct.solve_ms
+
+    @property
+    def prec_final(self):
+        return self.struct.prec_final
 
 
 def make_opts(tol=1e-6, max_iter=100000, prec=PKM_FP32, reliable_every=25, check_every=1,
@@ -369,3 +387,38 @@ def pkm_mlp_train_step(ctx, net, prob: Problem, Z, KZ, lr):
     _check(load().pkm_mlp_train_step(ctx, net, prob.ref, int(Z.shape[1]), _ptr(Z), _ptr(KZ),
                                      float(lr), C.byref(loss)), ctx)
     return loss.value
+
+
+def pkm_adagrad_step(theta, g, G, eta=1.0, eps=1e-8):
+    """In-place ADAGRAD ascent on float64 numpy arrays theta and G."""
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
+    assert theta.dtype == np.float64 and G.dtype == np.float64
+    assert theta.flags.c_contiguous and G.flags.c_contiguous
+    P = C.POINTER(C.c_double)
+    _check(load().pkm_adagrad_step(int(theta.size), theta.ctypes.data_as(P),
+                                   g.ctypes.data_as(P), G.ctypes.data_as(P), float(eta),
+                                   float(eps)))
+    return theta
+
+
+def pkm_solve_batched(ctx, probs, Bs, pcs=None, Xs=None, opts=None):
+    """probs: list of Problem; Bs: list of (n_b, k) device tensors.
+    Returns (list of X tensors, list of SolveInfo, rc)."""
+    import torch
+    P = len(probs)
+    k = Bs[0].shape[1]
+    Xs = Xs or [torch.zeros_like(b) for b in Bs]
+    arr = (pkm_problem * P)(*[p.struct for p in probs])
+    VP = C.c_void_p * P
+    bptr = VP(*[_ptr(b).value for b in Bs])
+    xptr = VP(*[_ptr(x).value for x in Xs])
+    pcp = VP(*[(pc.value if pc is not None else None) for pc in pcs]) if pcs else None
+    infos = [SolveInfo(k) for _ in range(P)]
+    iarr = (pkm_solve_info * P)(*[i.struct for i in infos])
+    opts = opts or make_opts()
+    rc = load().pkm_solve_batched(ctx, P, arr, pcp, k, bptr, xptr, C.byref(opts), iarr)
+    for i, inf in enumerate(infos):
+        inf.struct = iarr[i]
+        inf.rc = rc
+    _check(rc, ctx, allow=(PKM_OK, PKM_NOT_CONVERGED))
+    return Xs, infos, rc

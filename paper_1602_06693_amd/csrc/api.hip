@@ -13,6 +13,9 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const
                    const double* Phi, double jitter, pkm_precond* pc);
 int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, const double* B,
           double* X, const pkm_solve_opts* o, pkm_solve_info* info);
+int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_precond* const* pcs,
+                  int k, const double* const* B, double* const* X, const pkm_solve_opts* o,
+                  pkm_solve_info* infos);
 void grad_pass(pkm_ctx* ctx, const pkm_problem* prob, int N, const double* AS,
                const double* YZ, double* grad);
 void mlp_create(pkm_ctx* ctx, int d_in, int hidden, int rank, const float* params_host,
@@ -123,6 +126,7 @@ int pkm_destroy(pkm_ctx* ctx) {
         b->release();
     for (auto& b : ctx->pcg) b.release();
     for (auto& b : ctx->ws_setup) b.release();
+    for (auto& b : ctx->batch) b.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -142,6 +146,23 @@ int pkm_kernel_mvm(pkm_ctx* ctx, const pkm_problem* prob, int32_t k, int32_t pre
         PKM_REQUIRE(V != Y, "Y may not alias V");
         prepare(ctx, prob, prec == PKM_FP64, prec != PKM_FP64);
         mvm(ctx, prec, k, V, Y);
+        return PKM_OK;
+    });
+}
+
+int pkm_kernel_mvm_shift(pkm_ctx* ctx, const pkm_problem* prob, int32_t k, int32_t prec,
+                         double shift, const double* V, double* Y) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        validate_problem(prob);
+        PKM_REQUIRE(k >= 1 && k <= 4096, "k must be in [1, 4096]");
+        PKM_REQUIRE(std::isfinite(shift) && shift >= 0.0, "shift must be >= 0");
+        check_prec(prec, prob->d);
+        require_dev(V, "V");
+        require_dev(Y, "Y");
+        PKM_REQUIRE(V != Y, "Y may not alias V");
+        prepare(ctx, prob, prec == PKM_FP64, prec != PKM_FP64);
+        mvm_shift(ctx, prec, k, V, Y, shift);
         return PKM_OK;
     });
 }
@@ -244,6 +265,33 @@ int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int3
             PKM_REQUIRE(pc->device == ctx->device, "preconditioner belongs to another device");
         }
         return solve(ctx, prob, pc, k, B, X, &o, info);
+    });
+}
+
+int pkm_solve_batched(pkm_ctx* ctx, int32_t P, const pkm_problem* probs,
+                      const pkm_precond* const* pcs, int32_t k, const double* const* B,
+                      double* const* X, const pkm_solve_opts* opts, pkm_solve_info* infos) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        PKM_REQUIRE(P >= 1 && P <= 4096, "P must be in [1, 4096]");
+        PKM_REQUIRE(probs != nullptr && B != nullptr && X != nullptr, "NULL argument");
+        pkm_solve_opts o;
+        fill_opts(opts, &o);
+        PKM_REQUIRE(o.prec == PKM_FP32 || o.prec == PKM_FP64,
+                    "batched solve supports FP32 or FP64 products");
+        PKM_REQUIRE(k >= 1 && k <= 33, "batched solve supports 1 <= k <= 33");
+        for (int b = 0; b < P; ++b) {
+            validate_problem(&probs[b]);
+            check_prec(o.prec, probs[b].d);
+            require_dev(B[b], "B[b]");
+            require_dev(X[b], "X[b]");
+            PKM_REQUIRE(B[b] != X[b], "X[b] may not alias B[b]");
+            if (pcs && pcs[b]) {
+                PKM_REQUIRE(pcs[b]->n == probs[b].n, "preconditioner built for another n");
+                PKM_REQUIRE(pcs[b]->device == ctx->device, "preconditioner on another device");
+            }
+        }
+        return solve_batched(ctx, P, probs, pcs, k, B, X, &o, infos);
     });
 }
 
@@ -352,7 +400,7 @@ int pkm_mlp_forward(pkm_ctx* ctx, pkm_mlp* net, const pkm_problem* prob, double*
     return guarded(ctx, [&] {
         require_dev(U, "U");
         mlp_check(ctx, net, prob);
-        mlp_forward(ctx, net, prob->n, ctx->prep.xs64.as<double>(), U);
+        mlp_forward(ctx, net, prob->n, ctx->P().xs64.as<double>(), U);
         return PKM_OK;
     });
 }
@@ -366,7 +414,7 @@ int pkm_mlp_loss_grad(pkm_ctx* ctx, pkm_mlp* net, const pkm_problem* prob, int32
         require_dev(KZ, "KZ");
         PKM_REQUIRE(loss != nullptr, "loss is NULL");
         mlp_check(ctx, net, prob);
-        *loss = mlp_loss_grad(ctx, net, prob->n, ctx->prep.xs64.as<double>(), nz, Z, KZ);
+        *loss = mlp_loss_grad(ctx, net, prob->n, ctx->P().xs64.as<double>(), nz, Z, KZ);
         if (grads) {
             PKM_HIP(hipMemcpyAsync(grads, mlp_grad_ptr(net), sizeof(float) * mlp_nparams(net),
                                    hipMemcpyDeviceToHost, ctx->stream));
@@ -385,10 +433,28 @@ int pkm_mlp_train_step(pkm_ctx* ctx, pkm_mlp* net, const pkm_problem* prob, int3
         require_dev(Z, "Z");
         require_dev(KZ, "KZ");
         mlp_check(ctx, net, prob);
-        double L = mlp_train_step(ctx, net, prob->n, ctx->prep.xs64.as<double>(), nz, Z, KZ, lr);
+        double L = mlp_train_step(ctx, net, prob->n, ctx->P().xs64.as<double>(), nz, Z, KZ, lr);
         if (loss) *loss = L;
         return PKM_OK;
     });
+}
+
+int pkm_adagrad_step(int32_t p, double* theta, const double* g, double* G, double eta,
+                     double eps) {
+    if (p < 1 || !theta || !g || !G || !(eta > 0.0) || !(eps >= 0.0)) {
+        g_last_error = "pkm_adagrad_step: invalid argument";
+        return PKM_ERR_INVALID;
+    }
+    for (int i = 0; i < p; ++i)
+        if (!std::isfinite(g[i])) {
+            g_last_error = "pkm_adagrad_step: non-finite gradient";
+            return PKM_ERR_INVALID;
+        }
+    for (int i = 0; i < p; ++i) {
+        G[i] += g[i] * g[i];
+        theta[i] += eta * g[i] / (std::sqrt(G[i]) + eps);
+    }
+    return PKM_OK;
 }
 
 int pkm_timing_enable(pkm_ctx* ctx, int32_t on) {

@@ -1,0 +1,1098 @@
+// Batched PCG: many independent GP problems (own X, theta, lambda, n, d and
+// preconditioner) solved together, every PCG phase one launch for all of
+// them (Algorithm 1 per problem and per right-hand-side column).
+//
+// Layout: the problems' rows are packed one after another, each padded to a
+// multiple of 256 rows; every FP64 vector (x, r, z, p, K_y p, b) is one
+// packed n_total x k block, and a per-256-row-block table names the problem.
+// Padding rows stay zero throughout.
+//
+// Kernel product: one work-queue launch per input-dimension class (the
+// augmented length fixes the MFMA shape).  Work items are (problem,
+// 256-row block) pairs ordered longest first; every work-group pulls items
+// with an atomic counter until the list is exhausted, so uneven problems
+// balance across the chip and no work-group ever waits on another.
+// Problems whose columns have all converged are skipped.
+//
+// The launch shape (i-tiles per wave) is chosen per class by a small
+// autotuner that times the candidates on the first call and caches the
+// winner in memory and, if PKM_TUNE_CACHE names a file, in that JSON file.
+
+#include "pkm_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <cstring>
+#include <sstream>
+#include <string>
+#include <tuple>
+
+namespace pkm {
+
+struct BDesc {
+    int64_t row0;          // packed row offset
+    int64_t n;             // rows of this problem
+    int64_t tile0;         // row0 / 16
+    int64_t ntiles;        // n_pad / 16 of its own prepared operands
+    const float* jside;
+    const float* iside;
+    const double* psi;     // preconditioner (NULL: none)
+    const double* dinv;
+    int m;
+    int pad;
+    double lambda;
+    int64_t partoff;       // phase-1 partial sums offset (doubles)
+    int64_t toff;          // padded T offset (doubles)
+    int64_t rpc;           // phase-1 rows per chunk
+    int nchunk;
+    int mpad;
+};
+
+struct BCol {
+    double rz, alpha, beta, bnorm, rec, tru, rr;
+    int32_t active, status, parked, restart;
+    int64_t iters;
+};
+
+struct BFlags {
+    int32_t live, pending, broke, pad;
+};
+
+__device__ inline bool bstep(const BCol& s) { return s.active && !s.parked; }
+
+// ---------------------------------------------------------------------------
+// work-queue FP32 kernel product (same inner loop as the single-problem one)
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int S4, int KT, int KR, int U>
+__global__ __launch_bounds__(256) void k_bmvm_f32(const BDesc* __restrict__ desc,
+                                                  const int2* __restrict__ items, int nitems,
+                                                  int* __restrict__ counter,
+                                                  const int* __restrict__ live,
+                                                  const int* __restrict__ use64,
+                                                  const float* __restrict__ vs,
+                                                  float* __restrict__ yout) {
+    constexpr int KP = 16 * KT + KR;
+    __shared__ int sh_item;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) sh_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = sh_item;
+        if (it >= nitems) return;
+        const int2 item = items[it];
+        if (!live[item.x] || use64[item.x]) continue;
+        const BDesc D = desc[item.x];
+        const int64_t itile0 = (int64_t(item.y) * 4 + wave) * U;   // local tile
+        float bi[U][S4];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int s = 0; s < S4; ++s) bi[u][s] = D.iside[((itile0 + u) * 64 + lane) * S4 + s];
+        f32x4 acc[U][KT > 0 ? KT : 1];
+        float racc[U][KR > 0 ? KR : 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int q = 0; q < (KT > 0 ? KT : 1); ++q) acc[u][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int e = 0; e < (KR > 0 ? KR : 1); ++e) racc[u][e] = 0.f;
+        }
+        for (int64_t t = 0; t < D.ntiles; ++t) {
+            float aj[S4];
+#pragma unroll
+            for (int s = 0; s < S4; ++s) aj[s] = D.jside[(t * 64 + lane) * S4 + s];
+            const float* vt = vs + (D.tile0 + t) * 16 * KP;
+            f32x4 vv[KT > 0 ? KT : 1];
+#pragma unroll
+            for (int q = 0; q < KT; ++q) vv[q] = *reinterpret_cast<const f32x4*>(vt + q * 256 + lane * 4);
+            f32x4 yr[KR > 0 ? KR : 1];
+#pragma unroll
+            for (int e = 0; e < KR; ++e)
+                yr[e] = *reinterpret_cast<const f32x4*>(vt + KT * 256 + e * 16 + g * 4);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                f32x4 st = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < S4; ++s)
+                    st = __builtin_amdgcn_mfma_f32_16x16x4f32(aj[s], bi[u][s], st, 0, 0, 0);
+                float kv[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) kv[r] = __builtin_amdgcn_exp2f(st[r]);
+#pragma unroll
+                for (int q = 0; q < KT; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        acc[u][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[r], vv[q][r], acc[u][q], 0, 0, 0);
+#pragma unroll
+                for (int e = 0; e < KR; ++e)
+                    racc[u][e] += kv[0] * yr[e][0] + kv[1] * yr[e][1] + kv[2] * yr[e][2] + kv[3] * yr[e][3];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t row0 = D.row0 + (itile0 + u) * 16;
+#pragma unroll
+            for (int q = 0; q < KT; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    yout[(row0 + 4 * g + r) * KP + 16 * q + (lane & 15)] = acc[u][q][r];
+#pragma unroll
+            for (int e = 0; e < KR; ++e) {
+                float v = racc[u][e];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                if (g == 0) yout[(row0 + (lane & 15)) * KP + 16 * KT + e] = v;
+            }
+        }
+    }
+}
+
+// p (packed FP64, n_total x k) -> MFMA lane-order tiles (global tile index)
+__global__ void k_bpack_v32(const double* __restrict__ V, int64_t ntot, int k, int KT, int KR,
+                            float* __restrict__ vs) {
+    const int KP = 16 * KT + KR;
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int64_t tot = (ntot / 16) * 16 * KP;
+    if (e >= tot) return;
+    int64_t t = e / (16 * KP);
+    int w = int(e - t * 16 * KP);
+    int64_t row;
+    int col;
+    if (w < KT * 256) {
+        int q = w >> 8, rem = w & 255;
+        int l = rem >> 2, r = rem & 3;
+        row = 16 * t + 4 * (l >> 4) + r;
+        col = 16 * q + (l & 15);
+    } else {
+        int w2 = w - KT * 256;
+        row = 16 * t + (w2 & 15);
+        col = 16 * KT + (w2 >> 4);
+    }
+    vs[e] = col < k ? float(V[row * k + col]) : 0.f;
+}
+
+// Ap = y32 + lambda_b p on valid rows (padding rows stay zero)
+__global__ void k_bfinish32(const float* __restrict__ y, int kp, int64_t ntot, int k,
+                            const int* __restrict__ rbprob, const BDesc* __restrict__ desc,
+                            const double* __restrict__ p, double* __restrict__ Ap) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= ntot * k) return;
+    const int64_t row = e / k;
+    const int c = int(e - row * k);
+    const BDesc& D = desc[rbprob[row >> 8]];
+    Ap[e] = (row - D.row0 < D.n) ? double(y[row * kp + c]) + D.lambda * p[e] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// per-problem reductions and recurrences
+// ---------------------------------------------------------------------------
+// part[rb][c] = sum over the 256 rows of row-block rb of u o v (k <= 256)
+__global__ __launch_bounds__(256) void k_bdot_part(const double* __restrict__ u,
+                                                   const double* __restrict__ v, int k,
+                                                   double* __restrict__ part) {
+    __shared__ double sh[256];
+    const int per = 256 / k;
+    const int T = per * k;
+    const int64_t beg = int64_t(blockIdx.x) * 256 * k, end = beg + int64_t(256) * k;
+    double acc = 0.0;
+    if (threadIdx.x < T)
+        for (int64_t e = beg + threadIdx.x; e < end; e += T) acc = fma(u[e], v[e], acc);
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double s = 0.0;
+        for (int q = 0; q < per; ++q) s += sh[threadIdx.x + q * k];
+        part[int64_t(blockIdx.x) * k + threadIdx.x] = s;
+    }
+}
+
+__device__ inline double bsum(const double* part, const int* rbrange, int b, int k, int c) {
+    double s = 0.0;
+    for (int rb = rbrange[b]; rb < rbrange[b + 1]; ++rb) s += part[int64_t(rb) * k + c];
+    return s;
+}
+
+__global__ void k_binit(const double* __restrict__ pbb, const double* __restrict__ prz,
+                        const int* __restrict__ rbrange, int P, int k, BCol* __restrict__ st) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * k) return;
+    const int b = e / k, c = e - b * k;
+    const double bb = bsum(pbb, rbrange, b, k, c);
+    BCol s{};
+    s.bnorm = sqrt(bb);
+    s.rz = bsum(prz, rbrange, b, k, c);
+    s.active = bb > 0.0 ? 1 : 0;
+    s.status = PKM_COL_CONVERGED;
+    s.rec = s.tru = bb > 0.0 ? 1.0 : 0.0;
+    if (!isfinite(bb) || !isfinite(s.rz) || (s.active && !(s.rz > 0.0))) {
+        s.active = 0;
+        s.status = PKM_COL_BREAKDOWN;
+    }
+    st[e] = s;
+}
+
+__global__ void k_balpha(const double* __restrict__ ppap, const int* __restrict__ rbrange, int P,
+                         int k, BCol* __restrict__ st) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * k) return;
+    const int b = e / k, c = e - b * k;
+    BCol s = st[e];
+    if (bstep(s)) {
+        const double pap = bsum(ppap, rbrange, b, k, c);
+        if (!(pap > 0.0) || !isfinite(pap)) {
+            s.active = 0;
+            s.status = PKM_COL_BREAKDOWN;
+            s.alpha = 0.0;
+        } else {
+            s.alpha = s.rz / pap;
+            s.iters += 1;
+        }
+    } else {
+        s.alpha = 0.0;
+    }
+    st[e] = s;
+}
+
+__device__ inline const BCol& col_of(const BCol* st, const int* rbprob, int64_t e, int k) {
+    const int64_t row = e / k;
+    return st[int64_t(rbprob[row >> 8]) * k + (e - row * k)];
+}
+
+__global__ void k_bupdate_xr(int64_t tot, int k, const int* __restrict__ rbprob,
+                             const BCol* __restrict__ st, const double* __restrict__ p,
+                             const double* __restrict__ Ap, double* __restrict__ x,
+                             double* __restrict__ r) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= tot) return;
+    const double a = col_of(st, rbprob, e, k).alpha;
+    if (a != 0.0) {
+        x[e] = fma(a, p[e], x[e]);
+        r[e] = fma(-a, Ap[e], r[e]);
+    }
+}
+
+__global__ void k_brr(const double* __restrict__ prr, const int* __restrict__ rbrange, int P,
+                      int k, double tol, BCol* __restrict__ st, BFlags* __restrict__ fl,
+                      int* __restrict__ live_prob, int* __restrict__ broke_prob) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * k) return;
+    const int b = e / k, c = e - b * k;
+    BCol s = st[e];
+    const double rr = bsum(prr, rbrange, b, k, c);
+    s.rr = rr;
+    s.rec = s.bnorm > 0.0 ? sqrt(rr) / s.bnorm : 0.0;
+    if (s.active && !isfinite(rr)) {
+        s.active = 0;
+        s.status = PKM_COL_BREAKDOWN;
+    }
+    if (bstep(s) && s.rec <= tol) s.parked = 1;
+    if (s.active) {
+        atomicAdd(&fl->live, 1);
+        if (!s.parked) {
+            atomicAdd(&fl->pending, 1);
+            atomicOr(&live_prob[b], 1);
+        }
+    }
+    if (s.status == PKM_COL_BREAKDOWN) {
+        atomicAdd(&fl->broke, 1);
+        atomicAdd(&broke_prob[b], 1);
+    }
+    st[e] = s;
+}
+
+__global__ void k_btrue_res(int64_t tot, int k, const int* __restrict__ rbprob,
+                            const BCol* __restrict__ st, const double* __restrict__ b,
+                            const double* __restrict__ Ax, double* __restrict__ r) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= tot) return;
+    if (col_of(st, rbprob, e, k).active) r[e] = b[e] - Ax[e];
+}
+
+__global__ void k_btrue_final(const double* __restrict__ prr, const int* __restrict__ rbrange,
+                              int P, int k, double tol, BCol* __restrict__ st,
+                              BFlags* __restrict__ fl, int* __restrict__ live_prob,
+                              int* __restrict__ broke_prob,
+                              unsigned long long* __restrict__ maxtru_bits) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * k) return;
+    const int b = e / k, c = e - b * k;
+    BCol s = st[e];
+    if (s.active) {
+        const double rr = bsum(prr, rbrange, b, k, c);
+        s.rr = rr;
+        s.tru = s.rec = s.bnorm > 0.0 ? sqrt(rr) / s.bnorm : 0.0;
+        if (!isfinite(rr)) {
+            s.active = 0;
+            s.status = PKM_COL_BREAKDOWN;
+        } else if (s.tru <= tol) {
+            s.active = 0;
+            s.status = PKM_COL_CONVERGED;
+        }
+        s.parked = 0;
+    }
+    if (s.active) {
+        atomicAdd(&fl->live, 1);
+        atomicAdd(&fl->pending, 1);
+        atomicOr(&live_prob[b], 1);
+        // non-negative doubles order like their bit patterns
+        atomicMax(&maxtru_bits[b], (unsigned long long)__double_as_longlong(s.tru));
+    }
+    if (s.status == PKM_COL_BREAKDOWN) {
+        atomicAdd(&fl->broke, 1);
+        atomicAdd(&broke_prob[b], 1);
+    }
+    st[e] = s;
+}
+
+// problems marked in esc: broken columns resume; active columns restart (beta = 0)
+__global__ void k_breactivate(int P, int k, const int* __restrict__ esc, BCol* __restrict__ st) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * k || !esc[e / k]) return;
+    BCol s = st[e];
+    if (s.status == PKM_COL_BREAKDOWN) {
+        s.active = 1;
+        s.status = PKM_COL_CONVERGED;
+        s.parked = 0;
+    }
+    if (s.active) s.restart = 1;
+    st[e] = s;
+}
+
+__global__ void k_bbeta(const double* __restrict__ prz, const int* __restrict__ rbrange, int P,
+                        int k, BCol* __restrict__ st) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * k) return;
+    const int b = e / k, c = e - b * k;
+    BCol s = st[e];
+    if (bstep(s)) {
+        const double rz = bsum(prz, rbrange, b, k, c);
+        if (rz < 0.0 || !isfinite(rz)) {
+            s.active = 0;
+            s.status = PKM_COL_BREAKDOWN;
+            s.beta = 0.0;
+        } else {
+            s.beta = (s.rz > 0.0 && !s.restart) ? rz / s.rz : 0.0;
+            s.rz = rz;
+            s.restart = 0;
+        }
+    } else {
+        s.beta = 0.0;
+    }
+    st[e] = s;
+}
+
+__global__ void k_bupdate_p(int64_t tot, int k, const int* __restrict__ rbprob,
+                            const BCol* __restrict__ st, const double* __restrict__ z,
+                            double* __restrict__ p) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= tot) return;
+    const BCol& s = col_of(st, rbprob, e, k);
+    if (bstep(s)) p[e] = fma(s.beta, p[e], z[e]);
+}
+
+__global__ void k_bmark_maxiter(int P, int k, BCol* __restrict__ st) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < P * k && st[e].active) {
+        st[e].active = 0;
+        st[e].status = PKM_COL_MAX_ITER;
+    }
+}
+
+__global__ void k_breport(const double* __restrict__ prr, const int* __restrict__ rbrange, int P,
+                          int k, BCol* __restrict__ st) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * k) return;
+    const int b = e / k, c = e - b * k;
+    const double rr = bsum(prr, rbrange, b, k, c);
+    st[e].tru = st[e].bnorm > 0.0 ? sqrt(rr) / st[e].bnorm : 0.0;
+}
+
+__global__ void k_bsub(int64_t tot, const double* __restrict__ a, const double* __restrict__ b,
+                       double* __restrict__ out) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e < tot) out[e] = a[e] - b[e];
+}
+
+// ---------------------------------------------------------------------------
+// batched Woodbury apply: Z = D^-1 R - Psi (Psi^T R) per problem
+// ---------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// items: (problem, 64-column block of Psi, row chunk)
+template <int KT>
+__global__ __launch_bounds__(256) void k_bpsit_r(const BDesc* __restrict__ desc,
+                                                 const int4* __restrict__ items,
+                                                 const int* __restrict__ live,
+                                                 const double* __restrict__ R, int k,
+                                                 double* __restrict__ part) {
+    const int4 item = items[blockIdx.x];
+    if (!live[item.x]) return;
+    const BDesc D = desc[item.x];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, cc = lane & 15;
+    const int j0 = (item.y * 4 + w) * 16;
+    if (j0 >= D.m) return;
+    const int m = D.m;
+    const int64_t i0 = int64_t(item.z) * D.rpc;
+    const int64_t i1 = min(D.n, i0 + D.rpc);
+    const int jj = j0 + cc;
+    const bool jv = jj < m;
+    f64x4 acc[KT];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) acc[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t ib = i0; ib < i1; ib += 16) {
+        double a[4], bb[4][KT];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = ib + 4 * g + q;
+            const bool iv = i < i1;
+            a[q] = (iv && jv) ? D.psi[i * m + jj] : 0.0;
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) {
+                const int c = 16 * kt + cc;
+                bb[q][kt] = (iv && c < k) ? R[(D.row0 + i) * k + c] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+                acc[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], bb[q][kt], acc[kt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = j0 + g + 4 * r;
+            const int c = 16 * kt + cc;
+            if (j < m && c < k) part[D.partoff + (int64_t(item.z) * m + j) * k + c] = acc[kt][r];
+        }
+}
+
+// items: (problem, 64-output block of its padded T)
+__global__ __launch_bounds__(256) void k_bsum_chunks(const BDesc* __restrict__ desc,
+                                                     const int4* __restrict__ items,
+                                                     const int* __restrict__ live,
+                                                     const double* __restrict__ part, int k,
+                                                     int ldt, double* __restrict__ T) {
+    __shared__ double sh[4][64];
+    const int4 item = items[blockIdx.x];
+    const BDesc D = desc[item.x];
+    const bool lv = live[item.x] != 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t e = int64_t(item.y) * 64 + lane;
+    const bool ev = lv && e < int64_t(D.mpad) * ldt;
+    const int j = ev ? int(e / ldt) : 0, c = ev ? int(e % ldt) : 0;
+    double s = 0.0;
+    if (ev && j < D.m && c < k)
+        for (int q = w; q < D.nchunk; q += 4) s += part[D.partoff + (int64_t(q) * D.m + j) * k + c];
+    sh[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && ev) T[D.toff + e] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+}
+
+// items: (problem, 64-row block); problems without a preconditioner copy R.
+template <int KT>
+__global__ __launch_bounds__(256) void k_bapply_z(const BDesc* __restrict__ desc,
+                                                  const int4* __restrict__ items,
+                                                  const int* __restrict__ live,
+                                                  const double* __restrict__ T, int ldt,
+                                                  const double* __restrict__ R, int k,
+                                                  double* __restrict__ Z) {
+    const int4 item = items[blockIdx.x];
+    if (!live[item.x]) return;
+    const BDesc D = desc[item.x];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, rr = lane & 15;
+    const int64_t lrow0 = (int64_t(item.y) * 4 + w) * 16;
+    if (lrow0 >= D.n) return;
+    if (D.psi == nullptr) {
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = lrow0 + g + 4 * q;
+            if (i < D.n)
+                for (int c = rr; c < k; c += 16) Z[(D.row0 + i) * k + c] = R[(D.row0 + i) * k + c];
+        }
+        return;
+    }
+    const int m = D.m;
+    const int64_t row = lrow0 + rr;
+    const bool rv = row < D.n;
+    const double* prow = D.psi + (rv ? row : 0) * m;
+    const double* Tb = T + D.toff;
+    f64x4 acc[KT];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) acc[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int m0 = 0; m0 < m; m0 += 16) {
+        double a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int mm = m0 + 4 * g + q;
+            a[q] = (rv && mm < m) ? prow[mm] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double* trow = Tb + int64_t(m0 + 4 * g + q) * ldt + rr;
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+                acc[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], trow[16 * kt], acc[kt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = lrow0 + g + 4 * r;
+            const int c = 16 * kt + rr;
+            if (i < D.n && c < k) {
+                const int64_t e = (D.row0 + i) * k + c;
+                Z[e] = D.dinv[i] * R[e] - acc[kt][r];
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct TuneKey {
+    int s4, kt, kr;
+    int64_t work_bucket;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(s4, kt, kr, work_bucket) < std::tie(o.s4, o.kt, o.kr, o.work_bucket);
+    }
+};
+
+static std::map<TuneKey, int> g_tune;   // key -> i-tiles per wave (U)
+static bool g_tune_loaded = false;
+
+static void tune_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("PKM_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        TuneKey k{};
+        int u = 0;
+        long long wb = 0;
+        if (std::sscanf(line.c_str(), " {\"s4\": %d, \"kt\": %d, \"kr\": %d, \"work\": %lld, \"u\": %d",
+                        &k.s4, &k.kt, &k.kr, &wb, &u) == 5) {
+            k.work_bucket = wb;
+            g_tune[k] = u;
+        }
+    }
+}
+
+static void tune_save() {
+    const char* path = std::getenv("PKM_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path);
+    for (auto& kv : g_tune)
+        f << "{\"s4\": " << kv.first.s4 << ", \"kt\": " << kv.first.kt << ", \"kr\": " << kv.first.kr
+          << ", \"work\": " << kv.first.work_bucket << ", \"u\": " << kv.second << "}\n";
+}
+
+template <int S4, int KT, int KR>
+static void launch_bmvm_u(int U, int grid, hipStream_t s, const BDesc* desc, const int2* items,
+                          int nitems, int* counter, const int* live, const int* use64,
+                          const float* vs, float* y) {
+    if (U == 4)
+        k_bmvm_f32<S4, KT, KR, 4><<<grid, 256, 0, s>>>(desc, items, nitems, counter, live, use64, vs, y);
+    else if (U == 2)
+        k_bmvm_f32<S4, KT, KR, 2><<<grid, 256, 0, s>>>(desc, items, nitems, counter, live, use64, vs, y);
+    else
+        k_bmvm_f32<S4, KT, KR, 1><<<grid, 256, 0, s>>>(desc, items, nitems, counter, live, use64, vs, y);
+}
+
+template <int S4>
+static void launch_bmvm_s(int KT, int KR, int U, int grid, hipStream_t s, const BDesc* desc,
+                          const int2* items, int nitems, int* counter, const int* live,
+                          const int* use64, const float* vs, float* y) {
+#define PKM_BB(kt, kr)                                                                         \
+    if (KT == kt && KR == kr) {                                                                \
+        launch_bmvm_u<S4, kt, kr>(U, grid, s, desc, items, nitems, counter, live, use64, vs, y); \
+        return;                                                                                \
+    }
+    PKM_BB(0, 1) PKM_BB(1, 0) PKM_BB(1, 1) PKM_BB(2, 0) PKM_BB(2, 1)
+#undef PKM_BB
+    fail(PKM_ERR_UNSUPPORTED, "batched product: k must be <= 33");
+}
+
+static void launch_bmvm(int S4, int KT, int KR, int U, int grid, hipStream_t s, const BDesc* desc,
+                        const int2* items, int nitems, int* counter, const int* live,
+                        const int* use64, const float* vs, float* y) {
+    switch (S4) {
+        case 1: launch_bmvm_s<1>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
+        case 2: launch_bmvm_s<2>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
+        case 3: launch_bmvm_s<3>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
+        case 4: launch_bmvm_s<4>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
+        case 5: launch_bmvm_s<5>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
+        case 6: launch_bmvm_s<6>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
+        case 7: launch_bmvm_s<7>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
+        case 8: launch_bmvm_s<8>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
+        case 9: launch_bmvm_s<9>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
+        default: fail(PKM_ERR_UNSUPPORTED, "batched product: d must be <= 34");
+    }
+}
+
+struct ClassPlan {
+    int s4;
+    std::vector<int> probs;
+    int U = 4;
+    int64_t work = 0;           // sum of n_pad^2 / 256
+    DevBuf items;               // int2 per U
+    int nitems = 0;
+};
+
+int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_precond* const* pcs,
+                  int k, const double* const* B, double* const* X, const pkm_solve_opts* o,
+                  pkm_solve_info* infos) {
+    hipStream_t s = ctx->stream;
+    auto t_start = std::chrono::steady_clock::now();
+    const int prec = o->prec;
+    PKM_REQUIRE(prec == PKM_FP32 || prec == PKM_FP64, "batched solve supports FP32 or FP64 products");
+    PKM_REQUIRE(k >= 1 && k <= 33, "batched solve supports 1 <= k <= 33");
+    tune_load();
+
+    // per-problem prepared operands and packed layout (released on every exit)
+    struct Preps {
+        pkm_ctx* ctx;
+        std::vector<Prepared> v;
+        ~Preps() {
+            ctx->active = &ctx->prep;
+            for (auto& q : v) {
+                q.xs64.release();
+                q.jside.release();
+                q.iside.release();
+                q.jsb.release();
+                q.isb.release();
+            }
+        }
+    } holder{ctx, std::vector<Prepared>(P)};
+    std::vector<Prepared>& preps = holder.v;
+    std::vector<BDesc> hd(P);
+    std::vector<int64_t> row0(P + 1, 0);
+    for (int b = 0; b < P; ++b) {
+        ctx->active = &preps[b];
+        prepare(ctx, &probs[b], true, prec == PKM_FP32);
+        ctx->active = &ctx->prep;
+        row0[b + 1] = row0[b] + round_up(probs[b].n, 256);
+    }
+    const int64_t ntot = row0[P];
+    const int nrb = int(ntot / 256);
+    std::vector<int> rbprob(nrb), rbrange(P + 1);
+    for (int b = 0; b < P; ++b) {
+        rbrange[b] = int(row0[b] / 256);
+        for (int64_t rb = row0[b] / 256; rb < row0[b + 1] / 256; ++rb) rbprob[rb] = b;
+    }
+    rbrange[P] = nrb;
+    // preconditioner partial-sum layout
+    int KT = k / 16, KR = k % 16;
+    if (KR > 1) {
+        KT += 1;
+        KR = 0;
+    }
+    const int KP = 16 * KT + KR;
+    const int KTa = int(cdiv(k, 16));   // apply column tiles
+    const int ldt = 16 * KTa;
+    int64_t partoff = 0, toff = 0;
+    std::vector<int4> it1, itS, it2;
+    for (int b = 0; b < P; ++b) {
+        BDesc& D = hd[b];
+        D.row0 = row0[b];
+        D.n = probs[b].n;
+        D.tile0 = row0[b] / 16;
+        D.ntiles = preps[b].n_pad / 16;
+        D.jside = preps[b].jside.as<float>();
+        D.iside = preps[b].iside.as<float>();
+        D.lambda = probs[b].lambda;
+        const pkm_precond* pc = pcs ? pcs[b] : nullptr;
+        D.psi = pc ? pc->psi.as<double>() : nullptr;
+        D.dinv = pc ? pc->dinv.as<double>() : nullptr;
+        D.m = pc ? pc->m : 0;
+        if (pc) {
+            PKM_REQUIRE(pc->n == probs[b].n, "batched: preconditioner built for another n");
+            const int mt = int(cdiv(D.m, 64));
+            int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(cdiv(D.n, 256), 64));
+            D.rpc = round_up(cdiv(D.n, nchunk), 16);
+            D.nchunk = int(cdiv(D.n, D.rpc));
+            D.mpad = int(round_up(D.m, 16));
+            D.partoff = partoff;
+            D.toff = toff;
+            partoff += int64_t(D.nchunk) * D.m * k;
+            toff += int64_t(D.mpad) * ldt;
+            for (int y = 0; y < mt; ++y)
+                for (int z = 0; z < D.nchunk; ++z) it1.push_back({b, y, z, 0});
+            for (int y = 0; y < int(cdiv(int64_t(D.mpad) * ldt, 64)); ++y) itS.push_back({b, y, 0, 0});
+        }
+        for (int y = 0; y < int(cdiv(D.n, 64)); ++y) it2.push_back({b, y, 0, 0});
+    }
+    // product work lists per dimension class, longest items first
+    std::map<int, ClassPlan> classes;
+    if (prec == PKM_FP32)
+        for (int b = 0; b < P; ++b) {
+            ClassPlan& cp = classes[preps[b].d4 / 4];
+            cp.s4 = preps[b].d4 / 4;
+            cp.probs.push_back(b);
+            cp.work += preps[b].n_pad * preps[b].n_pad / 256;
+        }
+
+    // device buffers (batch workspace)
+    auto& W = ctx->batch;
+    W[0].ensure(sizeof(BDesc) * P);
+    W[1].ensure(sizeof(int) * (nrb + P + 1));
+    const size_t vec = sizeof(double) * ntot * k;
+    for (int i = 2; i < 8; ++i) W[i].ensure(vec);   // b, x, r, z, p, Ap
+    W[8].ensure(vec);                                  // tmp
+    W[9].ensure(sizeof(double) * int64_t(nrb) * k * 2);
+    W[10].ensure(sizeof(BCol) * P * k + sizeof(BFlags) + 64);
+    W[11].ensure(sizeof(int) * (4 * P + 64) + sizeof(unsigned long long) * P);   // per-problem flags
+    W[12].ensure(sizeof(int4) * (it1.size() + itS.size() + it2.size() + 3));
+    W[13].ensure(sizeof(double) * std::max<int64_t>(partoff + toff, 1));
+    W[14].ensure(sizeof(float) * (ntot / 16) * 16 * KP + 64);
+    W[15].ensure(sizeof(float) * ntot * KP + 64);
+    BDesc* d_desc = W[0].as<BDesc>();
+    int* d_rbprob = W[1].as<int>();
+    int* d_rbrange = d_rbprob + nrb;
+    double* bb = W[2].as<double>();
+    double* x = W[3].as<double>();
+    double* r = W[4].as<double>();
+    double* z = W[5].as<double>();
+    double* p = W[6].as<double>();
+    double* Ap = W[7].as<double>();
+    double* tmp = W[8].as<double>();
+    double* partA = W[9].as<double>();
+    double* partB = partA + int64_t(nrb) * k;
+    BCol* st = W[10].as<BCol>();
+    BFlags* fl = reinterpret_cast<BFlags*>(st + P * k);
+    int* live = W[11].as<int>();
+    int* counter = live + P;              // 16 ints reserved
+    int* use64d = counter + 16;           // P: problem runs on FP64 products
+    int* esc = use64d + P;                // P: problem escalates now
+    int* brokep = esc + P;                // P: broken columns per problem
+    unsigned long long* maxtru = reinterpret_cast<unsigned long long*>(
+        W[11].as<char>() + round_up(sizeof(int) * (4 * P + 64), 8));
+    int4* d_it1 = W[12].as<int4>();
+    int4* d_itS = d_it1 + it1.size();
+    int4* d_it2 = d_itS + itS.size();
+    double* part = W[13].as<double>();
+    double* Tpad = part + partoff;
+    float* vs = W[14].as<float>();
+    float* y32 = W[15].as<float>();
+    PKM_HIP(hipMemcpyAsync(d_desc, hd.data(), sizeof(BDesc) * P, hipMemcpyHostToDevice, s));
+    PKM_HIP(hipMemcpyAsync(d_rbprob, rbprob.data(), sizeof(int) * nrb, hipMemcpyHostToDevice, s));
+    PKM_HIP(hipMemcpyAsync(d_rbrange, rbrange.data(), sizeof(int) * (P + 1), hipMemcpyHostToDevice, s));
+    if (!it1.empty()) PKM_HIP(hipMemcpyAsync(d_it1, it1.data(), sizeof(int4) * it1.size(), hipMemcpyHostToDevice, s));
+    if (!itS.empty()) PKM_HIP(hipMemcpyAsync(d_itS, itS.data(), sizeof(int4) * itS.size(), hipMemcpyHostToDevice, s));
+    PKM_HIP(hipMemcpyAsync(d_it2, it2.data(), sizeof(int4) * it2.size(), hipMemcpyHostToDevice, s));
+    // pack b, x0 = 0
+    for (int i = 2; i < 9; ++i) PKM_HIP(hipMemsetAsync(W[i].p, 0, vec, s));
+    for (int b = 0; b < P; ++b)
+        PKM_HIP(hipMemcpyAsync(bb + row0[b] * k, B[b], sizeof(double) * probs[b].n * k,
+                               hipMemcpyDeviceToDevice, s));
+    const int64_t tot = ntot * k;
+    const unsigned gb = unsigned(cdiv(tot, 256));
+    const unsigned gpk = unsigned(cdiv(int64_t(P) * k, 256));
+    BFlags* hfl = static_cast<BFlags*>(ctx->pinned);
+
+    auto dots = [&](const double* u, const double* v, double* out) {
+        k_bdot_part<<<nrb, 256, 0, s>>>(u, v, k, out);
+        PKM_CHECK_LAUNCH();
+    };
+    auto reset_flags = [&]() {
+        PKM_HIP(hipMemsetAsync(fl, 0, sizeof(BFlags), s));
+        PKM_HIP(hipMemsetAsync(live, 0, sizeof(int) * P, s));
+    };
+    auto poll = [&]() {
+        PKM_HIP(hipMemcpyAsync(hfl, fl, sizeof(BFlags), hipMemcpyDeviceToHost, s));
+        PKM_HIP(hipStreamSynchronize(s));
+        return *hfl;
+    };
+    auto apply = [&](const double* R, double* Zo) {
+        if (!it1.empty()) {
+            switch (KTa) {
+                case 1: k_bpsit_r<1><<<unsigned(it1.size()), 256, 0, s>>>(d_desc, d_it1, live, R, k, part); break;
+                case 2: k_bpsit_r<2><<<unsigned(it1.size()), 256, 0, s>>>(d_desc, d_it1, live, R, k, part); break;
+                default: k_bpsit_r<3><<<unsigned(it1.size()), 256, 0, s>>>(d_desc, d_it1, live, R, k, part); break;
+            }
+            PKM_CHECK_LAUNCH();
+            k_bsum_chunks<<<unsigned(itS.size()), 256, 0, s>>>(d_desc, d_itS, live, part, k, ldt, Tpad);
+            PKM_CHECK_LAUNCH();
+        }
+        switch (KTa) {
+            case 1: k_bapply_z<1><<<unsigned(it2.size()), 256, 0, s>>>(d_desc, d_it2, live, Tpad, ldt, R, k, Zo); break;
+            case 2: k_bapply_z<2><<<unsigned(it2.size()), 256, 0, s>>>(d_desc, d_it2, live, Tpad, ldt, R, k, Zo); break;
+            default: k_bapply_z<3><<<unsigned(it2.size()), 256, 0, s>>>(d_desc, d_it2, live, Tpad, ldt, R, k, Zo); break;
+        }
+        PKM_CHECK_LAUNCH();
+    };
+    auto product64 = [&](const double* V, double* Y) {   // Y = K_y V per problem, FP64
+        for (int b = 0; b < P; ++b) {
+            ctx->active = &preps[b];
+            mvm(ctx, PKM_FP64, k, V + row0[b] * k, Y + row0[b] * k);
+            ctx->active = &ctx->prep;
+        }
+    };
+    const int grid_q = 256 * 4;   // work-queue work-groups (exit when the list is exhausted)
+    std::vector<int> use64(P, prec == PKM_FP64 ? 1 : 0);
+    PKM_HIP(hipMemcpyAsync(use64d, use64.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
+    PKM_HIP(hipMemsetAsync(brokep, 0, sizeof(int) * P, s));
+    // build the product item lists, tuned per class
+    for (auto& kv : classes) {
+        ClassPlan& cp = kv.second;
+        int64_t wb = 1;
+        while (wb < cp.work) wb <<= 1;
+        TuneKey key{cp.s4, KT, KR, wb};
+        auto build = [&](int U) {
+            std::vector<std::pair<int64_t, int2>> v;
+            for (int b : cp.probs) {
+                const int64_t rows_wg = 64 * U;
+                const int nblk = int(cdiv(preps[b].n_pad, rows_wg));
+                for (int y = 0; y < nblk; ++y) v.push_back({preps[b].n_pad, int2{b, y}});
+            }
+            std::stable_sort(v.begin(), v.end(), [](auto& a, auto& c) { return a.first > c.first; });
+            std::vector<int2> items(v.size());
+            for (size_t i = 0; i < v.size(); ++i) items[i] = v[i].second;
+            return items;
+        };
+        auto run = [&](int U, const std::vector<int2>& items) {
+            cp.items.ensure(sizeof(int2) * items.size());
+            PKM_HIP(hipMemcpyAsync(cp.items.p, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
+            PKM_HIP(hipMemsetAsync(counter, 0, sizeof(int), s));
+            launch_bmvm(cp.s4, KT, KR, U, grid_q, s, d_desc, cp.items.as<int2>(), int(items.size()),
+                        counter, live, use64d, vs, y32);
+            PKM_CHECK_LAUNCH();
+        };
+        auto found = g_tune.find(key);
+        if (found == g_tune.end()) {
+            // time U = 1, 2, 4 once on this batch (all problems live, p = 0)
+            std::vector<int> ones(P, 1);
+            PKM_HIP(hipMemcpyAsync(live, ones.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
+            float best_ms = 1e30f;
+            int best_u = 4;
+            for (int U : {1, 2, 4}) {
+                auto items = build(U);
+                run(U, items);   // warm
+                PKM_HIP(hipEventRecord(ctx->ev0, s));
+                run(U, items);
+                PKM_HIP(hipEventRecord(ctx->ev1, s));
+                PKM_HIP(hipEventSynchronize(ctx->ev1));
+                float ms = 0.f;
+                PKM_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_u = U;
+                }
+            }
+            g_tune[key] = best_u;
+            tune_save();
+        }
+        cp.U = g_tune[key];
+        auto items = build(cp.U);
+        cp.nitems = int(items.size());
+        cp.items.ensure(sizeof(int2) * items.size());
+        PKM_HIP(hipMemcpyAsync(cp.items.p, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
+    }
+    auto product = [&](const double* V, double* Y) {
+        if (prec == PKM_FP64) {
+            product64(V, Y);
+            return;
+        }
+        k_bpack_v32<<<cdiv((ntot / 16) * 16 * KP, 256), 256, 0, s>>>(V, ntot, k, KT, KR, vs);
+        PKM_CHECK_LAUNCH();
+        if (ctx->timing) PKM_HIP(hipEventRecord(ctx->ev0, s));
+        for (auto& kv : classes) {
+            ClassPlan& cp = kv.second;
+            PKM_HIP(hipMemsetAsync(counter, 0, sizeof(int), s));
+            launch_bmvm(cp.s4, KT, KR, cp.U, grid_q, s, d_desc, cp.items.as<int2>(), cp.nitems,
+                        counter, live, use64d, vs, y32);
+            PKM_CHECK_LAUNCH();
+        }
+        if (ctx->timing) {
+            PKM_HIP(hipEventRecord(ctx->ev1, s));
+            PKM_HIP(hipEventSynchronize(ctx->ev1));
+            float ms = 0.f;
+            PKM_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+            MvmStats& stt = ctx->stats[PKM_FP32];
+            stt.launches += 1;
+            stt.ms += ms;
+            for (int b = 0; b < P; ++b) {
+                const double pr = double(probs[b].n) * double(probs[b].n);
+                stt.pairs += pr;
+                stt.flops += pr * (2.0 * probs[b].d + 2.0 * k);
+            }
+        }
+        k_bfinish32<<<gb, 256, 0, s>>>(y32, KP, ntot, k, d_rbprob, d_desc, V, Y);
+        PKM_CHECK_LAUNCH();
+        for (int b = 0; b < P; ++b)   // escalated problems: FP64 products
+            if (use64[b]) {
+                ctx->active = &preps[b];
+                mvm(ctx, PKM_FP64, k, V + row0[b] * k, Y + row0[b] * k);
+                ctx->active = &ctx->prep;
+            }
+    };
+    int64_t true_count = 0;
+    auto true_residual = [&]() {
+        product64(x, tmp);
+        k_btrue_res<<<gb, 256, 0, s>>>(tot, k, d_rbprob, st, bb, tmp, r);
+        PKM_CHECK_LAUNCH();
+        dots(r, r, partA);
+        reset_flags();
+        PKM_HIP(hipMemsetAsync(maxtru, 0, sizeof(unsigned long long) * P, s));
+        PKM_HIP(hipMemsetAsync(brokep, 0, sizeof(int) * P, s));
+        k_btrue_final<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, o->tol, st, fl, live, brokep,
+                                          maxtru);
+        PKM_CHECK_LAUNCH();
+        ++true_count;
+    };
+    // Per-problem precision escalation: an FP32 problem whose largest true
+    // residual stalls (StallMonitor), or which has a broken column, moves to
+    // FP64 products; its broken columns resume and all its columns restart
+    // from the FP64 true residual.
+    std::vector<StallMonitor> mon(P);
+    std::vector<unsigned long long> h_maxtru(P);
+    std::vector<int> h_broke(P), h_esc(P);
+    auto escalate_check = [&](bool after_true) -> bool {
+        if (prec == PKM_FP64) return false;
+        PKM_HIP(hipMemcpyAsync(h_broke.data(), brokep, sizeof(int) * P, hipMemcpyDeviceToHost, s));
+        if (after_true)
+            PKM_HIP(hipMemcpyAsync(h_maxtru.data(), maxtru, sizeof(unsigned long long) * P,
+                                   hipMemcpyDeviceToHost, s));
+        PKM_HIP(hipStreamSynchronize(s));
+        bool any = false;
+        for (int b = 0; b < P; ++b) {
+            h_esc[b] = 0;
+            if (use64[b]) continue;
+            bool go = h_broke[b] > 0;
+            if (after_true) {
+                double mt;
+                std::memcpy(&mt, &h_maxtru[b], sizeof(double));
+                go = mon[b].stalled(mt) || go;
+            }
+            if (go) {
+                h_esc[b] = 1;
+                use64[b] = 1;
+                any = true;
+            }
+        }
+        if (!any) return false;
+        PKM_HIP(hipMemcpyAsync(esc, h_esc.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
+        PKM_HIP(hipMemcpyAsync(use64d, use64.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
+        k_breactivate<<<gpk, 256, 0, s>>>(P, k, esc, st);
+        PKM_CHECK_LAUNCH();
+        return true;
+    };
+
+    // r0 = b, z0 = P^-1 r0, p0 = z0
+    PKM_HIP(hipMemcpyAsync(r, bb, vec, hipMemcpyDeviceToDevice, s));
+    {
+        std::vector<int> ones(P, 1);
+        PKM_HIP(hipMemcpyAsync(live, ones.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
+    }
+    apply(r, z);
+    PKM_HIP(hipMemcpyAsync(p, z, vec, hipMemcpyDeviceToDevice, s));
+    dots(bb, bb, partA);
+    dots(r, z, partB);
+    k_binit<<<gpk, 256, 0, s>>>(partA, partB, d_rbrange, P, k, st);
+    PKM_CHECK_LAUNCH();
+    dots(r, r, partA);
+    reset_flags();
+    k_brr<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, o->tol, st, fl, live, brokep);
+    PKM_CHECK_LAUNCH();
+    BFlags f = poll();
+    if (f.live > 0 && f.pending == 0) {
+        true_residual();
+        f = poll();
+    }
+    int64_t it = 0;
+    while (f.live > 0 && it < o->max_iter) {
+        product(p, Ap);
+        dots(p, Ap, partA);
+        k_balpha<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, st);
+        PKM_CHECK_LAUNCH();
+        k_bupdate_xr<<<gb, 256, 0, s>>>(tot, k, d_rbprob, st, p, Ap, x, r);
+        PKM_CHECK_LAUNCH();
+        dots(r, r, partA);
+        reset_flags();
+        PKM_HIP(hipMemsetAsync(brokep, 0, sizeof(int) * P, s));
+        k_brr<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, o->tol, st, fl, live, brokep);
+        PKM_CHECK_LAUNCH();
+        ++it;
+        bool do_true = prec != PKM_FP64 && o->reliable_every > 0 && it % o->reliable_every == 0;
+        if (!do_true && (it % o->check_every == 0 || it == o->max_iter)) {
+            f = poll();
+            if (f.broke > 0 && escalate_check(false)) {
+                true_residual();   // reactivated columns get their FP64 residual
+                f = poll();
+            }
+            if (f.live == 0) break;
+            if (f.pending == 0) do_true = true;
+        }
+        if (do_true) {
+            true_residual();
+            f = poll();
+            if (escalate_check(true)) {
+                true_residual();
+                f = poll();
+            }
+            if (f.live == 0) break;
+        }
+        if (it == o->max_iter) break;
+        apply(r, z);
+        dots(r, z, partB);
+        k_bbeta<<<gpk, 256, 0, s>>>(partB, d_rbrange, P, k, st);
+        PKM_CHECK_LAUNCH();
+        k_bupdate_p<<<gb, 256, 0, s>>>(tot, k, d_rbprob, st, z, p);
+        PKM_CHECK_LAUNCH();
+    }
+    k_bmark_maxiter<<<gpk, 256, 0, s>>>(P, k, st);
+    PKM_CHECK_LAUNCH();
+    product64(x, tmp);
+    k_bsub<<<gb, 256, 0, s>>>(tot, bb, tmp, tmp);
+    PKM_CHECK_LAUNCH();
+    dots(tmp, tmp, partA);
+    k_breport<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, st);
+    PKM_CHECK_LAUNCH();
+    for (int b = 0; b < P; ++b)
+        PKM_HIP(hipMemcpyAsync(X[b], x + row0[b] * k, sizeof(double) * probs[b].n * k,
+                               hipMemcpyDeviceToDevice, s));
+    std::vector<BCol> hs(size_t(P) * k);
+    PKM_HIP(hipMemcpyAsync(hs.data(), st, sizeof(BCol) * P * k, hipMemcpyDeviceToHost, s));
+    PKM_HIP(hipStreamSynchronize(s));
+    auto t_end = std::chrono::steady_clock::now();
+    int code = PKM_OK;
+    for (int b = 0; b < P; ++b)
+        for (int c = 0; c < k; ++c) {
+            const BCol& h = hs[size_t(b) * k + c];
+            if (h.status == PKM_COL_BREAKDOWN) code = PKM_ERR_BREAKDOWN;
+            else if (h.status == PKM_COL_MAX_ITER && code == PKM_OK) code = PKM_NOT_CONVERGED;
+            if (infos) {
+                pkm_solve_info& inf = infos[b];
+                if (inf.iters) inf.iters[c] = h.iters;
+                if (inf.relres_true) inf.relres_true[c] = h.tru;
+                if (inf.relres_rec) inf.relres_rec[c] = h.rec;
+                if (inf.col_status) inf.col_status[c] = h.status;
+            }
+        }
+    if (infos)
+        for (int b = 0; b < P; ++b) {
+            infos[b].prec_final = use64[b] ? PKM_FP64 : prec;
+            infos[b].total_iters = it;
+            infos[b].true_residuals = true_count;
+            infos[b].solve_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+        }
+    if (code == PKM_ERR_BREAKDOWN) ctx->err = "batched solve: a column broke down";
+    else if (code == PKM_NOT_CONVERGED) ctx->err = "batched solve: a column reached max_iter";
+    return code;
+}
+
+}  // namespace pkm

@@ -148,7 +148,7 @@ void grad_pass(pkm_ctx* ctx, const pkm_problem* prob, int N, const double* AS,
     ctx->grad.ensure(sizeof(double) * (nblk * (d + 1) + nlam));
     double* part = ctx->grad.as<double>();
     std::vector<double> hp(nblk * (d + 1));
-    const double* xs = ctx->prep.xs64.as<double>();
+    const double* xs = ctx->P().xs64.as<double>();
     for (int c0 = 0; c0 < ncols;) {
         int rem = ncols - c0;
         int nc = rem > 17 ? 33 : rem > 9 ? 17 : rem > 5 ? 9 : rem > 1 ? 5 : 1;

@@ -182,7 +182,7 @@ static void launch_f32_s(F32Cfg c, dim3 grid, hipStream_t s, const float* js,
 }
 
 F32Out mvm_k32(pkm_ctx* ctx, int k, const double* V, int ldv) {
-    Prepared& P = ctx->prep;
+    Prepared& P = ctx->P();
     PKM_REQUIRE(P.valid32, "internal: FP32 operands not prepared");
     PKM_REQUIRE(k >= 1 && k <= 65, "FP32 product supports 1 <= k <= 65 columns per call");
     F32Cfg c = f32_cfg(k);
@@ -419,7 +419,7 @@ __global__ void k_sum_splits64(const double* __restrict__ part, int nsplit, int6
 }
 
 void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy) {
-    Prepared& P = ctx->prep;
+    Prepared& P = ctx->P();
     PKM_REQUIRE(P.valid64, "internal: FP64 operands not prepared");
     hipStream_t s = ctx->stream;
     const int64_t n = P.n;
@@ -507,12 +507,16 @@ __global__ void k_axpy_lam(int64_t n, int k, const double* __restrict__ V, doubl
 }
 
 void mvm(pkm_ctx* ctx, int prec, int k, const double* V, double* Y) {
-    Prepared& P = ctx->prep;
+    mvm_shift(ctx, prec, k, V, Y, ctx->P().lambda);
+}
+
+void mvm_shift(pkm_ctx* ctx, int prec, int k, const double* V, double* Y, double shift) {
+    Prepared& P = ctx->P();
     hipStream_t s = ctx->stream;
     const int64_t n = P.n;
     if (prec == PKM_FP64) {
         mvm_k64(ctx, k, V, k, Y, k);
-        k_axpy_lam<<<cdiv(n * k, 256), 256, 0, s>>>(n, k, V, P.lambda, Y);
+        k_axpy_lam<<<cdiv(n * k, 256), 256, 0, s>>>(n, k, V, shift, Y);
         PKM_CHECK_LAUNCH();
         return;
     }
@@ -523,7 +527,7 @@ void mvm(pkm_ctx* ctx, int prec, int k, const double* V, double* Y) {
         F32Out o = prec == PKM_FP32 ? mvm_k32(ctx, kc, V + c0, k)
                                     : mvm_kbf16(ctx, prec, kc, V + c0, k);
         k_finish32<<<cdiv(n * kc, 256), 256, 0, s>>>(o.y, o.jsplit, o.stride, o.kp, n, kc, V + c0, k,
-                                                      P.lambda, Y + c0, k);
+                                                      shift, Y + c0, k);
         PKM_CHECK_LAUNCH();
     }
 }

@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void k_mvm_bf16(
 }
 
 void prepare_bf16(pkm_ctx* ctx) {
-    Prepared& P = ctx->prep;
+    Prepared& P = ctx->P();
     if (P.validb) return;
     PKM_REQUIRE(P.valid32, "internal: FP32 preparation must precede BF16 preparation");
     P.s6 = int(cdiv(6 * P.d + 6, 32));
@@ -301,7 +301,7 @@ static void launch_bf16(int S6, int KT, dim3 grid, hipStream_t s, const bf16x8* 
 }
 
 F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
-    Prepared& P = ctx->prep;
+    Prepared& P = ctx->P();
     prepare_bf16(ctx);
     PKM_REQUIRE(k >= 1 && k <= 80, "BF16 product supports 1 <= k <= 80 columns per call");
     const int NP = prec == PKM_BF16X3 ? 3 : 1;

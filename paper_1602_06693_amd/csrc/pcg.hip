@@ -27,7 +27,8 @@ namespace pkm {
 struct ColState {
     double rz, alpha, beta, bnorm, rec, tru, rr;
     int32_t active, status;   // active: not yet accepted / failed
-    int32_t parked, pad;      // parked: recursive residual met tol, awaiting check
+    int32_t parked;           // recursive residual met tol, awaiting check
+    int32_t restart;          // next direction update takes beta = 0
     int64_t iters;
 };
 
@@ -36,6 +37,7 @@ struct Flags {
     int32_t pending;   // active columns that are not parked
     int32_t broke;     // columns that broke down
     int32_t pad;
+    double max_tru;    // largest FP64 true relative residual of active columns
 };
 
 __device__ inline bool stepping(const ColState& s) { return s.active && !s.parked; }
@@ -204,7 +206,27 @@ __global__ void k_true_final(const double* __restrict__ prr, int k, double tol,
         fl->live = live;
         fl->pending = live;
         fl->broke = broke;
+        double mx = 0.0;
+        for (int q = 0; q < k; ++q)
+            if (st[q].active) mx = fmax(mx, st[q].tru);
+        fl->max_tru = mx;
     }
+}
+
+// columns that broke down resume (their residual is replaced next)
+__global__ void k_reactivate(int k, ColState* __restrict__ st) {
+    int c = threadIdx.x;
+    if (c < k && st[c].status == PKM_COL_BREAKDOWN) {
+        st[c].active = 1;
+        st[c].status = PKM_COL_CONVERGED;
+        st[c].parked = 0;
+    }
+}
+
+// every active column restarts its directions at the next update (p = z)
+__global__ void k_set_restart(int k, ColState* __restrict__ st) {
+    int c = threadIdx.x;
+    if (c < k && st[c].active) st[c].restart = 1;
 }
 
 // true residual of every column, for the report (no state change)
@@ -226,8 +248,9 @@ __global__ void k_beta(const double* __restrict__ prz, int k, ColState* __restri
             s.status = PKM_COL_BREAKDOWN;
             s.beta = 0.0;
         } else {
-            s.beta = s.rz > 0.0 ? rz / s.rz : 0.0;
+            s.beta = (s.rz > 0.0 && !s.restart) ? rz / s.rz : 0.0;
             s.rz = rz;
+            s.restart = 0;
         }
     } else {
         s.beta = 0.0;
@@ -335,11 +358,36 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         f = poll();
     }
 
+    // Reduced-precision products carry a perturbation of K; when it is too
+    // large for lambda the refinement stagnates or a column breaks down.
+    // Then the product arithmetic is raised (BF16 -> FP32 -> FP64), broken
+    // columns resume, and every column restarts from its FP64 true residual.
+    int cur = prec;
+    int escalations = 0;
+    StallMonitor mon;
+    auto escalate = [&]() {
+        cur = (cur == PKM_BF16X1 || cur == PKM_BF16X3) ? PKM_FP32 : PKM_FP64;
+        ++escalations;
+        k_reactivate<<<1, 256, 0, s>>>(k, st);
+        PKM_CHECK_LAUNCH();
+        true_residual();
+        k_set_restart<<<1, 256, 0, s>>>(k, st);
+        PKM_CHECK_LAUNCH();
+        mon.reset();
+        return poll();
+    };
+    auto judge = [&](Flags fl_now) {   // after an FP64 true residual
+        if (cur == PKM_FP64) return fl_now;
+        if (fl_now.broke > 0) return escalate();
+        if (fl_now.live > 0 && mon.stalled(fl_now.max_tru)) return escalate();
+        return fl_now;
+    };
+
     int64_t it = 0;
     const int check = o->check_every;
     const int reliable = o->reliable_every;
     while (f.live > 0 && it < o->max_iter) {
-        mvm(ctx, prec, k, p, Ap);
+        mvm(ctx, cur, k, p, Ap);
         dot_part(ctx, p, Ap, n, k, partA);
         k_alpha<<<1, 256, 0, s>>>(partA, k, st);
         PKM_CHECK_LAUNCH();
@@ -349,15 +397,19 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         k_rr<<<1, 256, 0, s>>>(partA, k, o->tol, st, fl);
         PKM_CHECK_LAUNCH();
         ++it;
-        bool do_true = prec != PKM_FP64 && reliable > 0 && it % reliable == 0;
+        bool do_true = cur != PKM_FP64 && reliable > 0 && it % reliable == 0;
         if (!do_true && (it % check == 0 || it == o->max_iter)) {
             f = poll();
-            if (f.live == 0) break;
-            if (f.pending == 0) do_true = true;
+            if (f.broke > 0 && cur != PKM_FP64) {
+                f = escalate();
+            } else {
+                if (f.live == 0) break;
+                if (f.pending == 0) do_true = true;
+            }
         }
         if (do_true) {
             true_residual();
-            f = poll();
+            f = judge(poll());
             if (f.live == 0) break;
         }
         if (it == o->max_iter) break;
@@ -393,6 +445,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
             if (code == PKM_OK) code = PKM_NOT_CONVERGED;
         }
     }
+    (void)escalations;
     if (nbreak > 0)
         ctx->err = std::to_string(nbreak) + " column(s) broke down (first: column " +
                    std::to_string(first_break) + "): p^T K_y p <= 0, r^T z < 0 or a non-finite "
@@ -409,6 +462,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         }
         info->total_iters = it;
         info->true_residuals = true_count;
+        info->prec_final = cur;
         info->solve_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
     }
     return code;

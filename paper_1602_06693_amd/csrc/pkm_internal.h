@@ -39,6 +39,28 @@ struct Error : std::runtime_error {
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Watches the largest FP64 true relative residual of a problem's live columns
+// across residual replacements.  Refinement with a reduced-precision product
+// converges only while the product's perturbation of K stays small against
+// lambda; past that the true residual hovers around a floor.  "Stalled" means
+// three replacements in a row without dropping below 0.7 of the best value
+// seen at the current arithmetic.
+struct StallMonitor {
+    double best = 1e300;
+    int since = 0;
+    bool stalled(double max_true) {
+        if (!(max_true > 0.0)) return false;   // nothing live
+        if (max_true < 0.7 * best) {
+            best = max_true;
+            since = 0;
+        } else {
+            ++since;
+        }
+        return since >= 3;
+    }
+    void reset() { best = 1e300; since = 0; }
+};
+
 // Grow-only device buffer.
 struct DevBuf {
     void* p = nullptr;
@@ -98,10 +120,13 @@ struct pkm_ctx {
     bool timing = false;
     pkm::MvmStats stats[4];
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    pkm::Prepared prep;
+    pkm::Prepared prep;                 // the context's own prepared inputs
+    pkm::Prepared* active = &prep;      // inputs the kernels use (batched solves switch it)
+    pkm::Prepared& P() { return *active; }
     // scratch (grow-only), by purpose
     pkm::DevBuf vbf, v32, y32, v64pad, y64pad, red, red2, scal, state, pcg[8], grad;
     pkm::DevBuf ws_split, ws_tmp, ws_setup[4];
+    pkm::DevBuf batch[16];              // batched-solve workspace
     void* pinned = nullptr;   // pinned host staging area (PKM_PINNED_BYTES)
 };
 
@@ -137,6 +162,8 @@ void validate_problem(const pkm_problem* prob);
 // Y64 = (K + lambda I) V64 for row-major n x k FP64 blocks (device).
 // prec: PKM_FP64 .. PKM_BF16X3.  Uses ctx->prep (must be prepared).
 void mvm(pkm_ctx* ctx, int prec, int k, const double* V, double* Y);
+// Y64 = (K + shift I) V64.
+void mvm_shift(pkm_ctx* ctx, int prec, int k, const double* V, double* Y, double shift);
 // K V only (no lambda term) in FP64, writing into Y (n x k FP64).
 void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy);
 // FP32 product pipeline: pack V (n x k FP64, row-major) into MFMA tiles,

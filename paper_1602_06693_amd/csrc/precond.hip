@@ -130,7 +130,7 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const
         PKM_CHECK_LAUNCH();
         read_info(ctx, dinfo, &hinfo);
         PKM_REQUIRE(hinfo == 0, "inducing index out of range");
-        const double* xs = ctx->prep.xs64.as<double>();
+        const double* xs = ctx->P().xs64.as<double>();
         const int d = prob->d;
         // K_UU + jitter I, then L_U
         rbf_cross64(s, xs, idx, m, xs, idx, m, d, prob->sigma2, core, m);

@@ -120,7 +120,7 @@ __global__ void k_aug32(const double* __restrict__ X, int64_t n, int64_t n_pad, 
 void prepare(pkm_ctx* ctx, const pkm_problem* prob, bool need64, bool need32) {
     // Inputs are prepared afresh on every entry point (O(n d) work): the
     // caller may have changed X in place since the last call.
-    Prepared& P = ctx->prep;
+    Prepared& P = ctx->P();
     std::vector<double> ls(prob->lengthscales, prob->lengthscales + prob->d);
     P.valid64 = P.valid32 = P.validb = false;
     P.X = prob->X;

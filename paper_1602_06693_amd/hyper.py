@@ -1,0 +1,137 @@
+"""Hyperparameter learning loop (Section 5): stochastic-gradient ascent of the
+log-marginal likelihood with ADAGRAD, every step's gradient from the library's
+preconditioned solve and gradient pass.  Orchestration only: each numeric
+step is a libpkm call.
+
+theta = (log sigma2, log l_1 .. log l_d); lambda stays fixed.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import binding as pk
+
+
+def theta_of(sigma2, lengthscales):
+    return np.concatenate([[math.log(sigma2)], np.log(np.asarray(lengthscales, float))])
+
+
+def unpack(theta):
+    return float(math.exp(theta[0])), np.exp(np.asarray(theta[1:], float))
+
+
+class Arm:
+    """A preconditioner policy: returns a pkm_precond handle for the current problem."""
+
+    name = "none"
+
+    def setup(self, ctx, prob, step):
+        return None
+
+
+class NystromArm(Arm):
+    """Fresh uniform inducing points every step (Section 5)."""
+
+    name = "nystrom"
+
+    def __init__(self, n, m, seed=0, jitter=1e-8):
+        self.n, self.m, self.jitter = n, m, jitter
+        self.rng = np.random.default_rng(seed)
+
+    def setup(self, ctx, prob, step):
+        import torch
+        idx = np.sort(self.rng.choice(self.n, size=self.m, replace=False)).astype(np.int32)
+        return pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_NYSTROM, self.m,
+                                    idx=torch.from_numpy(idx).to(prob.X.device),
+                                    jitter=self.jitter)
+
+
+class LearnedArm(Arm):
+    """Sketch-Nystrom preconditioner from the factor network, fine-tuned on
+    K Z probe pairs at every step's hyperparameters."""
+
+    name = "learned"
+
+    def __init__(self, ctx, params, d, rank, n_train_probes=64, first_steps=200,
+                 steps_per_theta=20, lr=1e-3, seed=0, jitter=1e-8, log=None):
+        self.net = pk.pkm_mlp_create(ctx, params, d, 128, rank)
+        self.rank, self.nz = rank, n_train_probes
+        self.first, self.later, self.lr, self.jitter = first_steps, steps_per_theta, lr, jitter
+        self.rng = np.random.default_rng(seed)
+        self.train_s = 0.0
+        self.losses = []
+        self.log = log
+
+    def setup(self, ctx, prob, step):
+        import torch
+        t0 = time.perf_counter()
+        dev = prob.X.device
+        Z = torch.from_numpy(pk_rademacher(self.rng, prob.n, self.nz)).to(dev)
+        KZ = pk.pkm_kernel_mvm_shift(ctx, prob, Z, 0.0, pk.PKM_FP32)   # K Z
+        iters = self.first if step == 0 else self.later
+        for it in range(iters):
+            self.losses.append(pk.pkm_mlp_train_step(ctx, self.net, prob, Z, KZ, self.lr))
+            if self.log and (it + 1) % 50 == 0:
+                self.log(f"[learned] step {step}: Adam {it + 1}/{iters}, loss {self.losses[-1]:.4e}")
+        U = pk.pkm_mlp_forward(ctx, self.net, prob, self.rank)
+        torch.cuda.synchronize()
+        self.train_s += time.perf_counter() - t0
+        return pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_SKETCH, self.rank, Phi=U,
+                                    jitter=self.jitter)
+
+    def close(self):
+        pk.pkm_mlp_destroy(self.net)
+
+
+def pk_rademacher(rng, n, N):
+    return rng.integers(0, 2, size=(n, N)).astype(np.float64) * 2.0 - 1.0
+
+
+def run(ctx, X, y, Z, theta0, lam, arms, steps, eta=1.0, opts=None, replay=None,
+        log=None):
+    """Run ``steps`` ADAGRAD steps.  The first arm's gradient drives theta
+    (or ``replay``, a recorded trajectory); every arm solves the same systems.
+    Returns the theta trajectory and per-arm, per-step records."""
+    import torch
+    opts = opts or pk.make_opts(tol=1e-6, prec=pk.PKM_BF16X3)
+    d = X.shape[1]
+    theta = np.array(theta0, dtype=np.float64)
+    G = np.zeros_like(theta)
+    traj = [theta.copy()]
+    records = {a.name: [] for a in arms}
+    N = Z.shape[1]
+    sol = torch.zeros((X.shape[0], 1 + N), dtype=torch.float64, device=X.device)
+    for t in range(steps):
+        if replay is not None:
+            theta = np.array(replay[t], dtype=np.float64)
+        s2, ls = unpack(theta)
+        prob = pk.Problem(X, ls, s2, lam)
+        grads = {}
+        for arm in arms:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pc = arm.setup(ctx, prob, t)
+            t1 = time.perf_counter()
+            try:
+                g, info = pk.pkm_lml_grad(ctx, prob, y, Z, pc=pc, opts=opts, sol=sol)
+            finally:
+                if pc is not None:
+                    pk.pkm_precond_destroy(pc)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            grads[arm.name] = g
+            rec = {"step": t, "setup_s": t1 - t0, "solve_grad_s": t2 - t1,
+                   "iters": int(info.total_iters), "max_relres": float(info.relres_true.max()),
+                   "converged": bool(np.all(info.col_status == pk.PKM_COL_CONVERGED))}
+            records[arm.name].append(rec)
+            if log:
+                log(f"[{arm.name}] step {t}: iters {rec['iters']}, setup {rec['setup_s']:.3f} s, "
+                    f"solve+grad {rec['solve_grad_s']:.3f} s, relres {rec['max_relres']:.1e}")
+        if replay is None:
+            g = grads[arms[0].name][: 1 + d]          # (log sigma2, log l_r); lambda fixed
+            pk.pkm_adagrad_step(theta, g, G, eta=eta)
+        traj.append(theta.copy())
+    return traj, records

@@ -57,3 +57,24 @@ def test_null_context_is_rejected_without_gpu():
     assert lib.pkm_kernel_mvm(None, None, 1, 0, None, None) == binding.PKM_ERR_INVALID
     assert lib.pkm_create(None, 0, None) == binding.PKM_ERR_INVALID
     assert b"NULL" in lib.pkm_last_error(None)
+
+
+def test_adagrad_step_host_logic_matches_oracle():
+    """pkm_adagrad_step is host-only: checked on the CPU against the oracle."""
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libpkm.so not built")
+    import numpy as np
+    from oracle.adagrad import Adagrad
+    rng = np.random.default_rng(0)
+    theta = rng.standard_normal(10)
+    G = np.zeros(10)
+    ref = Adagrad(eta=0.7)
+    th_ref = theta.copy()
+    for _ in range(5):
+        g = rng.standard_normal(10)
+        binding.pkm_adagrad_step(theta, g, G, eta=0.7)
+        th_ref = ref.step(th_ref, g)
+    assert np.allclose(theta, th_ref, rtol=1e-14, atol=1e-14)
+    bad = np.array([1.0, np.nan])
+    with pytest.raises(binding.PkmError):
+        binding.pkm_adagrad_step(np.zeros(2), bad, np.zeros(2))

@@ -139,3 +139,15 @@ def test_bf16_full_size_sampled_rows(ctx):
     rows = np.random.default_rng(6).choice(p.n, size=64, replace=False)
     want = ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, p.B, rows=rows)
     assert rel_err(got[rows], want, axis=None) < 1e-4
+
+
+@pytest.mark.parametrize("prec,tol", [(pk.PKM_FP64, TOL64), (pk.PKM_FP32, TOL32)])
+def test_shifted_product_zero_shift_is_plain_K(ctx, prec, tol):
+    p = make("block_fp32", seed=17, n=900, n_probes=6)
+    g = GpuProblem(p)
+    want = ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, 0.0, p.B)
+    got = host(pk.pkm_kernel_mvm_shift(ctx, g.prob, g.B, 0.0, prec))
+    assert np.all(rel_err(got, want) < tol)
+    want2 = ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, 0.25, p.B)
+    got2 = host(pk.pkm_kernel_mvm_shift(ctx, g.prob, g.B, 0.25, prec))
+    assert np.all(rel_err(got2, want2) < tol)

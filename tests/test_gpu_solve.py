@@ -9,7 +9,7 @@ from oracle import kernel as ok
 from oracle import precond as op
 from oracle.pcg import pcg
 from paper_1602_06693_amd import binding as pk
-from pkm_inputs import make
+from pkm_inputs import batched_problems, make
 
 pytestmark = pytest.mark.gpu
 JIT = 1e-8
@@ -144,3 +144,40 @@ def test_bf16_products_reach_tolerance_with_reliable_updates(ctx, prec, lam):
         pk.pkm_precond_destroy(pc)
     tr = true_relres(p, host(X))
     assert np.all(tr <= 1e-6), tr
+
+
+def test_too_coarse_product_escalates_and_still_converges(ctx):
+    """A smooth kernel with small noise (d = 4, long lengthscales, lambda ~ 1e-4)
+    where FP32 products stagnate: the solve raises the arithmetic itself and
+    the answer still meets the FP64 tolerance."""
+    from pkm_inputs import batched_problems
+    p = batched_problems(seed=5, count=6, n_lo=300, n_hi=2500, n_probes=8)[0]
+    assert p.d == 4 and p.lam < 2e-4
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, len(p.idx), idx=g.idx, jitter=JIT)
+    try:
+        X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc,
+                               opts=pk.make_opts(tol=1e-6, prec=pk.PKM_BF16X3, max_iter=20000),
+                               allow_warning=False)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    assert np.all(info.col_status == pk.PKM_COL_CONVERGED)
+    print("escalation:", info.prec_final, info.total_iters, info.true_residuals)
+    # the solver certifies its own FP64 residual; the oracle's evaluation
+    # differs from it by summation order only (well under 1e-3 relative)
+    assert np.all(true_relres(p, host(X)) <= 1e-6 * 1.001)
+    assert info.prec_final in (pk.PKM_FP32, pk.PKM_FP64)
+
+
+def test_bf16_breakdown_escalates_at_small_lambda(ctx):
+    p = make("learned", seed=3, n=4096, m=256, n_probes=4)
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, len(p.idx), idx=g.idx, jitter=JIT)
+    try:
+        X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc,
+                               opts=pk.make_opts(tol=1e-6, prec=pk.PKM_BF16X1, max_iter=20000),
+                               allow_warning=False)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    assert np.all(true_relres(p, host(X)) <= 1e-6 * 1.001)
+    assert info.prec_final != pk.PKM_BF16X1
