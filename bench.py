@@ -156,6 +156,87 @@ def hyper_mode(pk, ctx, p, a):
     print(json.dumps(out), flush=True)
 
 
+def batched_mode(pk, ctx, a):
+    """Many independent GP problems (uneven n, d, theta, lambda; 1 + 8 columns
+    each): Nystrom setup for every problem, then one batched solve, against
+    the same problems solved one after another with the single-problem
+    solver.  Both to a certified FP64 true relative residual of 1e-6."""
+    import torch
+
+    from pkm_inputs import batched_problems
+    probs = batched_problems(seed=a.seed, count=a.count)
+    dev = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).to("cuda:0")
+    prec = {"fp32": pk.PKM_FP32, "fp64": pk.PKM_FP64}[a.prec if a.prec in ("fp32", "fp64")
+                                                      else "fp32"]
+    gps = [pk.Problem(dev(p.X), p.lengthscales, p.sigma2, p.lam) for p in probs]
+    Bs = [dev(p.B) for p in probs]
+    idxs = [dev(p.idx) for p in probs]
+    opts = pk.make_opts(tol=1e-6, prec=prec, reliable_every=a.reliable)
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+
+    def setups():
+        return [pk.pkm_precond_setup(ctx, g, pk.PKM_PC_NYSTROM, len(p.idx), idx=ix, jitter=1e-8)
+                for p, g, ix in zip(probs, gps, idxs)]
+
+    def batched_step():
+        pcs = setups()
+        try:
+            Xs, infos, rc = pk.pkm_solve_batched(ctx, gps, Bs, pcs=pcs, opts=opts)
+        finally:
+            for pc in pcs:
+                pk.pkm_precond_destroy(pc)
+        return infos, rc
+
+    def sequential_step():
+        infos = []
+        for p, g, b, ix in zip(probs, gps, Bs, idxs):
+            pc = pk.pkm_precond_setup(ctx, g, pk.PKM_PC_NYSTROM, len(p.idx), idx=ix, jitter=1e-8)
+            try:
+                infos.append(pk.pkm_solve(ctx, g, b, pc=pc, opts=opts)[1])
+            finally:
+                pk.pkm_precond_destroy(pc)
+        return infos
+
+    def timed(fn, label):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        pk.pkm_mvm_stats_reset(ctx)
+        pk.pkm_timing_enable(ctx, label == "batched")
+        ts, res = [], None
+        for i in range(a.steps):
+            t0 = time.perf_counter()
+            res = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            log(f"[{label}] step {i + 1}: {ts[-1]:.3f} s")
+        pk.pkm_timing_enable(ctx, False)
+        return statistics.median(ts), res
+
+    t_b, (infos_b, rc) = timed(batched_step, "batched")
+    st = pk.pkm_mvm_stats(ctx, pk.PKM_FP32)
+    t_s, infos_s = timed(sequential_step, "sequential")
+    ok_b = all(np.all(i.col_status == pk.PKM_COL_CONVERGED) and np.all(i.relres_true <= 1e-6)
+               for i in infos_b)
+    ok_s = all(np.all(i.col_status == pk.PKM_COL_CONVERGED) and np.all(i.relres_true <= 1e-6)
+               for i in infos_s)
+    out = {"mode": "batched", "problems": len(probs), "k": 1 + probs[0].Z.shape[1],
+           "product": a.prec, "sum_n": int(sum(p.n for p in probs)),
+           "sum_n2": float(sum(float(p.n) ** 2 for p in probs)),
+           "dims": sorted({p.d for p in probs}),
+           "batched_s": t_b, "sequential_s": t_s, "speedup": t_s / t_b,
+           "all_certified_batched": bool(ok_b), "all_certified_sequential": bool(ok_s),
+           "max_relres_batched": float(max(i.relres_true.max() for i in infos_b)),
+           "raised_to_fp64": int(sum(i.prec_final == pk.PKM_FP64 for i in infos_b))
+           if prec != pk.PKM_FP64 else None,
+           "iters_batched": [int(i.iters.max()) for i in infos_b],
+           "iters_sequential": [int(i.iters.max()) for i in infos_s],
+           "batched_product_ms": st["ms"] / max(st["launches"], 1),
+           "batched_product_tflops": st["flops"] / max(st["ms"], 1e-9) * 1e-9,
+           "batched_product_launches": st["launches"] // max(a.steps, 1)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,7 +256,8 @@ def main():
     ap.add_argument("--hyper-steps", type=int, default=20)
     ap.add_argument("--n", type=int, default=None, help="override the workload's n")
     ap.add_argument("--rank", type=int, default=128)
-    ap.add_argument("--mode", choices=("step", "mvm", "hyper"), default="step",
+    ap.add_argument("--count", type=int, default=64, help="batched mode: number of problems")
+    ap.add_argument("--mode", choices=("step", "mvm", "hyper", "batched"), default="step",
                     help="mvm: only --steps FP32 kernel products of the workload's size, "
                          "then one 1 GiB device copy (counter calibration for profiles)")
     a = ap.parse_args()
@@ -201,6 +283,10 @@ def main():
     prob = pk.Problem(X, p.lengthscales, p.sigma2, p.lam)
     if a.mode == "hyper":
         hyper_mode(pk, ctx, p, a)
+        pk.pkm_destroy(ctx)
+        return
+    if a.mode == "batched":
+        batched_mode(pk, ctx, a)
         pk.pkm_destroy(ctx)
         return
     if a.mode == "mvm":

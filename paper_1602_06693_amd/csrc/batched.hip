@@ -282,7 +282,8 @@ __global__ void k_bupdate_xr(int64_t tot, int k, const int* __restrict__ rbprob,
 
 __global__ void k_brr(const double* __restrict__ prr, const int* __restrict__ rbrange, int P,
                       int k, double tol, BCol* __restrict__ st, BFlags* __restrict__ fl,
-                      int* __restrict__ live_prob, int* __restrict__ broke_prob) {
+                      int* __restrict__ live_prob, int* __restrict__ broke_prob,
+                      int* __restrict__ act_prob) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P * k) return;
     const int b = e / k, c = e - b * k;
@@ -297,6 +298,7 @@ __global__ void k_brr(const double* __restrict__ prr, const int* __restrict__ rb
     if (bstep(s) && s.rec <= tol) s.parked = 1;
     if (s.active) {
         atomicAdd(&fl->live, 1);
+        atomicOr(&act_prob[b], 1);
         if (!s.parked) {
             atomicAdd(&fl->pending, 1);
             atomicOr(&live_prob[b], 1);
@@ -311,9 +313,11 @@ __global__ void k_brr(const double* __restrict__ prr, const int* __restrict__ rb
 
 __global__ void k_btrue_res(int64_t tot, int k, const int* __restrict__ rbprob,
                             const BCol* __restrict__ st, const double* __restrict__ b,
-                            const double* __restrict__ Ax, double* __restrict__ r) {
+                            const double* __restrict__ Ax, double* __restrict__ r,
+                            const int* __restrict__ tmask) {
     int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (e >= tot) return;
+    if (!tmask[rbprob[(e / k) >> 8]]) return;
     if (col_of(st, rbprob, e, k).active) r[e] = b[e] - Ax[e];
 }
 
@@ -321,11 +325,28 @@ __global__ void k_btrue_final(const double* __restrict__ prr, const int* __restr
                               int P, int k, double tol, BCol* __restrict__ st,
                               BFlags* __restrict__ fl, int* __restrict__ live_prob,
                               int* __restrict__ broke_prob,
-                              unsigned long long* __restrict__ maxtru_bits) {
+                              unsigned long long* __restrict__ maxtru_bits,
+                              int* __restrict__ act_prob, const int* __restrict__ tmask) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P * k) return;
     const int b = e / k, c = e - b * k;
     BCol s = st[e];
+    if (!tmask[b]) {
+        // problem not in this replacement: state unchanged, flags as k_brr
+        if (s.active) {
+            atomicAdd(&fl->live, 1);
+            atomicOr(&act_prob[b], 1);
+            if (!s.parked) {
+                atomicAdd(&fl->pending, 1);
+                atomicOr(&live_prob[b], 1);
+            }
+        }
+        if (s.status == PKM_COL_BREAKDOWN) {
+            atomicAdd(&fl->broke, 1);
+            atomicAdd(&broke_prob[b], 1);
+        }
+        return;
+    }
     if (s.active) {
         const double rr = bsum(prr, rbrange, b, k, c);
         s.rr = rr;
@@ -343,6 +364,7 @@ __global__ void k_btrue_final(const double* __restrict__ prr, const int* __restr
         atomicAdd(&fl->live, 1);
         atomicAdd(&fl->pending, 1);
         atomicOr(&live_prob[b], 1);
+        atomicOr(&act_prob[b], 1);
         // non-negative doubles order like their bit patterns
         atomicMax(&maxtru_bits[b], (unsigned long long)__double_as_longlong(s.tru));
     }
@@ -408,10 +430,11 @@ __global__ void k_bmark_maxiter(int P, int k, BCol* __restrict__ st) {
 }
 
 __global__ void k_breport(const double* __restrict__ prr, const int* __restrict__ rbrange, int P,
-                          int k, BCol* __restrict__ st) {
+                          int k, BCol* __restrict__ st, const int* __restrict__ tmask) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P * k) return;
     const int b = e / k, c = e - b * k;
+    if (!tmask[b]) return;   // certified columns keep the residual of their certification
     const double rr = bsum(prr, rbrange, b, k, c);
     st[e].tru = st[e].bnorm > 0.0 ? sqrt(rr) / st[e].bnorm : 0.0;
 }
@@ -755,7 +778,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     W[8].ensure(vec);                                  // tmp
     W[9].ensure(sizeof(double) * int64_t(nrb) * k * 2);
     W[10].ensure(sizeof(BCol) * P * k + sizeof(BFlags) + 64);
-    W[11].ensure(sizeof(int) * (4 * P + 64) + sizeof(unsigned long long) * P);   // per-problem flags
+    W[11].ensure(sizeof(int) * (6 * P + 64) + sizeof(unsigned long long) * P);   // per-problem flags
     W[12].ensure(sizeof(int4) * (it1.size() + itS.size() + it2.size() + 3));
     W[13].ensure(sizeof(double) * std::max<int64_t>(partoff + toff, 1));
     W[14].ensure(sizeof(float) * (ntot / 16) * 16 * KP + 64);
@@ -779,8 +802,10 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     int* use64d = counter + 16;           // P: problem runs on FP64 products
     int* esc = use64d + P;                // P: problem escalates now
     int* brokep = esc + P;                // P: broken columns per problem
+    int* actp = brokep + P;               // P: problem has active (maybe parked) columns
+    int* tmask = actp + P;                // P: problems in the current FP64 replacement
     unsigned long long* maxtru = reinterpret_cast<unsigned long long*>(
-        W[11].as<char>() + round_up(sizeof(int) * (4 * P + 64), 8));
+        W[11].as<char>() + round_up(sizeof(int) * (6 * P + 64), 8));
     int4* d_it1 = W[12].as<int4>();
     int4* d_itS = d_it1 + it1.size();
     int4* d_it2 = d_itS + itS.size();
@@ -803,6 +828,8 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     const unsigned gb = unsigned(cdiv(tot, 256));
     const unsigned gpk = unsigned(cdiv(int64_t(P) * k, 256));
     BFlags* hfl = static_cast<BFlags*>(ctx->pinned);
+    int* hact = reinterpret_cast<int*>(static_cast<char*>(ctx->pinned) + 64);   // P ints
+    int* hstep = hact + P;                                                        // P ints
 
     auto dots = [&](const double* u, const double* v, double* out) {
         k_bdot_part<<<nrb, 256, 0, s>>>(u, v, k, out);
@@ -811,10 +838,21 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     auto reset_flags = [&]() {
         PKM_HIP(hipMemsetAsync(fl, 0, sizeof(BFlags), s));
         PKM_HIP(hipMemsetAsync(live, 0, sizeof(int) * P, s));
+        PKM_HIP(hipMemsetAsync(actp, 0, sizeof(int) * P, s));
     };
+    // host copies (as of the last poll) of the per-problem flags: act = has
+    // active columns, ready = has active columns and all of them parked
+    std::vector<int> act(P, 1), ready(P, 0), stepping(P, 1);
     auto poll = [&]() {
         PKM_HIP(hipMemcpyAsync(hfl, fl, sizeof(BFlags), hipMemcpyDeviceToHost, s));
+        PKM_HIP(hipMemcpyAsync(hact, actp, sizeof(int) * P, hipMemcpyDeviceToHost, s));
+        PKM_HIP(hipMemcpyAsync(hstep, live, sizeof(int) * P, hipMemcpyDeviceToHost, s));
         PKM_HIP(hipStreamSynchronize(s));
+        for (int b = 0; b < P; ++b) {
+            act[b] = hact[b];
+            stepping[b] = hstep[b];
+            ready[b] = hact[b] && !hstep[b];
+        }
         return *hfl;
     };
     auto apply = [&](const double* R, double* Zo) {
@@ -835,8 +873,10 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         }
         PKM_CHECK_LAUNCH();
     };
-    auto product64 = [&](const double* V, double* Y) {   // Y = K_y V per problem, FP64
+    // Y = K_y V in FP64 for the problems with mask[b] != 0
+    auto product64 = [&](const double* V, double* Y, const std::vector<int>& mask) {
         for (int b = 0; b < P; ++b) {
+            if (!mask[b]) continue;
             ctx->active = &preps[b];
             mvm(ctx, PKM_FP64, k, V + row0[b] * k, Y + row0[b] * k);
             ctx->active = &ctx->prep;
@@ -904,7 +944,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     }
     auto product = [&](const double* V, double* Y) {
         if (prec == PKM_FP64) {
-            product64(V, Y);
+            product64(V, Y, stepping);
             return;
         }
         k_bpack_v32<<<cdiv((ntot / 16) * 16 * KP, 256), 256, 0, s>>>(V, ntot, k, KT, KR, vs);
@@ -925,7 +965,12 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             MvmStats& stt = ctx->stats[PKM_FP32];
             stt.launches += 1;
             stt.ms += ms;
+            // count the work of the problems the launch actually processed
+            std::vector<int> hlive(P);
+            PKM_HIP(hipMemcpyAsync(hlive.data(), live, sizeof(int) * P, hipMemcpyDeviceToHost, s));
+            PKM_HIP(hipStreamSynchronize(s));
             for (int b = 0; b < P; ++b) {
+                if (!hlive[b] || use64[b]) continue;
                 const double pr = double(probs[b].n) * double(probs[b].n);
                 stt.pairs += pr;
                 stt.flops += pr * (2.0 * probs[b].d + 2.0 * k);
@@ -934,23 +979,25 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         k_bfinish32<<<gb, 256, 0, s>>>(y32, KP, ntot, k, d_rbprob, d_desc, V, Y);
         PKM_CHECK_LAUNCH();
         for (int b = 0; b < P; ++b)   // escalated problems: FP64 products
-            if (use64[b]) {
+            if (use64[b] && stepping[b]) {
                 ctx->active = &preps[b];
                 mvm(ctx, PKM_FP64, k, V + row0[b] * k, Y + row0[b] * k);
                 ctx->active = &ctx->prep;
             }
     };
     int64_t true_count = 0;
-    auto true_residual = [&]() {
-        product64(x, tmp);
-        k_btrue_res<<<gb, 256, 0, s>>>(tot, k, d_rbprob, st, bb, tmp, r);
+    // FP64 residual replacement for the problems in mask
+    auto true_residual = [&](const std::vector<int>& mask) {
+        PKM_HIP(hipMemcpyAsync(tmask, mask.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
+        product64(x, tmp, mask);
+        k_btrue_res<<<gb, 256, 0, s>>>(tot, k, d_rbprob, st, bb, tmp, r, tmask);
         PKM_CHECK_LAUNCH();
         dots(r, r, partA);
         reset_flags();
         PKM_HIP(hipMemsetAsync(maxtru, 0, sizeof(unsigned long long) * P, s));
         PKM_HIP(hipMemsetAsync(brokep, 0, sizeof(int) * P, s));
         k_btrue_final<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, o->tol, st, fl, live, brokep,
-                                          maxtru);
+                                          maxtru, actp, tmask);
         PKM_CHECK_LAUNCH();
         ++true_count;
     };
@@ -1006,13 +1053,22 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     PKM_CHECK_LAUNCH();
     dots(r, r, partA);
     reset_flags();
-    k_brr<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, o->tol, st, fl, live, brokep);
+    k_brr<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, o->tol, st, fl, live, brokep, actp);
     PKM_CHECK_LAUNCH();
     BFlags f = poll();
-    if (f.live > 0 && f.pending == 0) {
-        true_residual();
+    // FP64 replacement for the problems in mask, then the escalation test
+    auto replace = [&](const std::vector<int>& mask) {
+        true_residual(mask);
         f = poll();
-    }
+        if (escalate_check(true)) {
+            true_residual(h_esc);
+            f = poll();
+        }
+    };
+    auto any_of = [](const std::vector<int>& v) {
+        return std::any_of(v.begin(), v.end(), [](int q) { return q != 0; });
+    };
+    if (f.live > 0 && any_of(ready)) replace(ready);
     int64_t it = 0;
     while (f.live > 0 && it < o->max_iter) {
         product(p, Ap);
@@ -1024,26 +1080,26 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         dots(r, r, partA);
         reset_flags();
         PKM_HIP(hipMemsetAsync(brokep, 0, sizeof(int) * P, s));
-        k_brr<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, o->tol, st, fl, live, brokep);
+        k_brr<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, o->tol, st, fl, live, brokep, actp);
         PKM_CHECK_LAUNCH();
         ++it;
         bool do_true = prec != PKM_FP64 && o->reliable_every > 0 && it % o->reliable_every == 0;
         if (!do_true && (it % o->check_every == 0 || it == o->max_iter)) {
             f = poll();
             if (f.broke > 0 && escalate_check(false)) {
-                true_residual();   // reactivated columns get their FP64 residual
+                true_residual(h_esc);   // reactivated columns get their FP64 residual
                 f = poll();
             }
             if (f.live == 0) break;
-            if (f.pending == 0) do_true = true;
+            // problems whose active columns have all reached the tolerance on
+            // the recursive residual are certified (or resume) right away
+            if (!do_true && any_of(ready)) {
+                replace(ready);
+                if (f.live == 0) break;
+            }
         }
         if (do_true) {
-            true_residual();
-            f = poll();
-            if (escalate_check(true)) {
-                true_residual();
-                f = poll();
-            }
+            replace(act);
             if (f.live == 0) break;
         }
         if (it == o->max_iter) break;
@@ -1056,12 +1112,26 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     }
     k_bmark_maxiter<<<gpk, 256, 0, s>>>(P, k, st);
     PKM_CHECK_LAUNCH();
-    product64(x, tmp);
-    k_bsub<<<gb, 256, 0, s>>>(tot, bb, tmp, tmp);
-    PKM_CHECK_LAUNCH();
-    dots(tmp, tmp, partA);
-    k_breport<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, st);
-    PKM_CHECK_LAUNCH();
+    // final FP64 residual for problems with a column that was not certified
+    {
+        std::vector<BCol> hs0(size_t(P) * k);
+        PKM_HIP(hipMemcpyAsync(hs0.data(), st, sizeof(BCol) * P * k, hipMemcpyDeviceToHost, s));
+        PKM_HIP(hipStreamSynchronize(s));
+        std::vector<int> need(P, 0);
+        for (int b = 0; b < P; ++b)
+            for (int c = 0; c < k; ++c)
+                if (hs0[size_t(b) * k + c].status != PKM_COL_CONVERGED) need[b] = 1;
+        if (any_of(need)) {
+            PKM_HIP(hipMemcpyAsync(tmask, need.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
+            product64(x, tmp, need);
+            k_bsub<<<gb, 256, 0, s>>>(tot, bb, tmp, tmp);
+            PKM_CHECK_LAUNCH();
+            dots(tmp, tmp, partA);
+            k_breport<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, st, tmask);
+            PKM_CHECK_LAUNCH();
+            PKM_HIP(hipStreamSynchronize(s));   // need is pageable host memory
+        }
+    }
     for (int b = 0; b < P; ++b)
         PKM_HIP(hipMemcpyAsync(X[b], x + row0[b] * k, sizeof(double) * probs[b].n * k,
                                hipMemcpyDeviceToDevice, s));
