@@ -8,11 +8,15 @@
 // Padding rows stay zero throughout.
 //
 // Kernel product: one work-queue launch per input-dimension class (the
-// augmented length fixes the MFMA shape).  Work items are (problem,
-// 256-row block) pairs ordered longest first; every work-group pulls items
-// with an atomic counter until the list is exhausted, so uneven problems
-// balance across the chip and no work-group ever waits on another.
-// Problems whose columns have all converged are skipped.
+// augmented length fixes the MFMA shape).  Work items are (problem, row
+// block, column-range split) triples ordered largest problem first; every
+// work-group pulls items with an atomic counter until the list is
+// exhausted, so uneven problems balance across the chip and no work-group
+// ever waits on another.  A problem is split over its columns j (up to 8
+// ranges, partial sums added in a fixed order afterwards) when its row
+// blocks alone would leave the chip idle, which keeps the last, largest
+// problems fast once the others have converged.  Problems whose columns
+// have all converged are skipped.
 //
 // The launch shape (i-tiles per wave) is chosen per class by a small
 // autotuner that times the candidates on the first call and caches the
@@ -56,6 +60,8 @@ struct BCol {
     double rz, alpha, beta, bnorm, rec, tru, rr;
     int32_t active, status, parked, restart;
     int64_t iters;
+    double ref;   // true relative residual at the last replacement
+    double eta;   // refinement mode (restart at replacement, inner target eta * ref)
 };
 
 struct BFlags {
@@ -71,12 +77,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int S4, int KT, int KR, int U>
 __global__ __launch_bounds__(256) void k_bmvm_f32(const BDesc* __restrict__ desc,
-                                                  const int2* __restrict__ items, int nitems,
+                                                  const int4* __restrict__ items, int nitems,
                                                   int* __restrict__ counter,
                                                   const int* __restrict__ live,
                                                   const int* __restrict__ use64,
                                                   const float* __restrict__ vs,
-                                                  float* __restrict__ yout) {
+                                                  float* __restrict__ ybase, int64_t split_stride) {
     constexpr int KP = 16 * KT + KR;
     __shared__ int sh_item;
     const int lane = threadIdx.x & 63;
@@ -88,9 +94,13 @@ __global__ __launch_bounds__(256) void k_bmvm_f32(const BDesc* __restrict__ desc
         __syncthreads();
         const int it = sh_item;
         if (it >= nitems) return;
-        const int2 item = items[it];
+        const int4 item = items[it];   // problem, row block, split, splits
         if (!live[item.x] || use64[item.x]) continue;
         const BDesc D = desc[item.x];
+        const int64_t tps = (D.ntiles + item.w - 1) / item.w;
+        const int64_t t_beg = item.z * tps;
+        const int64_t t_end = min(D.ntiles, t_beg + tps);
+        float* __restrict__ yout = ybase + item.z * split_stride;
         const int64_t itile0 = (int64_t(item.y) * 4 + wave) * U;   // local tile
         float bi[U][S4];
 #pragma unroll
@@ -106,7 +116,7 @@ __global__ __launch_bounds__(256) void k_bmvm_f32(const BDesc* __restrict__ desc
 #pragma unroll
             for (int e = 0; e < (KR > 0 ? KR : 1); ++e) racc[u][e] = 0.f;
         }
-        for (int64_t t = 0; t < D.ntiles; ++t) {
+        for (int64_t t = t_beg; t < t_end; ++t) {
             float aj[S4];
 #pragma unroll
             for (int s = 0; s < S4; ++s) aj[s] = D.jside[(t * 64 + lane) * S4 + s];
@@ -180,16 +190,25 @@ __global__ void k_bpack_v32(const double* __restrict__ V, int64_t ntot, int k, i
     vs[e] = col < k ? float(V[row * k + col]) : 0.f;
 }
 
-// Ap = y32 + lambda_b p on valid rows (padding rows stay zero)
-__global__ void k_bfinish32(const float* __restrict__ y, int kp, int64_t ntot, int k,
-                            const int* __restrict__ rbprob, const BDesc* __restrict__ desc,
+// Ap = (sum of the problem's split partials) + lambda_b p on valid rows
+// (padding rows stay zero); splits are added in order, in FP64
+__global__ void k_bfinish32(const float* __restrict__ y, int64_t split_stride, int kp,
+                            int64_t ntot, int k, const int* __restrict__ rbprob,
+                            const BDesc* __restrict__ desc, const int* __restrict__ nsplit,
                             const double* __restrict__ p, double* __restrict__ Ap) {
     int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (e >= ntot * k) return;
     const int64_t row = e / k;
     const int c = int(e - row * k);
-    const BDesc& D = desc[rbprob[row >> 8]];
-    Ap[e] = (row - D.row0 < D.n) ? double(y[row * kp + c]) + D.lambda * p[e] : 0.0;
+    const int b = rbprob[row >> 8];
+    const BDesc& D = desc[b];
+    if (row - D.row0 >= D.n) {
+        Ap[e] = 0.0;
+        return;
+    }
+    double acc = 0.0;
+    for (int q = 0; q < nsplit[b]; ++q) acc += double(y[q * split_stride + row * kp + c]);
+    Ap[e] = acc + D.lambda * p[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -232,7 +251,7 @@ __global__ void k_binit(const double* __restrict__ pbb, const double* __restrict
     s.rz = bsum(prz, rbrange, b, k, c);
     s.active = bb > 0.0 ? 1 : 0;
     s.status = PKM_COL_CONVERGED;
-    s.rec = s.tru = bb > 0.0 ? 1.0 : 0.0;
+    s.rec = s.tru = s.ref = bb > 0.0 ? 1.0 : 0.0;
     if (!isfinite(bb) || !isfinite(s.rz) || (s.active && !(s.rz > 0.0))) {
         s.active = 0;
         s.status = PKM_COL_BREAKDOWN;
@@ -295,7 +314,7 @@ __global__ void k_brr(const double* __restrict__ prr, const int* __restrict__ rb
         s.active = 0;
         s.status = PKM_COL_BREAKDOWN;
     }
-    if (bstep(s) && s.rec <= tol) s.parked = 1;
+    if (bstep(s) && s.rec <= fmax(tol, s.eta * s.ref)) s.parked = 1;
     if (s.active) {
         atomicAdd(&fl->live, 1);
         atomicOr(&act_prob[b], 1);
@@ -357,6 +376,9 @@ __global__ void k_btrue_final(const double* __restrict__ prr, const int* __restr
         } else if (s.tru <= tol) {
             s.active = 0;
             s.status = PKM_COL_CONVERGED;
+        } else {
+            s.ref = s.tru;
+            if (s.eta > 0.0) s.restart = 1;
         }
         s.parked = 0;
     }
@@ -375,17 +397,25 @@ __global__ void k_btrue_final(const double* __restrict__ prr, const int* __restr
     st[e] = s;
 }
 
-// problems marked in esc: broken columns resume; active columns restart (beta = 0)
-__global__ void k_breactivate(int P, int k, const int* __restrict__ esc, BCol* __restrict__ st) {
+// problems with esc[b] = 1: broken columns resume, active columns restart
+// (beta = 0) in plain replacement mode.  esc[b] = 2: active columns restart
+// and enter refinement mode with parameter eta.
+__global__ void k_breactivate(int P, int k, const int* __restrict__ esc, double eta,
+                              BCol* __restrict__ st) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P * k || !esc[e / k]) return;
+    const int mode = esc[e / k];
     BCol s = st[e];
-    if (s.status == PKM_COL_BREAKDOWN) {
+    if (mode == 1 && s.status == PKM_COL_BREAKDOWN) {
         s.active = 1;
         s.status = PKM_COL_CONVERGED;
         s.parked = 0;
     }
-    if (s.active) s.restart = 1;
+    if (s.active) {
+        s.restart = 1;
+        s.eta = mode == 2 ? eta : 0.0;
+        s.ref = s.tru;
+    }
     st[e] = s;
 }
 
@@ -625,25 +655,25 @@ static void tune_save() {
 }
 
 template <int S4, int KT, int KR>
-static void launch_bmvm_u(int U, int grid, hipStream_t s, const BDesc* desc, const int2* items,
+static void launch_bmvm_u(int U, int grid, hipStream_t s, const BDesc* desc, const int4* items,
                           int nitems, int* counter, const int* live, const int* use64,
-                          const float* vs, float* y) {
+                          const float* vs, float* y, int64_t ss) {
     if (U == 4)
-        k_bmvm_f32<S4, KT, KR, 4><<<grid, 256, 0, s>>>(desc, items, nitems, counter, live, use64, vs, y);
+        k_bmvm_f32<S4, KT, KR, 4><<<grid, 256, 0, s>>>(desc, items, nitems, counter, live, use64, vs, y, ss);
     else if (U == 2)
-        k_bmvm_f32<S4, KT, KR, 2><<<grid, 256, 0, s>>>(desc, items, nitems, counter, live, use64, vs, y);
+        k_bmvm_f32<S4, KT, KR, 2><<<grid, 256, 0, s>>>(desc, items, nitems, counter, live, use64, vs, y, ss);
     else
-        k_bmvm_f32<S4, KT, KR, 1><<<grid, 256, 0, s>>>(desc, items, nitems, counter, live, use64, vs, y);
+        k_bmvm_f32<S4, KT, KR, 1><<<grid, 256, 0, s>>>(desc, items, nitems, counter, live, use64, vs, y, ss);
 }
 
 template <int S4>
 static void launch_bmvm_s(int KT, int KR, int U, int grid, hipStream_t s, const BDesc* desc,
-                          const int2* items, int nitems, int* counter, const int* live,
-                          const int* use64, const float* vs, float* y) {
-#define PKM_BB(kt, kr)                                                                         \
-    if (KT == kt && KR == kr) {                                                                \
-        launch_bmvm_u<S4, kt, kr>(U, grid, s, desc, items, nitems, counter, live, use64, vs, y); \
-        return;                                                                                \
+                          const int4* items, int nitems, int* counter, const int* live,
+                          const int* use64, const float* vs, float* y, int64_t ss) {
+#define PKM_BB(kt, kr)                                                                             \
+    if (KT == kt && KR == kr) {                                                                    \
+        launch_bmvm_u<S4, kt, kr>(U, grid, s, desc, items, nitems, counter, live, use64, vs, y, ss); \
+        return;                                                                                    \
     }
     PKM_BB(0, 1) PKM_BB(1, 0) PKM_BB(1, 1) PKM_BB(2, 0) PKM_BB(2, 1)
 #undef PKM_BB
@@ -651,18 +681,18 @@ static void launch_bmvm_s(int KT, int KR, int U, int grid, hipStream_t s, const 
 }
 
 static void launch_bmvm(int S4, int KT, int KR, int U, int grid, hipStream_t s, const BDesc* desc,
-                        const int2* items, int nitems, int* counter, const int* live,
-                        const int* use64, const float* vs, float* y) {
+                        const int4* items, int nitems, int* counter, const int* live,
+                        const int* use64, const float* vs, float* y, int64_t ss) {
     switch (S4) {
-        case 1: launch_bmvm_s<1>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
-        case 2: launch_bmvm_s<2>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
-        case 3: launch_bmvm_s<3>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
-        case 4: launch_bmvm_s<4>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
-        case 5: launch_bmvm_s<5>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
-        case 6: launch_bmvm_s<6>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
-        case 7: launch_bmvm_s<7>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
-        case 8: launch_bmvm_s<8>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
-        case 9: launch_bmvm_s<9>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y); break;
+        case 1: launch_bmvm_s<1>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y, ss); break;
+        case 2: launch_bmvm_s<2>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y, ss); break;
+        case 3: launch_bmvm_s<3>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y, ss); break;
+        case 4: launch_bmvm_s<4>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y, ss); break;
+        case 5: launch_bmvm_s<5>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y, ss); break;
+        case 6: launch_bmvm_s<6>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y, ss); break;
+        case 7: launch_bmvm_s<7>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y, ss); break;
+        case 8: launch_bmvm_s<8>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y, ss); break;
+        case 9: launch_bmvm_s<9>(KT, KR, U, grid, s, desc, items, nitems, counter, live, use64, vs, y, ss); break;
         default: fail(PKM_ERR_UNSUPPORTED, "batched product: d must be <= 34");
     }
 }
@@ -672,7 +702,7 @@ struct ClassPlan {
     std::vector<int> probs;
     int U = 4;
     int64_t work = 0;           // sum of n_pad^2 / 256
-    DevBuf items;               // int2 per U
+    DevBuf items;               // int4 (problem, row block, split, splits)
     int nitems = 0;
 };
 
@@ -772,7 +802,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     // device buffers (batch workspace)
     auto& W = ctx->batch;
     W[0].ensure(sizeof(BDesc) * P);
-    W[1].ensure(sizeof(int) * (nrb + P + 1));
+    W[1].ensure(sizeof(int) * (nrb + 2 * P + 1));
     const size_t vec = sizeof(double) * ntot * k;
     for (int i = 2; i < 8; ++i) W[i].ensure(vec);   // b, x, r, z, p, Ap
     W[8].ensure(vec);                                  // tmp
@@ -782,10 +812,13 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     W[12].ensure(sizeof(int4) * (it1.size() + itS.size() + it2.size() + 3));
     W[13].ensure(sizeof(double) * std::max<int64_t>(partoff + toff, 1));
     W[14].ensure(sizeof(float) * (ntot / 16) * 16 * KP + 64);
-    W[15].ensure(sizeof(float) * ntot * KP + 64);
+    constexpr int kMaxSplit = 8;
+    const int64_t split_stride = ntot * KP;
+    W[15].ensure(sizeof(float) * split_stride * kMaxSplit + 64);
     BDesc* d_desc = W[0].as<BDesc>();
     int* d_rbprob = W[1].as<int>();
     int* d_rbrange = d_rbprob + nrb;
+    int* d_nsplit = d_rbrange + P + 1;   // column-range splits per problem
     double* bb = W[2].as<double>();
     double* x = W[3].as<double>();
     double* r = W[4].as<double>();
@@ -882,7 +915,8 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             ctx->active = &ctx->prep;
         }
     };
-    const int grid_q = 256 * 4;   // work-queue work-groups (exit when the list is exhausted)
+    const int grid_q = 256 * 8;   // work-queue work-groups (exit when the list is exhausted)
+    std::vector<int> hsplit(P, 1);
     std::vector<int> use64(P, prec == PKM_FP64 ? 1 : 0);
     PKM_HIP(hipMemcpyAsync(use64d, use64.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
     PKM_HIP(hipMemsetAsync(brokep, 0, sizeof(int) * P, s));
@@ -892,25 +926,35 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         int64_t wb = 1;
         while (wb < cp.work) wb <<= 1;
         TuneKey key{cp.s4, KT, KR, wb};
+        // items for U i-tiles per wave; a problem whose row blocks alone give
+        // fewer than kFill work-groups is split over up to kMaxSplit column
+        // ranges of at least 16 tiles each
         auto build = [&](int U) {
-            std::vector<std::pair<int64_t, int2>> v;
+            constexpr int kFill = 1024;
+            std::vector<std::pair<int64_t, int4>> v;
             for (int b : cp.probs) {
                 const int64_t rows_wg = 64 * U;
                 const int nblk = int(cdiv(preps[b].n_pad, rows_wg));
-                for (int y = 0; y < nblk; ++y) v.push_back({preps[b].n_pad, int2{b, y}});
+                const int64_t ntiles = preps[b].n_pad / 16;
+                int ns = 1;
+                while (ns < kMaxSplit && int64_t(nblk) * ns < kFill && ntiles / (2 * ns) >= 16) ns *= 2;
+                hsplit[b] = ns;
+                for (int y = 0; y < nblk; ++y)
+                    for (int q = 0; q < ns; ++q) v.push_back({preps[b].n_pad, int4{b, y, q, ns}});
             }
             std::stable_sort(v.begin(), v.end(), [](auto& a, auto& c) { return a.first > c.first; });
-            std::vector<int2> items(v.size());
+            std::vector<int4> items(v.size());
             for (size_t i = 0; i < v.size(); ++i) items[i] = v[i].second;
             return items;
         };
-        auto run = [&](int U, const std::vector<int2>& items) {
-            cp.items.ensure(sizeof(int2) * items.size());
-            PKM_HIP(hipMemcpyAsync(cp.items.p, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
+        auto run = [&](int U, const std::vector<int4>& items) {
+            cp.items.ensure(sizeof(int4) * items.size());
+            PKM_HIP(hipMemcpyAsync(cp.items.p, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, s));
             PKM_HIP(hipMemsetAsync(counter, 0, sizeof(int), s));
-            launch_bmvm(cp.s4, KT, KR, U, grid_q, s, d_desc, cp.items.as<int2>(), int(items.size()),
-                        counter, live, use64d, vs, y32);
+            launch_bmvm(cp.s4, KT, KR, U, grid_q, s, d_desc, cp.items.as<int4>(), int(items.size()),
+                        counter, live, use64d, vs, y32, split_stride);
             PKM_CHECK_LAUNCH();
+            PKM_HIP(hipStreamSynchronize(s));   // items is pageable host memory
         };
         auto found = g_tune.find(key);
         if (found == g_tune.end()) {
@@ -939,9 +983,11 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         cp.U = g_tune[key];
         auto items = build(cp.U);
         cp.nitems = int(items.size());
-        cp.items.ensure(sizeof(int2) * items.size());
-        PKM_HIP(hipMemcpyAsync(cp.items.p, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
+        cp.items.ensure(sizeof(int4) * items.size());
+        PKM_HIP(hipMemcpyAsync(cp.items.p, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, s));
+        PKM_HIP(hipStreamSynchronize(s));
     }
+    PKM_HIP(hipMemcpyAsync(d_nsplit, hsplit.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
     auto product = [&](const double* V, double* Y) {
         if (prec == PKM_FP64) {
             product64(V, Y, stepping);
@@ -953,8 +999,8 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         for (auto& kv : classes) {
             ClassPlan& cp = kv.second;
             PKM_HIP(hipMemsetAsync(counter, 0, sizeof(int), s));
-            launch_bmvm(cp.s4, KT, KR, cp.U, grid_q, s, d_desc, cp.items.as<int2>(), cp.nitems,
-                        counter, live, use64d, vs, y32);
+            launch_bmvm(cp.s4, KT, KR, cp.U, grid_q, s, d_desc, cp.items.as<int4>(), cp.nitems,
+                        counter, live, use64d, vs, y32, split_stride);
             PKM_CHECK_LAUNCH();
         }
         if (ctx->timing) {
@@ -976,7 +1022,8 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
                 stt.flops += pr * (2.0 * probs[b].d + 2.0 * k);
             }
         }
-        k_bfinish32<<<gb, 256, 0, s>>>(y32, KP, ntot, k, d_rbprob, d_desc, V, Y);
+        k_bfinish32<<<gb, 256, 0, s>>>(y32, split_stride, KP, ntot, k, d_rbprob, d_desc, d_nsplit,
+                                       V, Y);
         PKM_CHECK_LAUNCH();
         for (int b = 0; b < P; ++b)   // escalated problems: FP64 products
             if (use64[b] && stepping[b]) {
@@ -1001,13 +1048,16 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         PKM_CHECK_LAUNCH();
         ++true_count;
     };
-    // Per-problem precision escalation: an FP32 problem whose largest true
-    // residual stalls (StallMonitor), or which has a broken column, moves to
-    // FP64 products; its broken columns resume and all its columns restart
-    // from the FP64 true residual.
+    // Per-problem response to a stalled or broken FP32 refinement: a problem
+    // whose largest true residual stalls (StallMonitor) first enters
+    // refinement mode (restart at every replacement, inner target
+    // kRefineEta); stalling again there, or a broken column, moves it to FP64
+    // products: its broken columns resume and all its columns restart from
+    // the FP64 true residual.  Returns whether some problem moved to FP64;
+    // h_escm then marks those problems (they need a fresh true residual).
     std::vector<StallMonitor> mon(P);
     std::vector<unsigned long long> h_maxtru(P);
-    std::vector<int> h_broke(P), h_esc(P);
+    std::vector<int> h_broke(P), h_esc(P), h_escm(P), refining(P, 0);
     auto escalate_check = [&](bool after_true) -> bool {
         if (prec == PKM_FP64) return false;
         PKM_HIP(hipMemcpyAsync(h_broke.data(), brokep, sizeof(int) * P, hipMemcpyDeviceToHost, s));
@@ -1015,28 +1065,37 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             PKM_HIP(hipMemcpyAsync(h_maxtru.data(), maxtru, sizeof(unsigned long long) * P,
                                    hipMemcpyDeviceToHost, s));
         PKM_HIP(hipStreamSynchronize(s));
-        bool any = false;
+        bool any = false, moved = false;
         for (int b = 0; b < P; ++b) {
             h_esc[b] = 0;
+            h_escm[b] = 0;
             if (use64[b]) continue;
-            bool go = h_broke[b] > 0;
+            bool stalled = false;
             if (after_true) {
                 double mt;
                 std::memcpy(&mt, &h_maxtru[b], sizeof(double));
-                go = mon[b].stalled(mt) || go;
+                stalled = mon[b].stalled(mt);
             }
-            if (go) {
+            if (h_broke[b] > 0 || (stalled && refining[b])) {
                 h_esc[b] = 1;
+                h_escm[b] = 1;
                 use64[b] = 1;
+                refining[b] = 0;
+                mon[b].reset();
+                any = moved = true;
+            } else if (stalled) {
+                h_esc[b] = 2;
+                refining[b] = 1;
+                mon[b].reset();
                 any = true;
             }
         }
         if (!any) return false;
         PKM_HIP(hipMemcpyAsync(esc, h_esc.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
         PKM_HIP(hipMemcpyAsync(use64d, use64.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
-        k_breactivate<<<gpk, 256, 0, s>>>(P, k, esc, st);
+        k_breactivate<<<gpk, 256, 0, s>>>(P, k, esc, kRefineEta, st);
         PKM_CHECK_LAUNCH();
-        return true;
+        return moved;
     };
 
     // r0 = b, z0 = P^-1 r0, p0 = z0
@@ -1061,7 +1120,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         true_residual(mask);
         f = poll();
         if (escalate_check(true)) {
-            true_residual(h_esc);
+            true_residual(h_escm);
             f = poll();
         }
     };
@@ -1087,7 +1146,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         if (!do_true && (it % o->check_every == 0 || it == o->max_iter)) {
             f = poll();
             if (f.broke > 0 && escalate_check(false)) {
-                true_residual(h_esc);   // reactivated columns get their FP64 residual
+                true_residual(h_escm);   // reactivated columns get their FP64 residual
                 f = poll();
             }
             if (f.live == 0) break;

@@ -16,6 +16,14 @@
 // is replaced by that true residual and the column resumes.  With FP32
 // kernel products the recursive residual drifts from the true one, so the
 // same replacement also runs every reliable_every steps.
+//
+// When the product's error is large against lambda, keeping p across a
+// replacement stops helping: the search directions belong to the perturbed
+// operator and the recursion stalls.  A column in refinement mode (eta > 0)
+// therefore restarts (p = z) at every replacement and parks as soon as its
+// recursive residual has dropped by the factor eta below the true residual
+// of the last replacement: an outer iterative refinement in FP64 around
+// short inner PCG solves with the fast product.
 
 #include "pkm_internal.h"
 
@@ -30,6 +38,8 @@ struct ColState {
     int32_t parked;           // recursive residual met tol, awaiting check
     int32_t restart;          // next direction update takes beta = 0
     int64_t iters;
+    double ref;               // true relative residual at the last replacement
+    double eta;               // refinement mode: inner solve target eta * ref (0: off)
 };
 
 struct Flags {
@@ -88,6 +98,8 @@ __global__ void k_init_state(const double* __restrict__ pbb, const double* __res
     s.iters = 0;
     s.rec = bb > 0.0 ? 1.0 : 0.0;
     s.tru = s.rec;
+    s.ref = s.rec;
+    s.eta = 0.0;
     if (!isfinite(bb) || !isfinite(s.rz)) {   // NaN or Inf in b or x0
         s.active = 0;
         s.status = PKM_COL_BREAKDOWN;
@@ -148,7 +160,7 @@ __global__ void k_rr(const double* __restrict__ prr, int k, double tol, ColState
             s.active = 0;
             s.status = PKM_COL_BREAKDOWN;
         }
-        if (stepping(s) && s.rec <= tol) s.parked = 1;
+        if (stepping(s) && s.rec <= fmax(tol, s.eta * s.ref)) s.parked = 1;
         if (s.active) {
             atomicAdd(&live, 1);
             if (!s.parked) atomicAdd(&pending, 1);
@@ -194,6 +206,9 @@ __global__ void k_true_final(const double* __restrict__ prr, int k, double tol,
             } else if (s.tru <= tol) {
                 s.active = 0;
                 s.status = PKM_COL_CONVERGED;
+            } else {
+                s.ref = s.tru;
+                if (s.eta > 0.0) s.restart = 1;
             }
             s.parked = 0;
         }
@@ -224,9 +239,14 @@ __global__ void k_reactivate(int k, ColState* __restrict__ st) {
 }
 
 // every active column restarts its directions at the next update (p = z)
-__global__ void k_set_restart(int k, ColState* __restrict__ st) {
+// and takes refinement parameter eta (0: plain residual replacement)
+__global__ void k_set_restart(int k, ColState* __restrict__ st, double eta) {
     int c = threadIdx.x;
-    if (c < k && st[c].active) st[c].restart = 1;
+    if (c < k && st[c].active) {
+        st[c].restart = 1;
+        st[c].eta = eta;
+        st[c].ref = st[c].tru;
+    }
 }
 
 // true residual of every column, for the report (no state change)
@@ -358,20 +378,22 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         f = poll();
     }
 
-    // Reduced-precision products carry a perturbation of K; when it is too
-    // large for lambda the refinement stagnates or a column breaks down.
-    // Then the product arithmetic is raised (BF16 -> FP32 -> FP64), broken
-    // columns resume, and every column restarts from its FP64 true residual.
+    // Reduced-precision products carry a perturbation of K.  When the true
+    // residual stalls, the columns first switch to refinement mode (restart
+    // at every replacement, short inner solves); if it stalls again, or a
+    // column breaks down, the product arithmetic is raised (BF16 -> FP32 ->
+    // FP64), broken columns resume, and every column restarts from its FP64
+    // true residual in plain replacement mode.
     int cur = prec;
-    int escalations = 0;
+    bool refining = false;
     StallMonitor mon;
     auto escalate = [&]() {
         cur = (cur == PKM_BF16X1 || cur == PKM_BF16X3) ? PKM_FP32 : PKM_FP64;
-        ++escalations;
+        refining = false;
         k_reactivate<<<1, 256, 0, s>>>(k, st);
         PKM_CHECK_LAUNCH();
         true_residual();
-        k_set_restart<<<1, 256, 0, s>>>(k, st);
+        k_set_restart<<<1, 256, 0, s>>>(k, st, 0.0);
         PKM_CHECK_LAUNCH();
         mon.reset();
         return poll();
@@ -379,7 +401,13 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     auto judge = [&](Flags fl_now) {   // after an FP64 true residual
         if (cur == PKM_FP64) return fl_now;
         if (fl_now.broke > 0) return escalate();
-        if (fl_now.live > 0 && mon.stalled(fl_now.max_tru)) return escalate();
+        if (fl_now.live > 0 && mon.stalled(fl_now.max_tru)) {
+            if (refining) return escalate();
+            refining = true;
+            k_set_restart<<<1, 256, 0, s>>>(k, st, kRefineEta);
+            PKM_CHECK_LAUNCH();
+            mon.reset();
+        }
         return fl_now;
     };
 
@@ -445,7 +473,6 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
             if (code == PKM_OK) code = PKM_NOT_CONVERGED;
         }
     }
-    (void)escalations;
     if (nbreak > 0)
         ctx->err = std::to_string(nbreak) + " column(s) broke down (first: column " +
                    std::to_string(first_break) + "): p^T K_y p <= 0, r^T z < 0 or a non-finite "

@@ -61,6 +61,10 @@ struct StallMonitor {
     void reset() { best = 1e300; since = 0; }
 };
 
+// Refinement mode: an inner PCG solve with the fast product ends once its
+// recursive residual is this factor below the last FP64 true residual.
+constexpr double kRefineEta = 1e-3;
+
 // Grow-only device buffer.
 struct DevBuf {
     void* p = nullptr;
