@@ -40,8 +40,16 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
+_INPUTS = {
+    "small_fp64": "X~U[0,1]^d, lengthscales 0.5",
+    "block_fp32": "X~U[0,1]^d, ARD lengthscales LogU[0.1,1]",
+    "mixed": "X~N(0,I_d), ARD lengthscales LogU[2,8]",
+    "learned": "X~U[0,1]^d, lengthscales 0.5",
+}
+
+
 def _describe(p, m, prec, reliable):
-    return (f"{p.name}: n={p.n}, d={p.d}, X~U[0,1], ARD lengthscales LogU[0.1,1], "
+    return (f"{p.name}: n={p.n}, d={p.d}, {_INPUTS.get(p.name, '')}, "
             f"sigma2={p.sigma2}, lambda={p.lam}, k=1+{p.Z.shape[1]} (y + Rademacher probes), "
             f"Nystrom m={m}, tol={p.tol} (certified FP64 true residual), {prec} kernel "
             f"products, FP64 vectors, FP64 residual replacement every {reliable} steps; "
@@ -354,7 +362,7 @@ def main():
     kname = {"fp32": "k_mvm_f32 (FP32 MFMA distance + exp2 + FP32 MFMA K V)",
              "bf16x3": "k_mvm_bf16<NP=3> (BF16x6-split distance + exp2 + BF16x3 K V, FP32 acc)",
              "bf16x1": "k_mvm_bf16<NP=1> (BF16x6-split distance + exp2 + BF16 K V, FP32 acc)",
-             "fp64": "k_mvm_f64 (FP64 VALU)"}[a.prec]
+             "fp64": "k_mvm_f64x (FP64 MFMA distance + table exp2 + FP64 MFMA K V)"}[a.prec]
     out = {
         "metric": METRIC,
         "value": value,

@@ -117,6 +117,8 @@ int pkm_destroy(pkm_ctx* ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     ctx->prep.xs64.release();
+    ctx->prep.jside64.release();
+    ctx->prep.iside64.release();
     ctx->prep.jside.release();
     ctx->prep.iside.release();
     ctx->prep.jsb.release();

@@ -724,6 +724,8 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             ctx->active = &ctx->prep;
             for (auto& q : v) {
                 q.xs64.release();
+                q.jside64.release();
+                q.iside64.release();
                 q.jside.release();
                 q.iside.release();
                 q.jsb.release();
@@ -1076,7 +1078,11 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
                 std::memcpy(&mt, &h_maxtru[b], sizeof(double));
                 stalled = mon[b].stalled(mt);
             }
-            if (h_broke[b] > 0 || (stalled && refining[b])) {
+            double mt = 0.0;
+            if (after_true) std::memcpy(&mt, &h_maxtru[b], sizeof(double));
+            // diverging (true residual above the right-hand side), broken, or
+            // stalled again in refinement mode: FP64 products
+            if (h_broke[b] > 0 || mt > 1.0 || (stalled && refining[b])) {
                 h_esc[b] = 1;
                 h_escm[b] = 1;
                 use64[b] = 1;

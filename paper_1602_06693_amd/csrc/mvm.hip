@@ -300,89 +300,114 @@ __global__ __launch_bounds__(256) void k_mvm_f64(const double* __restrict__ xs, 
     }
 }
 
-// FP64 product with K V on 16x16x4 FP64 MFMA (d <= 16).  Wave: U i-tiles of
-// 16 rows; per 16-row j-tile each lane computes, with direct FP64
-// differences and exp on the vector ALUs, the four kernel entries
-// K[i0 + l % 16][j0 + 4 s + l / 16], s = 0..3 -- the A operands of four MFMAs
-// whose B operands are V[j0 + 4 s + l / 16][16 kt + l % 16].
+// 2^S in FP64, table-driven (Tang's method, ACM TOMS 1989): S = N / 64 + r
+// with N = rint(64 S) and |r| <= 1/128, so 2^S = 2^(N >> 6) * 2^((N & 63) / 64)
+// * 2^r.  2^(j / 64) comes from a 64-entry table; 2^r = e^(r ln 2) is its
+// Taylor polynomial of degree 6 (truncation below 3e-20 relative on
+// |r| <= 1/128).  S below -1100 gives 0 (2^-1100 underflows); NaN stays NaN.
+__device__ inline double exp2_tab(double S, const double* __restrict__ tab) {
+    constexpr double L = 0.6931471805599453;   // ln 2
+    constexpr double c1 = L, c2 = c1 * L / 2, c3 = c2 * L / 3, c4 = c3 * L / 4,
+                     c5 = c4 * L / 5, c6 = c5 * L / 6;
+    S = S < -1100.0 ? -1100.0 : S;
+    const double y = rint(S * 64.0);
+    const double r = fma(y, -1.0 / 64.0, S);   // exact
+    const int N = int(y);
+    double p = fma(c6, r, c5);
+    p = fma(p, r, c4);
+    p = fma(p, r, c3);
+    p = fma(p, r, c2);
+    p = fma(p, r, c1);
+    p = fma(p, r, 1.0);
+    return ldexp(tab[N & 63] * p, N >> 6);
+}
+
+// FP64 product on 16x16x4 FP64 MFMA, same structure as the FP32 one: per
+// 16-row j-tile, the exponent tile S^T = B_J A_I^T (S4 MFMAs over the
+// augmented operands) leaves lane l with S[i = l % 16][j = l / 16 + 4 r],
+// r = 0..3 -- exactly the A operands of four K V MFMAs whose B operands are
+// V[j0 + 4 r + l / 16][16 q + l % 16].  exp2 runs on the vector ALUs in
+// FP64 (exp2_tab).  Wave: U i-tiles of 16 rows; grid.y splits the j tiles.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <int DP, int KT, int U>
-__global__ __launch_bounds__(256) void k_mvm_f64m(const double* __restrict__ xs, int d,
+template <int S4, int KT, int U>
+__global__ __launch_bounds__(256) void k_mvm_f64x(const double* __restrict__ jside,
+                                                  const double* __restrict__ iside,
                                                   const double* __restrict__ V, int64_t ldv,
-                                                  int kcols, int64_t n, double sigma2,
+                                                  int kcols, int64_t n, int64_t ntiles,
                                                   double* __restrict__ part, int64_t ldp,
-                                                  int64_t split_stride, int64_t j_per_split) {
+                                                  int64_t split_stride, int64_t tiles_per_split) {
+    __shared__ double tab[64];
+    if (threadIdx.x < 64) tab[threadIdx.x] = exp2(double(threadIdx.x) / 64.0);
+    __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane >> 4, cc = lane & 15;
     const int64_t itile0 = (int64_t(blockIdx.x) * 4 + w) * U;
-    const int split = blockIdx.y;
-    const int64_t j0s = split * j_per_split;
-    const int64_t j1 = min(n, j0s + j_per_split);
-    double xi[U][DP];
+    const int64_t t0 = int64_t(blockIdx.y) * tiles_per_split;
+    const int64_t t1 = min(ntiles, t0 + tiles_per_split);
+    double ai[U][S4];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t i = (itile0 + u) * 16 + cc;
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int r = 0; r < DP; ++r) xi[u][r] = (i < n && r < d) ? xs[i * d + r] : 0.0;
-    }
+        for (int q = 0; q < S4; ++q) ai[u][q] = iside[((itile0 + u) * 64 + lane) * S4 + q];
     f64x4 acc[U][KT];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int kt = 0; kt < KT; ++kt) acc[u][kt] = f64x4{0.0, 0.0, 0.0, 0.0};
-    const double ls2 = log(sigma2);
-    for (int64_t jb = j0s; jb < j1; jb += 16) {
+        for (int q = 0; q < KT; ++q) acc[u][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t t = t0; t < t1; ++t) {
+        double bj[S4];
 #pragma unroll
-        for (int sidx = 0; sidx < 4; ++sidx) {
-            const int64_t j = jb + 4 * sidx + g;
-            const bool jv = j < j1;
-            double xj[DP], vb[KT];
+        for (int q = 0; q < S4; ++q) bj[q] = jside[(t * 64 + lane) * S4 + q];
+        double vb[KT][4];
 #pragma unroll
-            for (int r = 0; r < DP; ++r) xj[r] = (jv && r < d) ? xs[j * d + r] : 0.0;
+        for (int r = 0; r < 4; ++r) {
+            const int64_t j = t * 16 + 4 * r + g;
 #pragma unroll
-            for (int kt = 0; kt < KT; ++kt) {
-                const int c = 16 * kt + cc;
-                vb[kt] = (jv && c < kcols) ? V[j * ldv + c] : 0.0;
+            for (int q = 0; q < KT; ++q) {
+                const int c = 16 * q + cc;
+                vb[q][r] = (j < n && c < kcols) ? V[j * ldv + c] : 0.0;
             }
+        }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                double sq = 0.0;
+        for (int u = 0; u < U; ++u) {
+            f64x4 st = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int r = 0; r < DP; ++r) {
-                    const double t = xi[u][r] - xj[r];
-                    sq = fma(t, t, sq);
-                }
-                const double kij = exp(fma(-0.5, sq, ls2));
+            for (int q = 0; q < S4; ++q)
+                st = __builtin_amdgcn_mfma_f64_16x16x4f64(bj[q], ai[u][q], st, 0, 0, 0);
+            double kv[4];
 #pragma unroll
-                for (int kt = 0; kt < KT; ++kt)
-                    acc[u][kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(kij, vb[kt], acc[u][kt], 0, 0, 0);
-            }
+            for (int r = 0; r < 4; ++r) kv[r] = exp2_tab(st[r], tab);
+#pragma unroll
+            for (int q = 0; q < KT; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[u][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[r], vb[q][r], acc[u][q], 0, 0, 0);
         }
     }
     // FP64 16x16x4 results: lane l holds rows l / 16 + 4 r, column l % 16
-    double* po = part + split * split_stride;
+    double* po = part + blockIdx.y * split_stride;
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int kt = 0; kt < KT; ++kt)
+        for (int q = 0; q < KT; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = (itile0 + u) * 16 + g + 4 * r;
-                const int c = 16 * kt + cc;
-                if (i < n && c < kcols) po[i * ldp + c] = acc[u][kt][r];
+                const int c = 16 * q + cc;
+                if (i < n && c < kcols) po[i * ldp + c] = acc[u][q][r];
             }
 }
 
-template <int DP>
-static void launch_f64m(int KT, dim3 grid, hipStream_t s, const double* xs, int d, const double* V,
-                        int64_t ldv, int k, int64_t n, double sigma2, double* part, int64_t ldp,
-                        int64_t sstride, int64_t jps) {
+template <int S4>
+static void launch_f64x(int KT, dim3 grid, hipStream_t s, const double* js, const double* is,
+                        const double* V, int64_t ldv, int k, int64_t n, int64_t ntiles,
+                        double* part, int64_t ldp, int64_t sstride, int64_t tps) {
     switch (KT) {
-        case 1: k_mvm_f64m<DP, 1, 2><<<grid, 256, 0, s>>>(xs, d, V, ldv, k, n, sigma2, part, ldp, sstride, jps); break;
-        case 2: k_mvm_f64m<DP, 2, 2><<<grid, 256, 0, s>>>(xs, d, V, ldv, k, n, sigma2, part, ldp, sstride, jps); break;
-        case 3: k_mvm_f64m<DP, 3, 2><<<grid, 256, 0, s>>>(xs, d, V, ldv, k, n, sigma2, part, ldp, sstride, jps); break;
-        case 4: k_mvm_f64m<DP, 4, 2><<<grid, 256, 0, s>>>(xs, d, V, ldv, k, n, sigma2, part, ldp, sstride, jps); break;
+        case 1: k_mvm_f64x<S4, 1, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, part, ldp, sstride, tps); break;
+        case 2: k_mvm_f64x<S4, 2, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, part, ldp, sstride, tps); break;
+        case 3: k_mvm_f64x<S4, 3, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, part, ldp, sstride, tps); break;
+        case 4: k_mvm_f64x<S4, 4, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, part, ldp, sstride, tps); break;
         default: fail(PKM_ERR_UNSUPPORTED, "FP64 MFMA product: bad column tiling");
     }
 }
@@ -424,7 +449,7 @@ void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy) 
     hipStream_t s = ctx->stream;
     const int64_t n = P.n;
     const int d = P.d;
-    const bool use_mfma = d <= 16 && k >= 4;
+    const bool use_mfma = P.d4 <= kAug64MaxD4 && k >= 4;
     // rows per work-group: 128 on the MFMA path (4 waves x 2 tiles x 16), 256 otherwise
     const int64_t rows_wg = use_mfma ? 128 : 256;
     int64_t nrb = cdiv(n, rows_wg);
@@ -441,12 +466,25 @@ void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy) 
     if (ctx->timing) PKM_HIP(hipEventRecord(e0, s));
     const double* xs = P.xs64.as<double>();
     if (use_mfma) {
+        // j tiles of 16 rows over the padded length; jps is a multiple of 64
+        const int64_t ntiles = P.n_pad / 16;
+        const int64_t tps = jps / 16;
+        const double* js = P.jside64.as<double>();
+        const double* is = P.iside64.as<double>();
         for (int col0 = 0; col0 < k; col0 += 64) {
             const int kc = std::min(64, k - col0);
             const int KT = int(cdiv(kc, 16));
-            if (d <= 4) launch_f64m<4>(KT, grid, s, xs, d, V + col0, ldv, kc, n, P.sigma2, part + col0, k, sstride, jps);
-            else if (d <= 8) launch_f64m<8>(KT, grid, s, xs, d, V + col0, ldv, kc, n, P.sigma2, part + col0, k, sstride, jps);
-            else launch_f64m<16>(KT, grid, s, xs, d, V + col0, ldv, kc, n, P.sigma2, part + col0, k, sstride, jps);
+            switch (P.d4 / 4) {
+#define PKM_F64X(S4)                                                                          \
+    case S4:                                                                                  \
+        launch_f64x<S4>(KT, grid, s, js, is, V + col0, ldv, kc, n, ntiles, part + col0, k, \
+                        sstride, tps);                                                        \
+        break;
+                PKM_F64X(1) PKM_F64X(2) PKM_F64X(3) PKM_F64X(4) PKM_F64X(5)
+                PKM_F64X(6) PKM_F64X(7) PKM_F64X(8) PKM_F64X(9)
+#undef PKM_F64X
+                default: fail(PKM_ERR_UNSUPPORTED, "FP64 MFMA product: augmented length");
+            }
             PKM_CHECK_LAUNCH();
         }
     } else {

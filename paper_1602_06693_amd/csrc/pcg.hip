@@ -29,6 +29,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 
 namespace pkm {
 
@@ -386,6 +387,8 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     // true residual in plain replacement mode.
     int cur = prec;
     bool refining = false;
+    // PKM_VERBOSE=1 reports every FP64 replacement on stderr (long solves)
+    static const bool verbose = std::getenv("PKM_VERBOSE") != nullptr;
     StallMonitor mon;
     auto escalate = [&]() {
         cur = (cur == PKM_BF16X1 || cur == PKM_BF16X3) ? PKM_FP32 : PKM_FP64;
@@ -401,6 +404,9 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     auto judge = [&](Flags fl_now) {   // after an FP64 true residual
         if (cur == PKM_FP64) return fl_now;
         if (fl_now.broke > 0) return escalate();
+        // a true residual above the right-hand side itself: the iteration
+        // diverges, the product is far too coarse for lambda
+        if (fl_now.live > 0 && fl_now.max_tru > 1.0) return escalate();
         if (fl_now.live > 0 && mon.stalled(fl_now.max_tru)) {
             if (refining) return escalate();
             refining = true;
@@ -438,8 +444,15 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         if (do_true) {
             true_residual();
             f = judge(poll());
+            if (verbose)
+                std::fprintf(stderr, "pkm_solve: step %lld, product %d%s, live columns %d, "
+                             "largest true relative residual %.3e\n", (long long)it, cur,
+                             refining ? " (refinement mode)" : "", f.live, f.max_tru);
             if (f.live == 0) break;
         }
+        if (verbose && cur == PKM_FP64 && it % 25 == 0)
+            std::fprintf(stderr, "pkm_solve: step %lld, FP64 products, live columns %d\n",
+                         (long long)it, f.live);
         if (it == o->max_iter) break;
         precond(r, z);
         dot_part(ctx, r, z, n, k, partB);

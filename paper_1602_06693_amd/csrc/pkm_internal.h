@@ -65,6 +65,10 @@ struct StallMonitor {
 // recursive residual is this factor below the last FP64 true residual.
 constexpr double kRefineEta = 1e-3;
 
+// Largest augmented length (d + 2 rounded up to 4) of the FP64 MFMA product;
+// larger d takes the FP64 vector-ALU product on direct differences.
+constexpr int kAug64MaxD4 = 36;
+
 // Grow-only device buffer.
 struct DevBuf {
     void* p = nullptr;
@@ -101,6 +105,9 @@ struct Prepared {
     int d = 0;
     // FP64: X scaled by 1/l_r (direct differences need no centring)
     DevBuf xs64;            // n_pad x d
+    // FP64 MFMA operands of the augmented contraction (same form and lane
+    // order as the FP32 ones, d4 slots)
+    DevBuf jside64, iside64;
     // FP32 MFMA operands of the augmented distance contraction.
     int d4 = 0;             // augmented length d + 2 rounded up to 4
     DevBuf jside;           // j-side operand tiles, MFMA lane order

@@ -4,7 +4,8 @@
 // scaled differences (x_ir - x_jr) / l_r, so every product works on scaled
 // rows.  Two forms are prepared:
 //
-//  * FP64 rows xs_i = x_i / l (direct differences in the FP64 product).
+//  * FP64 rows xs_i = x_i / l (direct differences, used by the setup
+//    kernels and the FP64 product for large d).
 //  * FP32 operands of one augmented contraction whose value is the base-2
 //    exponent of the kernel entry.  With xh_i = (x_i - mean) / l * c,
 //    c = sqrt(log2(e) / 2), and
@@ -16,8 +17,11 @@
 //    which bounds the cancellation error of the expansion.  Padded j rows
 //    get a huge negative exponent so their entries vanish.
 //
-// Both FP32 operands are stored in the lane order of the 16x16x4 FP32 MFMA:
-// element (tile t, lane l, group s) = row 16 t + l % 16, slot 4 s + l / 16.
+// The same operands are prepared in FP32 and in FP64 (the FP64 product's
+// contraction has an absolute exponent error of a few units of 2^-53 times
+// |xh|^2).  Both are stored in the lane order of the 16x16x4 MFMA (the FP32
+// and FP64 forms share it): element (tile t, lane l, group s) =
+// row 16 t + l % 16, slot 4 s + l / 16.
 
 #include "pkm_internal.h"
 
@@ -73,47 +77,50 @@ __global__ void k_scale64(const double* __restrict__ X, int64_t n, int64_t n_pad
     xs[e] = i < n ? X[i * d + r] * inv_l[r] : 0.0;
 }
 
-// FP32 augmented operands in MFMA lane order (see file header).
-__global__ void k_aug32(const double* __restrict__ X, int64_t n, int64_t n_pad, int d,
-                        int d4, const double* __restrict__ inv_l,
-                        const double* __restrict__ mean, double log2s2,
-                        float* __restrict__ jside, float* __restrict__ iside) {
+// Augmented operands in MFMA lane order (see file header), FP32 or FP64.
+template <class T>
+__global__ void k_aug(const double* __restrict__ X, int64_t n, int64_t n_pad, int d,
+                      int d4, const double* __restrict__ inv_l,
+                      const double* __restrict__ mean, double log2s2,
+                      T* __restrict__ jside, T* __restrict__ iside) {
     int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i >= n_pad) return;
     const double c = sqrt(0.5 * 1.4426950408889634);  // sqrt(log2(e) / 2)
     int64_t t = i >> 4;
     int row = int(i & 15);
     int groups = d4 >> 2;
-    auto put = [&](float* base, int slot, float v) {
+    auto put = [&](T* base, int slot, double v) {
         int s = slot >> 2, kk = slot & 3;
         int lane = row + 16 * kk;
-        base[(t * 64 + lane) * groups + s] = v;
+        base[(t * 64 + lane) * groups + s] = T(v);
     };
     if (i < n) {
         double nrm = 0.0;
         for (int r = 0; r < d; ++r) {
-            float xh = float((X[i * d + r] - mean[r]) * inv_l[r] * c);
+            // the stored (rounded) coordinate enters the norm, so the
+            // expansion is exact for the stored values up to its own rounding
+            T xh = T((X[i * d + r] - mean[r]) * inv_l[r] * c);
             nrm += double(xh) * double(xh);
-            put(iside, r, 2.0f * xh);
-            put(jside, r, xh);
+            put(iside, r, 2.0 * double(xh));
+            put(jside, r, double(xh));
         }
-        put(iside, d, float(log2s2 - nrm));
-        put(iside, d + 1, 1.0f);
-        put(jside, d, 1.0f);
-        put(jside, d + 1, float(-nrm));
+        put(iside, d, log2s2 - nrm);
+        put(iside, d + 1, 1.0);
+        put(jside, d, 1.0);
+        put(jside, d + 1, -nrm);
     } else {
         for (int r = 0; r < d; ++r) {
-            put(iside, r, 0.0f);
-            put(jside, r, 0.0f);
+            put(iside, r, 0.0);
+            put(jside, r, 0.0);
         }
-        put(iside, d, float(log2s2));
-        put(iside, d + 1, 1.0f);
-        put(jside, d, 1.0f);
-        put(jside, d + 1, -1.0e30f);
+        put(iside, d, log2s2);
+        put(iside, d + 1, 1.0);
+        put(jside, d, 1.0);
+        put(jside, d + 1, -1.0e30);
     }
     for (int sl = d + 2; sl < d4; ++sl) {
-        put(iside, sl, 0.0f);
-        put(jside, sl, 0.0f);
+        put(iside, sl, 0.0);
+        put(jside, sl, 0.0);
     }
 }
 
@@ -141,23 +148,32 @@ void prepare(pkm_ctx* ctx, const pkm_problem* prob, bool need64, bool need32) {
     double hbuf[64];
     for (int r = 0; r < d; ++r) hbuf[r] = 1.0 / ls[r];
     PKM_HIP(hipMemcpyAsync(inv_l, hbuf, sizeof(double) * d, hipMemcpyHostToDevice, s));
+    k_colmean<<<d, 256, 0, s>>>(prob->X, n, d, mean);
+    PKM_CHECK_LAUNCH();
+    P.d4 = int(round_up(d + 2, 4));
     if (need64 && !P.valid64) {
         P.xs64.ensure(sizeof(double) * n_pad * d);
         int64_t tot = n_pad * d;
         k_scale64<<<cdiv(tot, 256), 256, 0, s>>>(prob->X, n, n_pad, d, inv_l,
                                                   P.xs64.as<double>());
         PKM_CHECK_LAUNCH();
+        if (P.d4 <= kAug64MaxD4) {
+            P.jside64.ensure(sizeof(double) * n_pad * P.d4);
+            P.iside64.ensure(sizeof(double) * n_pad * P.d4);
+            k_aug<double><<<cdiv(n_pad, 256), 256, 0, s>>>(prob->X, n, n_pad, d, P.d4, inv_l, mean,
+                                                           std::log2(P.sigma2),
+                                                           P.jside64.as<double>(),
+                                                           P.iside64.as<double>());
+            PKM_CHECK_LAUNCH();
+        }
         P.valid64 = true;
     }
     if (need32 && !P.valid32) {
-        k_colmean<<<d, 256, 0, s>>>(prob->X, n, d, mean);
-        PKM_CHECK_LAUNCH();
-        P.d4 = int(round_up(d + 2, 4));
         P.jside.ensure(sizeof(float) * n_pad * P.d4);
         P.iside.ensure(sizeof(float) * n_pad * P.d4);
-        k_aug32<<<cdiv(n_pad, 256), 256, 0, s>>>(prob->X, n, n_pad, d, P.d4, inv_l, mean,
-                                                  std::log2(P.sigma2), P.jside.as<float>(),
-                                                  P.iside.as<float>());
+        k_aug<float><<<cdiv(n_pad, 256), 256, 0, s>>>(prob->X, n, n_pad, d, P.d4, inv_l, mean,
+                                                      std::log2(P.sigma2), P.jside.as<float>(),
+                                                      P.iside.as<float>());
         PKM_CHECK_LAUNCH();
         P.valid32 = true;
     }

@@ -9,7 +9,10 @@ from pkm_inputs import make
 
 pytestmark = pytest.mark.gpu
 
-# FP64: direct differences and FP64 exp on both sides -> rounding-order level.
+# FP64: the GPU's augmented FP64 contraction leaves each base-2 exponent with
+# an absolute error of a few 2^-53 (|a_i| + |b_j|) (|xh|^2 <= ~40 after
+# centring), i.e. ~1e-14 relative per entry; its exp2 adds a few ulp and the
+# sums differ from the oracle's only in order: 1e-13 norm-wise.
 TOL64 = 1e-13
 # FP32: each entry's base-2 exponent carries about 2^-24 (|a_i| + |b_j|) absolute
 # error from the FP32 contraction (|xh|^2 <= ~40 after centring), exp2 adds ~2
