@@ -346,6 +346,7 @@ __global__ void k_btrue_final(const double* __restrict__ prr, const int* __restr
                               int* __restrict__ broke_prob,
                               unsigned long long* __restrict__ maxtru_bits,
                               int* __restrict__ act_prob, const int* __restrict__ tmask) {
+    unsigned long long* __restrict__ maxgap_bits = maxtru_bits + P;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= P * k) return;
     const int b = e / k, c = e - b * k;
@@ -366,10 +367,13 @@ __global__ void k_btrue_final(const double* __restrict__ prr, const int* __restr
         }
         return;
     }
+    double gap = 0.0;
     if (s.active) {
         const double rr = bsum(prr, rbrange, b, k, c);
         s.rr = rr;
+        const double rec_before = s.rec;
         s.tru = s.rec = s.bnorm > 0.0 ? sqrt(rr) / s.bnorm : 0.0;
+        gap = s.tru / fmax(rec_before, 1e-300);
         if (!isfinite(rr)) {
             s.active = 0;
             s.status = PKM_COL_BREAKDOWN;
@@ -389,6 +393,8 @@ __global__ void k_btrue_final(const double* __restrict__ prr, const int* __restr
         atomicOr(&act_prob[b], 1);
         // non-negative doubles order like their bit patterns
         atomicMax(&maxtru_bits[b], (unsigned long long)__double_as_longlong(s.tru));
+        if (isfinite(gap))
+            atomicMax(&maxgap_bits[b], (unsigned long long)__double_as_longlong(gap));
     }
     if (s.status == PKM_COL_BREAKDOWN) {
         atomicAdd(&fl->broke, 1);
@@ -810,7 +816,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     W[8].ensure(vec);                                  // tmp
     W[9].ensure(sizeof(double) * int64_t(nrb) * k * 2);
     W[10].ensure(sizeof(BCol) * P * k + sizeof(BFlags) + 64);
-    W[11].ensure(sizeof(int) * (6 * P + 64) + sizeof(unsigned long long) * P);   // per-problem flags
+    W[11].ensure(sizeof(int) * (6 * P + 64) + sizeof(unsigned long long) * 2 * P);   // per-problem flags
     W[12].ensure(sizeof(int4) * (it1.size() + itS.size() + it2.size() + 3));
     W[13].ensure(sizeof(double) * std::max<int64_t>(partoff + toff, 1));
     W[14].ensure(sizeof(float) * (ntot / 16) * 16 * KP + 64);
@@ -1043,7 +1049,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         PKM_CHECK_LAUNCH();
         dots(r, r, partA);
         reset_flags();
-        PKM_HIP(hipMemsetAsync(maxtru, 0, sizeof(unsigned long long) * P, s));
+        PKM_HIP(hipMemsetAsync(maxtru, 0, sizeof(unsigned long long) * 2 * P, s));
         PKM_HIP(hipMemsetAsync(brokep, 0, sizeof(int) * P, s));
         k_btrue_final<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, o->tol, st, fl, live, brokep,
                                           maxtru, actp, tmask);
@@ -1058,13 +1064,13 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     // the FP64 true residual.  Returns whether some problem moved to FP64;
     // h_escm then marks those problems (they need a fresh true residual).
     std::vector<StallMonitor> mon(P);
-    std::vector<unsigned long long> h_maxtru(P);
+    std::vector<unsigned long long> h_maxtru(2 * P);   // largest true residual, largest gap
     std::vector<int> h_broke(P), h_esc(P), h_escm(P), refining(P, 0);
     auto escalate_check = [&](bool after_true) -> bool {
         if (prec == PKM_FP64) return false;
         PKM_HIP(hipMemcpyAsync(h_broke.data(), brokep, sizeof(int) * P, hipMemcpyDeviceToHost, s));
         if (after_true)
-            PKM_HIP(hipMemcpyAsync(h_maxtru.data(), maxtru, sizeof(unsigned long long) * P,
+            PKM_HIP(hipMemcpyAsync(h_maxtru.data(), maxtru, sizeof(unsigned long long) * 2 * P,
                                    hipMemcpyDeviceToHost, s));
         PKM_HIP(hipStreamSynchronize(s));
         bool any = false, moved = false;
@@ -1078,11 +1084,16 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
                 std::memcpy(&mt, &h_maxtru[b], sizeof(double));
                 stalled = mon[b].stalled(mt);
             }
-            double mt = 0.0;
-            if (after_true) std::memcpy(&mt, &h_maxtru[b], sizeof(double));
-            // diverging (true residual above the right-hand side), broken, or
-            // stalled again in refinement mode: FP64 products
-            if (h_broke[b] > 0 || mt > 1.0 || (stalled && refining[b])) {
+            double mt = 0.0, mg = 0.0;
+            if (after_true) {
+                std::memcpy(&mt, &h_maxtru[b], sizeof(double));
+                std::memcpy(&mg, &h_maxtru[P + b], sizeof(double));
+            }
+            // diverging (true residual above the right-hand side while the
+            // recursion believes it 100 times smaller), broken, or stalled
+            // again in refinement mode: FP64 products
+            const bool diverging = mt > 1.0 && mg > 100.0;
+            if (h_broke[b] > 0 || diverging || (stalled && refining[b])) {
                 h_esc[b] = 1;
                 h_escm[b] = 1;
                 use64[b] = 1;

@@ -39,6 +39,7 @@ struct ColState {
     int32_t parked;           // recursive residual met tol, awaiting check
     int32_t restart;          // next direction update takes beta = 0
     int64_t iters;
+    double gap;               // true / recursive residual at the last replacement
     double ref;               // true relative residual at the last replacement
     double eta;               // refinement mode: inner solve target eta * ref (0: off)
 };
@@ -49,6 +50,7 @@ struct Flags {
     int32_t broke;     // columns that broke down
     int32_t pad;
     double max_tru;    // largest FP64 true relative residual of active columns
+    double max_gap;    // largest true / recursive residual ratio at the replacement
 };
 
 __device__ inline bool stepping(const ColState& s) { return s.active && !s.parked; }
@@ -199,7 +201,9 @@ __global__ void k_true_final(const double* __restrict__ prr, int k, double tol,
         if (s.active) {
             double rr = sum_parts(prr, k, c);
             s.rr = rr;
+            const double rec_before = s.rec;
             s.tru = s.bnorm > 0.0 ? sqrt(rr) / s.bnorm : 0.0;
+            s.gap = s.tru / fmax(rec_before, 1e-300);
             s.rec = s.tru;
             if (!isfinite(rr)) {
                 s.active = 0;
@@ -222,10 +226,14 @@ __global__ void k_true_final(const double* __restrict__ prr, int k, double tol,
         fl->live = live;
         fl->pending = live;
         fl->broke = broke;
-        double mx = 0.0;
+        double mx = 0.0, mg = 0.0;
         for (int q = 0; q < k; ++q)
-            if (st[q].active) mx = fmax(mx, st[q].tru);
+            if (st[q].active) {
+                mx = fmax(mx, st[q].tru);
+                mg = fmax(mg, st[q].gap);
+            }
         fl->max_tru = mx;
+        fl->max_gap = mg;
     }
 }
 
@@ -404,9 +412,11 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     auto judge = [&](Flags fl_now) {   // after an FP64 true residual
         if (cur == PKM_FP64) return fl_now;
         if (fl_now.broke > 0) return escalate();
-        // a true residual above the right-hand side itself: the iteration
-        // diverges, the product is far too coarse for lambda
-        if (fl_now.live > 0 && fl_now.max_tru > 1.0) return escalate();
+        // a true residual above the right-hand side itself while the
+        // recursion believes it is 100 times smaller: the product is far
+        // too coarse for lambda (PCG residual norms alone may rise early on)
+        if (fl_now.live > 0 && fl_now.max_tru > 1.0 && fl_now.max_gap > 100.0)
+            return escalate();
         if (fl_now.live > 0 && mon.stalled(fl_now.max_tru)) {
             if (refining) return escalate();
             refining = true;
