@@ -176,11 +176,17 @@ int pkm_precond_destroy(pkm_precond* pc);
  * live column has stopped); if it fails, r is replaced by the true residual
  * and the column resumes.  With FP32 or BF16 products the same replacement
  * also runs every reliable_every steps.  A reduced-precision product whose
- * error is too large for lambda shows as a column breakdown or as a largest
- * true residual that fails to decrease over two replacement periods; the
- * solve then raises the product arithmetic (BF16 -> FP32 -> FP64), resumes
- * broken columns and restarts every column's directions from its FP64 true
- * residual (reported in prec_final).  A column converges when its FP64 true
+ * error is too large for lambda shows as a largest true residual that stops
+ * decreasing (three replacements in a row without falling below 0.7 of its
+ * best value), as a true residual above |b| while the recursive one is 100
+ * times smaller, or as a column breakdown.  On the first stall the columns
+ * switch to refinement mode: they restart their directions (p = z) at every
+ * replacement and stop stepping once the recursive residual is 1e-3 below
+ * the last true one (outer FP64 iterative refinement around short inner
+ * solves).  On a second stall, divergence or breakdown the solve raises the
+ * product arithmetic (BF16 -> FP32 -> FP64), resumes broken columns and
+ * restarts every column from its FP64 true residual (reported in
+ * prec_final).  A column converges when its FP64 true
  * relative residual is <= tol.  Returns PKM_NOT_CONVERGED if a column reached max_iter and
  * PKM_ERR_BREAKDOWN if one broke down; X holds the last iterate either way. */
 int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
@@ -197,6 +203,12 @@ int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
  * product is a work-queue launch per input-dimension class whose tile
  * shape is autotuned on first use (cached in memory and, if the
  * environment variable PKM_TUNE_CACHE names a file, there as JSON lines).
+ * A problem whose columns all stopped stepping is certified by its own FP64
+ * true residual at once; FP64 products run only for problems that need
+ * them.  A large problem is split over column ranges of K (partial sums
+ * added in a fixed order) when its row blocks alone would leave the chip
+ * idle.  Stalls are handled per problem as in pkm_solve (refinement mode,
+ * then FP64 products for that problem only; infos[b].prec_final).
  * prec PKM_FP32 (with FP64 residual replacement) or PKM_FP64;
  * 1 <= k <= 33, every d <= 34 for PKM_FP32.                                */
 int pkm_solve_batched(pkm_ctx* ctx, int32_t P, const pkm_problem* probs,
