@@ -69,6 +69,9 @@ extern "C" {
 #define PKM_PC_SKETCH   4   /* P = K S (S^T K S)^-1 S^T K + lambda I: Nystrom
                                with a general n x m sketch S (Section 3.1 is the
                                case S = columns of I at the inducing points)   */
+#define PKM_PC_PITC     5   /* P = Q + blockdiag(K - Q) + lambda I over blocks
+                               of consecutive rows (Section 3.1.1); set up by
+                               pkm_precond_setup_pitc                          */
 
 /* ---- per-column solver status ------------------------------------------ */
 #define PKM_COL_CONVERGED  0
@@ -161,6 +164,16 @@ int pkm_precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int32_t kind,
                       int32_t m, const int32_t* idx, const double* Phi,
                       double jitter, pkm_precond** out);
 /* Z = P^-1 R for R, Z device n x k FP64 (may not alias).                   */
+/* PITC (Section 3.1.1): Nystrom's Q with its error corrected exactly on
+ * diagonal blocks of `block` consecutive rows (1 <= block <= 64; the last
+ * block may be shorter): P = Q + blockdiag(K - Q) + lambda I.  Block 1 is
+ * FITC without its clip at zero.  The blocks are only as useful as the
+ * caller's ordering of X makes them (e.g. rows sorted along a space-filling
+ * curve).  Inducing points and jitter as for NYSTROM.  Not accepted by
+ * pkm_solve_batched (PKM_ERR_UNSUPPORTED).                                 */
+int pkm_precond_setup_pitc(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
+                           const int32_t* idx, int32_t block, double jitter,
+                           pkm_precond** out);
 int pkm_precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int32_t k,
                       const double* R, double* Z);
 /* Host copy of the preconditioner's diagonal part D (n values).           */

@@ -12,6 +12,13 @@ K_UX.  The diagonal D = diag(K - Q) + lambda I takes the place of lambda I:
     P^{-1} v = D^{-1} v - D^{-1} K_XU (K_UU + K_UX D^{-1} K_XU)^{-1} K_UX D^{-1} v.
 diag(K - Q) is clipped at zero against rounding.
 
+Section 3.1.1 (PITC): the same with the diagonal correction widened to
+blocks of consecutive rows B_1, B_2, ... (size ``block``, the last one
+ragged): D = blockdiag(K_BB - Q_BB) + lambda I, P = Q + D, and
+    P^{-1} v = D^{-1} v - D^{-1} K_XU (K_UU + K_UX D^{-1} K_XU)^{-1} K_UX D^{-1} v
+with D^{-1} applied block by block.  Block size 1 is FITC (up to FITC's
+clipping); one block of all n rows is K + lambda I itself.
+
 Section 3.2 (factor form): P = Phi Phi^T + lambda I,
     P^{-1} v = lambda^{-1} [ v - Phi (lambda I + Phi^T Phi)^{-1} Phi^T v ],
 again with lambda restored in the core (printed as I + Phi^T Phi).
@@ -91,6 +98,44 @@ def fitc(X, sigma2, lengthscales, lam, idx, jitter=0.0):
         return Kxu @ np.linalg.solve(Kuu, Kxu.T) + np.diag(D)
 
     return Preconditioner(apply, dense, {"D": D, "Kxu": Kxu, "Kuu": Kuu})
+
+
+def pitc(X, sigma2, lengthscales, lam, idx, block, jitter=0.0):
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    Xu = X[np.asarray(idx)]
+    Kuu = rbf_block(Xu, Xu, sigma2, lengthscales) + jitter * np.eye(len(idx))
+    Kxu = rbf_block(X, Xu, sigma2, lengthscales)
+    starts = list(range(0, n, block))
+    Dblocks = []
+    for s0 in starts:
+        s1 = min(n, s0 + block)
+        Kbb = rbf_block(X[s0:s1], X[s0:s1], sigma2, lengthscales)
+        Qbb = Kxu[s0:s1] @ np.linalg.solve(Kuu, Kxu[s0:s1].T)
+        Dblocks.append(Kbb - Qbb + lam * np.eye(s1 - s0))
+
+    def dinv(R):
+        out = np.empty_like(R)
+        for s0, Db in zip(starts, Dblocks):
+            out[s0:s0 + Db.shape[0]] = np.linalg.solve(Db, R[s0:s0 + Db.shape[0]])
+        return out
+
+    DKxu = dinv(Kxu)
+    core = Kuu + Kxu.T @ DKxu
+
+    def apply(R):
+        R2 = R if R.ndim == 2 else R[:, None]
+        DR = dinv(R2)
+        out = DR - DKxu @ np.linalg.solve(core, Kxu.T @ DR)
+        return out if R.ndim == 2 else out[:, 0]
+
+    def dense():
+        D = np.zeros((n, n))
+        for s0, Db in zip(starts, Dblocks):
+            D[s0:s0 + Db.shape[0], s0:s0 + Db.shape[0]] = Db
+        return Kxu @ np.linalg.solve(Kuu, Kxu.T) + D
+
+    return Preconditioner(apply, dense, {"Dblocks": Dblocks, "Kxu": Kxu, "Kuu": Kuu})
 
 
 def sketch(X, sigma2, lengthscales, lam, S, jitter=0.0):

@@ -10,7 +10,7 @@
 
 namespace pkm {
 void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const int32_t* idx,
-                   const double* Phi, double jitter, pkm_precond* pc);
+                   const double* Phi, double jitter, pkm_precond* pc, int block);
 int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, const double* B,
           double* X, const pkm_solve_opts* o, pkm_solve_info* info);
 int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_precond* const* pcs,
@@ -128,6 +128,7 @@ int pkm_destroy(pkm_ctx* ctx) {
         b->release();
     for (auto& b : ctx->pcg) b.release();
     for (auto& b : ctx->ws_setup) b.release();
+    for (auto& b : ctx->ws_pitc) b.release();
     for (auto& b : ctx->batch) b.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -188,7 +189,32 @@ int pkm_precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int32_t kind, int32
             PKM_REQUIRE((reinterpret_cast<uintptr_t>(idx) & 3) == 0, "idx must be 4-byte aligned");
         }
         pc = new pkm_precond();
-        precond_setup(ctx, prob, kind, m, idx, Phi, jitter, pc);
+        precond_setup(ctx, prob, kind, m, idx, Phi, jitter, pc, 0);
+        return PKM_OK;
+    });
+    if (rc != PKM_OK) {
+        if (pc) pkm_precond_destroy(pc);
+        return rc;
+    }
+    *out = pc;
+    return PKM_OK;
+}
+
+int pkm_precond_setup_pitc(pkm_ctx* ctx, const pkm_problem* prob, int32_t m, const int32_t* idx,
+                           int32_t block, double jitter, pkm_precond** out) {
+    if (!ctx) return PKM_ERR_INVALID;
+    if (out) *out = nullptr;
+    pkm_precond* pc = nullptr;
+    int rc = guarded(ctx, [&] {
+        PKM_REQUIRE(out != nullptr, "out is NULL");
+        validate_problem(prob);
+        PKM_REQUIRE(m >= 1 && m <= 4096 && m <= prob->n, "m must be in [1, min(n, 4096)]");
+        PKM_REQUIRE(block >= 1 && block <= 64, "block must be in [1, 64]");
+        PKM_REQUIRE(std::isfinite(jitter) && jitter >= 0.0, "jitter must be >= 0");
+        PKM_REQUIRE(idx != nullptr, "idx is NULL");
+        PKM_REQUIRE((reinterpret_cast<uintptr_t>(idx) & 3) == 0, "idx must be 4-byte aligned");
+        pc = new pkm_precond();
+        precond_setup(ctx, prob, PKM_PC_PITC, m, idx, nullptr, jitter, pc, block);
         return PKM_OK;
     });
     if (rc != PKM_OK) {
@@ -233,6 +259,7 @@ int pkm_precond_destroy(pkm_precond* pc) {
     (void)hipDeviceSynchronize();
     pc->psi.release();
     pc->dinv.release();
+    pc->dblk.release();
     delete pc;
     return PKM_OK;
 }
@@ -291,6 +318,8 @@ int pkm_solve_batched(pkm_ctx* ctx, int32_t P, const pkm_problem* probs,
             if (pcs && pcs[b]) {
                 PKM_REQUIRE(pcs[b]->n == probs[b].n, "preconditioner built for another n");
                 PKM_REQUIRE(pcs[b]->device == ctx->device, "preconditioner on another device");
+                if (pcs[b]->kind == PKM_PC_PITC)
+                    fail(PKM_ERR_UNSUPPORTED, "batched solve: PITC preconditioners are not supported");
             }
         }
         return solve_batched(ctx, P, probs, pcs, k, B, X, &o, infos);

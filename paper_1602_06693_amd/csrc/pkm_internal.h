@@ -137,6 +137,7 @@ struct pkm_ctx {
     // scratch (grow-only), by purpose
     pkm::DevBuf vbf, v32, y32, v64pad, y64pad, red, red2, scal, state, pcg[8], grad;
     pkm::DevBuf ws_split, ws_tmp, ws_setup[4];
+    pkm::DevBuf ws_pitc[2];             // PITC setup: block inverses, L_D^-1 Phi
     pkm::DevBuf batch[16];              // batched-solve workspace
     void* pinned = nullptr;   // pinned host staging area (PKM_PINNED_BYTES)
 };
@@ -146,8 +147,10 @@ struct pkm_precond {
     int64_t n = 0;
     int m = 0;
     int device = 0;
-    pkm::DevBuf psi;    // n x m FP64: P^-1 = diag(dinv) - psi psi^T
-    pkm::DevBuf dinv;   // n FP64
+    pkm::DevBuf psi;    // n x m FP64: P^-1 = D^-1 - psi psi^T
+    pkm::DevBuf dinv;   // n FP64: 1 / diag(D)
+    int block = 0;      // PITC: block size b; dblk holds blockdiag(D^-1), n x b
+    pkm::DevBuf dblk;
 };
 
 // Learned factor network (mlp.hip).

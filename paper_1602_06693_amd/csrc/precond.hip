@@ -9,6 +9,8 @@
 //            then Phi Phi^T = K_XU K_UU^-1 K_UX.
 //   FITC     same Phi, D = max(diag(K - Phi Phi^T), 0) + lambda.
 //   LOWRANK  Phi given by the caller, D = lambda I.
+//   SKETCH   Phi = K S L^-T (L L^T = S^T K S + jitter), D = lambda I.
+//   PITC     Nystrom's Phi, D block diagonal (see the PITC kernels below).
 // Scaling Phi by D^-1/2 before forming C keeps the core well conditioned:
 // C's eigenvalues are 1 + (those of Phi^T D^-1 Phi) >= 1.
 //
@@ -95,13 +97,201 @@ __global__ void k_check_idx(const int32_t* __restrict__ idx, int m, int64_t n, i
     if (i < m && (idx[i] < 0 || idx[i] >= n)) atomicOr(bad, 1);
 }
 
+// ---------------------------------------------------------------------------
+// PITC (Section 3.1.1): D = blockdiag(K_BB - Phi_B Phi_B^T) + lambda I over
+// consecutive row blocks of size b (last block ragged).  With block Cholesky
+// D_B = L_B L_B^T the unified form holds with L_D^-1 in place of D^-1/2:
+//     Phi~ = L_D^-1 Phi,  C = I + Phi~^T Phi~ = L_C L_C^T,
+//     Psi = L_D^-T Phi~ L_C^-T,   P^-1 = D^-1 - Psi Psi^T.
+// Blocks are stored row-major per row: element (i, lj) at i * b + lj is
+// block(i)'s entry (i mod b, lj); columns past a ragged block's size are 0.
+// ---------------------------------------------------------------------------
+__global__ void k_pitc_blocks(const double* __restrict__ xs, int64_t n, int d, double sigma2,
+                              double lambda, const double* __restrict__ phi, int m, int b,
+                              double* __restrict__ Dblk) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= n * b) return;
+    const int64_t i = e / b;
+    const int lj = int(e - i * b);
+    const int64_t j = (i / b) * b + lj;
+    if (j >= n) {
+        Dblk[e] = 0.0;
+        return;
+    }
+    double sq = 0.0;
+    for (int r = 0; r < d; ++r) {
+        const double t = xs[i * d + r] - xs[j * d + r];
+        sq = fma(t, t, sq);
+    }
+    double q = 0.0;
+    const double* pi = phi + i * m;
+    const double* pj = phi + j * m;
+    for (int c = 0; c < m; ++c) q = fma(pi[c], pj[c], q);
+    Dblk[e] = sigma2 * exp(-0.5 * sq) - q + (i == j ? lambda : 0.0);
+}
+
+// One work-group per block: Cholesky D_B = L L^T in LDS, then L^-1 (written
+// to Linv) and D_B^-1 = L^-T L^-1 (written over Dblk).  b <= 64.  info gets
+// 1 + (first failing block) if a pivot is not positive.
+constexpr int kPitcMaxBlock = 64;
+__global__ __launch_bounds__(256) void k_pitc_factor(int64_t n, int b, double* __restrict__ Dblk,
+                                                     double* __restrict__ Linv,
+                                                     int* __restrict__ info) {
+    __shared__ double A[kPitcMaxBlock][kPitcMaxBlock + 1];
+    __shared__ double Li[kPitcMaxBlock][kPitcMaxBlock + 1];
+    __shared__ int bad;
+    const int64_t r0 = int64_t(blockIdx.x) * b;
+    const int bs = int(min(int64_t(b), n - r0));
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    for (int e = tid; e < bs * bs; e += blockDim.x) {
+        const int li = e / bs, lj = e - li * bs;
+        A[li][lj] = Dblk[(r0 + li) * b + lj];
+        Li[li][lj] = 0.0;
+    }
+    __syncthreads();
+    // right-looking Cholesky, lower triangle
+    for (int j = 0; j < bs; ++j) {
+        const double piv = A[j][j];
+        if (!(piv > 0.0)) {
+            if (tid == 0) bad = 1;
+            break;   // uniform: every thread reads the same A[j][j]
+        }
+        const double lj = sqrt(piv);
+        __syncthreads();
+        for (int i = j + tid; i < bs; i += blockDim.x) A[i][j] = (i == j) ? lj : A[i][j] / lj;
+        __syncthreads();
+        const int rem = bs - j - 1;
+        for (int e = tid; e < rem * rem; e += blockDim.x) {
+            const int i = j + 1 + e / rem, c = j + 1 + e % rem;
+            if (c <= i) A[i][c] -= A[i][j] * A[c][j];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) atomicCAS(info, 0, int(blockIdx.x) + 1);
+        return;
+    }
+    // L^-1 column by column (forward substitution), one thread per column
+    for (int c = tid; c < bs; c += blockDim.x) {
+        for (int i = c; i < bs; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int t = c; t < i; ++t) s -= A[i][t] * Li[t][c];
+            Li[i][c] = s / A[i][i];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < b * b; e += blockDim.x) {
+        const int li = e / b, lj = e - li * b;
+        if (li >= bs) continue;
+        double inv = 0.0, dinvv = 0.0;
+        if (lj < bs) {
+            inv = Li[li][lj];
+            const int t0 = li > lj ? li : lj;
+            for (int t = t0; t < bs; ++t) dinvv = fma(Li[t][li], Li[t][lj], dinvv);
+        }
+        Linv[(r0 + li) * b + lj] = inv;
+        Dblk[(r0 + li) * b + lj] = dinvv;
+    }
+}
+
+// out = blockdiag(L^-1) in (trans = 0) or blockdiag(L^-T) in (trans = 1),
+// in / out n x m row-major, distinct.
+__global__ void k_pitc_tri_mul(int64_t n, int b, const double* __restrict__ Linv, int trans,
+                               const double* __restrict__ in, int m, double* __restrict__ out) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= n * m) return;
+    const int64_t i = e / m;
+    const int c = int(e - i * m);
+    const int64_t r0 = (i / b) * b;
+    const int li = int(i - r0);
+    const int bs = int(min(int64_t(b), n - r0));
+    double s = 0.0;
+    if (!trans) {
+        for (int t = 0; t <= li; ++t) s = fma(Linv[i * b + t], in[(r0 + t) * m + c], s);
+    } else {
+        for (int t = li; t < bs; ++t) s = fma(Linv[(r0 + t) * b + li], in[(r0 + t) * m + c], s);
+    }
+    out[e] = s;
+}
+
+// Z = blockdiag(D^-1) R (R, Z n x k row-major, distinct)
+__global__ void k_pitc_dinv(int64_t n, int b, const double* __restrict__ Dinv,
+                            const double* __restrict__ R, int k, double* __restrict__ Z) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= n * k) return;
+    const int64_t i = e / k;
+    const int c = int(e - i * k);
+    const int64_t r0 = (i / b) * b;
+    const int bs = int(min(int64_t(b), n - r0));
+    double s = 0.0;
+    for (int t = 0; t < bs; ++t) s = fma(Dinv[i * b + t], R[(r0 + t) * k + c], s);
+    Z[e] = s;
+}
+
+// 1 / D_ii from the (not yet inverted) blocks, for pkm_precond_diag
+__global__ void k_pitc_diag_recip(int64_t n, int b, const double* __restrict__ Dblk,
+                                  double* __restrict__ dinv) {
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    dinv[i] = 1.0 / Dblk[i * b + (i % b)];
+}
+
 static void read_info(pkm_ctx* ctx, const int* dinfo, int* out) {
     PKM_HIP(hipMemcpyAsync(out, dinfo, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     PKM_HIP(hipStreamSynchronize(ctx->stream));
 }
 
+// PITC from Nystrom's Phi (already in pc->psi): block factors, Phi~, core,
+// Psi.  Scratch: Linv (n x b), Phi~ (n x m).
+static void setup_pitc(pkm_ctx* ctx, const pkm_problem* prob, int m, int b, pkm_precond* pc) {
+    const int64_t n = prob->n;
+    hipStream_t s = ctx->stream;
+    double* psi = pc->psi.as<double>();
+    pc->block = b;
+    pc->dblk.ensure(sizeof(double) * n * b);
+    double* Dblk = pc->dblk.as<double>();
+    ctx->ws_pitc[0].ensure(sizeof(double) * n * b);
+    ctx->ws_pitc[1].ensure(sizeof(double) * n * m);
+    double* Linv = ctx->ws_pitc[0].as<double>();
+    double* ptil = ctx->ws_pitc[1].as<double>();
+    double* core = ctx->ws_setup[0].as<double>();
+    double* winv = ctx->ws_setup[1].as<double>();
+    int* dinfo = ctx->ws_setup[3].as<int>();
+    int hinfo = 0;
+    const double* xs = ctx->P().xs64.as<double>();
+    k_pitc_blocks<<<cdiv(n * b, 256), 256, 0, s>>>(xs, n, prob->d, prob->sigma2, prob->lambda,
+                                                   psi, m, b, Dblk);
+    PKM_CHECK_LAUNCH();
+    k_pitc_diag_recip<<<cdiv(n, 256), 256, 0, s>>>(n, b, Dblk, pc->dinv.as<double>());   // 1 / D_ii
+    PKM_CHECK_LAUNCH();
+    PKM_HIP(hipMemsetAsync(dinfo, 0, sizeof(int), s));
+    k_pitc_factor<<<(unsigned)cdiv(n, b), 256, 0, s>>>(n, b, Dblk, Linv, dinfo);
+    PKM_CHECK_LAUNCH();
+    read_info(ctx, dinfo, &hinfo);
+    if (hinfo != 0)
+        fail(PKM_ERR_BREAKDOWN, "PITC: diagonal block " + std::to_string(hinfo - 1) +
+                                    " of K - Q + lambda I is not positive definite");
+    // Phi~ = L_D^-1 Phi;  C = I + Phi~^T Phi~;  Phi~ L_C^-T;  Psi = L_D^-T (.)
+    k_pitc_tri_mul<<<cdiv(n * m, 256), 256, 0, s>>>(n, b, Linv, 0, psi, m, ptil);
+    PKM_CHECK_LAUNCH();
+    dgemm(ctx, true, false, m, m, n, 1.0, ptil, m, ptil, m, 0.0, core, m);
+    k_identity_plus<<<cdiv(int64_t(m) * m, 256), 256, 0, s>>>(m, core);
+    PKM_CHECK_LAUNCH();
+    dpotrf_lower(ctx, m, core, m, winv, dinfo);
+    read_info(ctx, dinfo, &hinfo);
+    if (hinfo != 0)
+        fail(PKM_ERR_BREAKDOWN, "Woodbury core I + Phi^T D^-1 Phi is not positive definite "
+                                "(non-finite factor?)");
+    dtrsm_right_lt(ctx, n, m, core, m, winv, ptil, m);
+    k_pitc_tri_mul<<<cdiv(n * m, 256), 256, 0, s>>>(n, b, Linv, 1, ptil, m, psi);
+    PKM_CHECK_LAUNCH();
+    PKM_HIP(hipStreamSynchronize(s));
+}
+
 void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const int32_t* idx,
-                   const double* Phi, double jitter, pkm_precond* pc) {
+                   const double* Phi, double jitter, pkm_precond* pc, int block) {
     const int64_t n = prob->n;
     hipStream_t s = ctx->stream;
     prepare(ctx, prob, true, false);
@@ -124,7 +314,7 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const
     int* dinfo = ctx->ws_setup[3].as<int>();
     int hinfo = 0;
 
-    if (kind == PKM_PC_NYSTROM || kind == PKM_PC_FITC) {
+    if (kind == PKM_PC_NYSTROM || kind == PKM_PC_FITC || kind == PKM_PC_PITC) {
         PKM_HIP(hipMemsetAsync(dinfo, 0, sizeof(int), s));
         k_check_idx<<<cdiv(m, 256), 256, 0, s>>>(idx, m, n, dinfo);
         PKM_CHECK_LAUNCH();
@@ -147,6 +337,10 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const
         // Phi = K_XU L_U^-T
         rbf_cross64(s, xs, nullptr, n, xs, idx, m, d, prob->sigma2, psi, m);
         dtrsm_right_lt(ctx, n, m, core, m, winv, psi, m);
+        if (kind == PKM_PC_PITC) {
+            setup_pitc(ctx, prob, m, block, pc);
+            return;
+        }
         k_diag_d<<<cdiv(n, 256), 256, 0, s>>>(psi, n, m, kind == PKM_PC_FITC, prob->sigma2,
                                               prob->lambda, D);
         PKM_CHECK_LAUNCH();
@@ -323,7 +517,8 @@ __global__ __launch_bounds__(256) void k_apply_z(const double* __restrict__ psi,
         for (int r = 0; r < 4; ++r) {
             const int64_t i = row0 + g + 4 * r;
             const int c = c0 + 16 * kt + rr;
-            if (i < n && c < k) Z[i * k + c] = dinv[i] * R[i * k + c] - acc[kt][r];
+            if (i < n && c < k)
+                Z[i * k + c] = (dinv ? dinv[i] * R[i * k + c] : Z[i * k + c]) - acc[kt][r];
         }
 }
 
@@ -351,12 +546,19 @@ static void apply_chunk(pkm_ctx* ctx, const pkm_precond* pc, int k, int c0, cons
     k_sum_chunks<<<cdiv(int64_t(m_pad) * ldt, 64), 256, 0, s>>>(part, int(nchunk), m, k, c0, kc,
                                                                 m_pad, ldt, T);
     PKM_CHECK_LAUNCH();
-    k_apply_z<KT><<<(unsigned)cdiv(n, 64), 256, 0, s>>>(pc->psi.as<double>(), m, T, ldt,
-                                                        pc->dinv.as<double>(), R, k, c0, n, Z);
+    // PITC: Z already holds blockdiag(D^-1) R; the kernel subtracts Psi T
+    const double* dv = pc->kind == PKM_PC_PITC ? nullptr : pc->dinv.as<double>();
+    k_apply_z<KT><<<(unsigned)cdiv(n, 64), 256, 0, s>>>(pc->psi.as<double>(), m, T, ldt, dv, R,
+                                                        k, c0, n, Z);
     PKM_CHECK_LAUNCH();
 }
 
 void precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int k, const double* R, double* Z) {
+    if (pc->kind == PKM_PC_PITC) {
+        k_pitc_dinv<<<cdiv(pc->n * k, 256), 256, 0, ctx->stream>>>(pc->n, pc->block,
+                                                                   pc->dblk.as<double>(), R, k, Z);
+        PKM_CHECK_LAUNCH();
+    }
     for (int c0 = 0; c0 < k;) {
         int rem = k - c0;
         if (rem > 17) { apply_chunk<33>(ctx, pc, k, c0, R, Z); c0 += 33; }

@@ -109,3 +109,64 @@ def test_sketch_apply_matches_oracle(ctx, n, m):
     # hence P^-1 inherit that level, amplified by at most cond(P)
     tol = 1e-5 * np.linalg.cond(P.dense()) ** 0.5
     assert np.all(rel_err(got, want) < tol), (rel_err(got, want), tol)
+
+
+@pytest.mark.parametrize("n,m,block", [(700, 64, 32), (333, 40, 64), (200, 16, 1), (257, 30, 17)])
+def test_pitc_apply_matches_oracle(ctx, n, m, block):
+    """PITC (Section 3.1.1): block-diagonal correction over consecutive rows,
+    ragged last block included."""
+    p = make("block_fp32", seed=23, n=n, m=m, n_probes=4)
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup_pitc(ctx, g.prob, m, g.idx, block, jitter=JIT)
+    try:
+        got = host(pk.pkm_precond_apply(ctx, pc, g.B))
+        P = op.pitc(p.X, p.sigma2, p.lengthscales, p.lam, p.idx, block, jitter=JIT)
+        want = P(p.B)
+        assert np.all(rel_err(got, want) < _tol(P)), (rel_err(got, want), _tol(P))
+        D = pk.pkm_precond_diag(ctx, pc, n)
+        Dw = np.concatenate([np.diag(Db) for Db in P.info["Dblocks"]])
+        assert np.allclose(D, Dw, rtol=1e-9, atol=1e-12)
+    finally:
+        pk.pkm_precond_destroy(pc)
+
+
+def test_pitc_solve_with_ordered_blocks(ctx):
+    """Rows sorted along the first coordinate make the blocks local; PCG with
+    PITC reaches the FP64 tolerance and takes no more steps than the
+    oracle's PCG with the same preconditioner (+10 % + 2)."""
+    from oracle import kernel as ok
+    from oracle.pcg import pcg
+    p = make("small_fp64", seed=24, n=1500, m=48, n_probes=2)
+    order = np.argsort(p.X[:, 0], kind="stable")
+    X = np.ascontiguousarray(p.X[order])
+    B = np.ascontiguousarray(p.B[order])
+    inv = np.empty_like(order)
+    inv[order] = np.arange(len(order))
+    idx = np.sort(inv[p.idx]).astype(np.int32)
+    prob = pk.Problem(dev(X), p.lengthscales, p.sigma2, p.lam)
+    pc = pk.pkm_precond_setup_pitc(ctx, prob, len(idx), dev(idx), 32, jitter=JIT)
+    try:
+        Xs, info = pk.pkm_solve(ctx, prob, dev(B), pc=pc,
+                                opts=pk.make_opts(tol=1e-8, prec=pk.PKM_FP64),
+                                allow_warning=False)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    r = B - ok.kernel_mvm(X, p.sigma2, p.lengthscales, p.lam, host(Xs))
+    assert np.all(np.linalg.norm(r, axis=0) / np.linalg.norm(B, axis=0) <= 1e-8 * 1.001)
+    P = op.pitc(X, p.sigma2, p.lengthscales, p.lam, idx, 32, jitter=JIT)
+    res = pcg(lambda v: ok.kernel_mvm(X, p.sigma2, p.lengthscales, p.lam, v), B, precond=P,
+              tol=1e-8)
+    assert np.all(info.iters <= 1.1 * res.iters + 2), (info.iters, res.iters)
+
+
+def test_pitc_rejected_by_batched_solve(ctx):
+    p = make("block_fp32", seed=25, n=300, m=20, n_probes=1)
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup_pitc(ctx, g.prob, 20, g.idx, 16, jitter=JIT)
+    try:
+        with pytest.raises(pk.PkmError) as e:
+            pk.pkm_solve_batched(ctx, [g.prob], [g.B], pcs=[pc],
+                                 opts=pk.make_opts(tol=1e-6, prec=pk.PKM_FP64))
+        assert e.value.code == pk.PKM_ERR_UNSUPPORTED
+    finally:
+        pk.pkm_precond_destroy(pc)

@@ -103,3 +103,44 @@ def test_sketch_never_exceeds_K_and_full_sketch_is_exact():
     res = pcg(lambda V: ok.kernel_mvm(X2, 1.0, np.array([0.3, 0.4, 0.5]), 1e-2, V), B,
               precond=Pf, tol=1e-9, max_iter=20)
     assert np.all(res.iters == 1)
+
+
+def test_pitc_apply_equals_dense_solve_and_blocks_match_K():
+    """PITC (Section 3.1.1): apply equals a dense solve with P = Q +
+    blockdiag(K - Q) + lambda I, and P's diagonal blocks are K's plus lambda I
+    exactly (the correction restores them)."""
+    rng = np.random.default_rng(21)
+    X = rng.random((150, 3))
+    ls = np.array([0.4, 0.7, 1.1])
+    idx = np.sort(rng.choice(150, 20, replace=False))
+    lam, blk = 1e-2, 32
+    P = op.pitc(X, 1.3, ls, lam, idx, blk, jitter=1e-8)
+    Pd = P.dense()
+    R = rng.standard_normal((150, 3))
+    want = np.linalg.solve(Pd, R)
+    # both sides go through K_UU^-1 (condition ~1e8 with this jitter)
+    np.testing.assert_allclose(P(R), want, rtol=0, atol=1e-8 * np.abs(want).max())
+    K = ok.kernel_matrix(X, 1.3, ls)
+    for s0 in range(0, 150, blk):
+        s1 = min(150, s0 + blk)
+        np.testing.assert_allclose(Pd[s0:s1, s0:s1], K[s0:s1, s0:s1] + lam * np.eye(s1 - s0),
+                                   rtol=0, atol=1e-10)
+
+
+def test_pitc_limits_fitc_and_exact():
+    """Block size 1 is FITC; a single block of all rows is K + lambda I, so
+    PCG with it stops after one step."""
+    rng = np.random.default_rng(22)
+    X = rng.random((90, 2))
+    ls = np.array([0.5, 0.8])
+    idx = np.sort(rng.choice(90, 12, replace=False))
+    lam = 1e-2
+    P1 = op.pitc(X, 1.0, ls, lam, idx, 1, jitter=1e-10)
+    F = op.fitc(X, 1.0, ls, lam, idx, jitter=1e-10)
+    np.testing.assert_allclose(P1.dense(), F.dense(), rtol=0, atol=1e-9)
+    Pn = op.pitc(X, 1.0, ls, lam, idx, 90, jitter=1e-10)
+    Ky = ok.kernel_matrix(X, 1.0, ls) + lam * np.eye(90)
+    np.testing.assert_allclose(Pn.dense(), Ky, rtol=0, atol=1e-10)
+    b = np.sin(3 * X).sum(axis=1)
+    res = pcg(lambda v: Ky @ v, b, precond=Pn, tol=1e-10)
+    assert res.iters <= 2
