@@ -127,9 +127,10 @@ def mvm_only(pk, ctx, prob, p, steps, prec_names, ks):
 
 def hyper_mode(pk, ctx, p, a):
     """Section 5 loop: ADAGRAD steps on (log sigma2, log l); at every step the
-    Nystrom arm (fresh m inducing points) and the learned arm (factor network
-    fine-tuned on K Z probe pairs, sketch-Nystrom factor) solve the same
-    systems; the Nystrom arm's gradient drives theta."""
+    Nystrom arm (fresh m inducing points), the learned arm (the same inducing
+    points enlarged by the factor network's r columns, fine-tuned on probe
+    pairs (Z, (K - Q) Z)) and a control Nystrom arm with m + r inducing
+    points solve the same systems; the Nystrom arm's gradient drives theta."""
     import torch
 
     from paper_1602_06693_amd import hyper
@@ -140,9 +141,12 @@ def hyper_mode(pk, ctx, p, a):
     opts = pk.make_opts(tol=p.tol, prec=precs[a.prec], reliable_every=a.reliable)
     theta0 = hyper.theta_of(p.sigma2, p.lengthscales)
     log = lambda msg: print(msg, file=sys.stderr, flush=True)
-    learned = hyper.LearnedArm(ctx, mlp_params(a.seed, d_in=p.d, rank=a.rank), p.d, a.rank,
-                               log=log)
-    arms = [hyper.NystromArm(p.n, len(p.idx), seed=a.seed), learned]
+    m = len(p.idx)
+    learned = hyper.LearnedArm(ctx, mlp_params(a.seed, d_in=p.d, rank=a.rank, out_scale=0.1),
+                               p.d, a.rank, p.n, m, seed=a.seed, log=log)
+    # control: as many extra random inducing points as the learned columns
+    arms = [hyper.NystromArm(p.n, m, seed=a.seed), learned,
+            hyper.NystromArm(p.n, m + a.rank, seed=a.seed, name=f"nystrom_m{m + a.rank}")]
     t0 = time.perf_counter()
     try:
         traj, rec = hyper.run(ctx, dev(p.X), dev(p.y), dev(p.Z), theta0, p.lam, arms,

@@ -72,6 +72,9 @@ extern "C" {
 #define PKM_PC_PITC     5   /* P = Q + blockdiag(K - Q) + lambda I over blocks
                                of consecutive rows (Section 3.1.1); set up by
                                pkm_precond_setup_pitc                          */
+#define PKM_PC_HYBRID   6   /* SKETCH with S = [columns of I at inducing points,
+                               a learned n x r factor U]; set up by
+                               pkm_precond_setup_hybrid                        */
 
 /* ---- per-column solver status ------------------------------------------ */
 #define PKM_COL_CONVERGED  0
@@ -174,6 +177,23 @@ int pkm_precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int32_t kind,
 int pkm_precond_setup_pitc(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
                            const int32_t* idx, int32_t block, double jitter,
                            pkm_precond** out);
+/* Nystrom on the hybrid sketch S = [E_U, U]: E_U the m columns of the
+ * identity at the inducing indices idx (device, m distinct in [0, n)), U a
+ * device n x r FP64 array (e.g. the learned factor).  P = K S (S^T K S +
+ * jitter * mean-diagonal I)^-1 S^T K + lambda I: the Section 3.1 Nystrom
+ * preconditioner enlarged by the span of K U, so its low-rank part never
+ * exceeds K and grows monotonically with the sketch.  K_XU and K U (one
+ * FP64 product) in FP64.  m, r >= 1, m + r <= min(n, 4096), d <= 34.       */
+int pkm_precond_setup_hybrid(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
+                             const int32_t* idx, int32_t r, const double* U,
+                             double jitter, pkm_precond** out);
+/* Y <- Y - Phi Phi^T V for device n x k FP64 blocks V, Y (distinct), where
+ * Phi Phi^T is the low-rank part of P = D + Phi Phi^T (for Nystrom, FITC and
+ * PITC: Q = K_XU K_UU^-1 K_UX).  With Y = K V on entry this leaves
+ * (K - Q) V, the part of K the preconditioner misses (training pairs for a
+ * learned correction).  Two FP64 products with the stored n x m factor.    */
+int pkm_precond_sub_lowrank(pkm_ctx* ctx, const pkm_precond* pc, int32_t k,
+                            const double* V, double* Y);
 int pkm_precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int32_t k,
                       const double* R, double* Z);
 /* Host copy of the preconditioner's diagonal part D (n values).           */

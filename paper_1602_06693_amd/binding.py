@@ -34,6 +34,7 @@ PKM_PC_FITC = 2
 PKM_PC_LOWRANK = 3
 PKM_PC_SKETCH = 4
 PKM_PC_PITC = 5
+PKM_PC_HYBRID = 6
 
 PKM_COL_CONVERGED = 0
 PKM_COL_MAX_ITER = 1
@@ -43,7 +44,8 @@ PKM_COL_BREAKDOWN = 2
 EXPORTS = (
     "pkm_create", "pkm_destroy", "pkm_last_error", "pkm_version", "pkm_kernel_mvm",
     "pkm_kernel_mvm_shift",
-    "pkm_precond_setup", "pkm_precond_setup_pitc", "pkm_precond_apply", "pkm_precond_diag", "pkm_precond_destroy",
+    "pkm_precond_setup", "pkm_precond_setup_pitc",
+    "pkm_precond_setup_hybrid", "pkm_precond_sub_lowrank", "pkm_precond_apply", "pkm_precond_diag", "pkm_precond_destroy",
     "pkm_solve", "pkm_solve_batched", "pkm_grad_pass", "pkm_lml_grad", "pkm_timing_enable", "pkm_mvm_stats",
     "pkm_mvm_stats_reset", "pkm_mlp_create", "pkm_mlp_destroy", "pkm_mlp_params",
     "pkm_mlp_forward", "pkm_mlp_loss_grad", "pkm_mlp_train_step", "pkm_adagrad_step",
@@ -98,6 +100,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "pkm_kernel_mvm_shift": (C.c_int, [vp, P(pkm_problem), i32, i32, dbl, vp, vp]),
         "pkm_precond_setup": (C.c_int, [vp, P(pkm_problem), i32, i32, vp, vp, dbl, P(vp)]),
         "pkm_precond_setup_pitc": (C.c_int, [vp, P(pkm_problem), i32, vp, i32, dbl, P(vp)]),
+        "pkm_precond_setup_hybrid": (C.c_int, [vp, P(pkm_problem), i32, vp, i32, vp, dbl,
+                                               P(vp)]),
+        "pkm_precond_sub_lowrank": (C.c_int, [vp, vp, i32, vp, vp]),
         "pkm_precond_apply": (C.c_int, [vp, vp, i32, vp, vp]),
         "pkm_precond_diag": (C.c_int, [vp, vp, P(dbl)]),
         "pkm_precond_destroy": (C.c_int, [vp]),
@@ -226,6 +231,21 @@ def pkm_precond_setup_pitc(ctx, prob: Problem, m, idx, block, jitter=0.0):
     _check(load().pkm_precond_setup_pitc(ctx, prob.ref, int(m), _ptr(idx, "int32"), int(block),
                                          float(jitter), C.byref(out)), ctx)
     return out
+
+
+def pkm_precond_setup_hybrid(ctx, prob: Problem, m, idx, U, jitter=0.0):
+    out = C.c_void_p()
+    _check(load().pkm_precond_setup_hybrid(ctx, prob.ref, int(m), _ptr(idx, "int32"),
+                                           int(U.shape[1]), _ptr(U), float(jitter),
+                                           C.byref(out)), ctx)
+    return out
+
+
+def pkm_precond_sub_lowrank(ctx, pc, V, Y):
+    """Y <- Y - Phi Phi^T V in place; returns Y."""
+    k = V.shape[1] if V.dim() == 2 else 1
+    _check(load().pkm_precond_sub_lowrank(ctx, pc, k, _ptr(V), _ptr(Y)), ctx)
+    return Y
 
 
 def pkm_precond_apply(ctx, pc, R, Z=None):

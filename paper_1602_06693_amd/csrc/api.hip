@@ -10,7 +10,8 @@
 
 namespace pkm {
 void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const int32_t* idx,
-                   const double* Phi, double jitter, pkm_precond* pc, int block);
+                   const double* Phi, double jitter, pkm_precond* pc, int aux);
+void precond_sub_lowrank(pkm_ctx* ctx, const pkm_precond* pc, int k, const double* V, double* Y);
 int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, const double* B,
           double* X, const pkm_solve_opts* o, pkm_solve_info* info);
 int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_precond* const* pcs,
@@ -225,6 +226,49 @@ int pkm_precond_setup_pitc(pkm_ctx* ctx, const pkm_problem* prob, int32_t m, con
     return PKM_OK;
 }
 
+int pkm_precond_setup_hybrid(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
+                             const int32_t* idx, int32_t r, const double* U, double jitter,
+                             pkm_precond** out) {
+    if (!ctx) return PKM_ERR_INVALID;
+    if (out) *out = nullptr;
+    pkm_precond* pc = nullptr;
+    int rc = guarded(ctx, [&] {
+        PKM_REQUIRE(out != nullptr, "out is NULL");
+        validate_problem(prob);
+        PKM_REQUIRE(prob->d <= 34, "hybrid preconditioner needs d <= 34");
+        PKM_REQUIRE(m >= 1 && r >= 1 && int64_t(m) + r <= 4096 && int64_t(m) + r <= prob->n,
+                    "m, r >= 1 and m + r <= min(n, 4096)");
+        PKM_REQUIRE(std::isfinite(jitter) && jitter >= 0.0, "jitter must be >= 0");
+        PKM_REQUIRE(idx != nullptr, "idx is NULL");
+        PKM_REQUIRE((reinterpret_cast<uintptr_t>(idx) & 3) == 0, "idx must be 4-byte aligned");
+        require_dev(U, "U");
+        pc = new pkm_precond();
+        precond_setup(ctx, prob, PKM_PC_HYBRID, m, idx, U, jitter, pc, r);
+        return PKM_OK;
+    });
+    if (rc != PKM_OK) {
+        if (pc) pkm_precond_destroy(pc);
+        return rc;
+    }
+    *out = pc;
+    return PKM_OK;
+}
+
+int pkm_precond_sub_lowrank(pkm_ctx* ctx, const pkm_precond* pc, int32_t k, const double* V,
+                            double* Y) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        PKM_REQUIRE(pc != nullptr, "preconditioner is NULL");
+        PKM_REQUIRE(pc->device == ctx->device, "preconditioner belongs to another device");
+        PKM_REQUIRE(k >= 1 && k <= 4096, "k must be in [1, 4096]");
+        require_dev(V, "V");
+        require_dev(Y, "Y");
+        PKM_REQUIRE(V != Y, "Y may not alias V");
+        precond_sub_lowrank(ctx, pc, k, V, Y);
+        return PKM_OK;
+    });
+}
+
 int pkm_precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int32_t k, const double* R,
                       double* Z) {
     if (!ctx) return PKM_ERR_INVALID;
@@ -260,6 +304,7 @@ int pkm_precond_destroy(pkm_precond* pc) {
     pc->psi.release();
     pc->dinv.release();
     pc->dblk.release();
+    pc->phi.release();
     delete pc;
     return PKM_OK;
 }

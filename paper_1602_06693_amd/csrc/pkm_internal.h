@@ -151,6 +151,7 @@ struct pkm_precond {
     pkm::DevBuf dinv;   // n FP64: 1 / diag(D)
     int block = 0;      // PITC: block size b; dblk holds blockdiag(D^-1), n x b
     pkm::DevBuf dblk;
+    pkm::DevBuf phi;    // n x m FP64: the low-rank factor of P = D + phi phi^T
 };
 
 // Learned factor network (mlp.hip).

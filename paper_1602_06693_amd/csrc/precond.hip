@@ -238,9 +238,78 @@ __global__ void k_pitc_diag_recip(int64_t n, int b, const double* __restrict__ D
     dinv[i] = 1.0 / Dblk[i * b + (i % b)];
 }
 
+// dst[:, col0 : col0 + cols] (leading dimension ldd) = src (rows x cols, dense)
+__global__ void k_put_cols(int64_t rows, int cols, const double* __restrict__ src,
+                           double* __restrict__ dst, int64_t ldd, int col0) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= rows * cols) return;
+    const int64_t i = e / cols;
+    const int c = int(e - i * cols);
+    dst[i * ldd + col0 + c] = src[e];
+}
+
+// out[t, :] = W[idx[t], :] for t < m (W and out with row length w)
+__global__ void k_gather_rows(const double* __restrict__ W, const int32_t* __restrict__ idx,
+                              int m, int w, double* __restrict__ out) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= int64_t(m) * w) return;
+    const int64_t t = e / w;
+    const int c = int(e - t * w);
+    out[e] = W[int64_t(idx[t]) * w + c];
+}
+
 static void read_info(pkm_ctx* ctx, const int* dinfo, int* out) {
     PKM_HIP(hipMemcpyAsync(out, dinfo, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     PKM_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+// The low-rank factor Phi of P = D + Phi Phi^T (pc->psi holds it at this
+// point) is kept for pkm_precond_sub_lowrank.
+static void keep_factor(pkm_ctx* ctx, pkm_precond* pc) {
+    pc->phi.ensure(sizeof(double) * pc->n * pc->m);
+    PKM_HIP(hipMemcpyAsync(pc->phi.p, pc->psi.p, sizeof(double) * pc->n * pc->m,
+                           hipMemcpyDeviceToDevice, ctx->stream));
+}
+
+// Hybrid sketch S = [columns of I at idx (m_idx), U (n x r)]: the factor
+// W L^-T with W = K S (K_XU and K U in FP64) and
+// L L^T = S^T W + jitter * mean(diag) I (rows idx of W, then U^T W).
+// Written to out (n x (m_idx + r)); core / winv: (m_idx + r)^2 scratch.
+static void hybrid_factor(pkm_ctx* ctx, const pkm_problem* prob, int m_idx, int r,
+                          const int32_t* idx, const double* U, double jitter, double* out,
+                          double* core, double* winv, int* dinfo) {
+    const int64_t n = prob->n;
+    const int w = m_idx + r;
+    hipStream_t s = ctx->stream;
+    const double* xs = ctx->P().xs64.as<double>();
+    rbf_cross64(s, xs, nullptr, n, xs, idx, m_idx, prob->d, prob->sigma2, out, w);
+    ctx->ws_pitc[1].ensure(sizeof(double) * n * r);
+    double* KU = ctx->ws_pitc[1].as<double>();
+    mvm_shift(ctx, PKM_FP64, r, U, KU, 0.0);
+    k_put_cols<<<cdiv(n * r, 256), 256, 0, s>>>(n, r, KU, out, w, m_idx);
+    PKM_CHECK_LAUNCH();
+    k_gather_rows<<<cdiv(int64_t(m_idx) * w, 256), 256, 0, s>>>(out, idx, m_idx, w, core);
+    PKM_CHECK_LAUNCH();
+    dgemm(ctx, true, false, r, w, n, 1.0, U, r, out, w, 0.0, core + int64_t(m_idx) * w, w);
+    k_symmetrize<<<cdiv(int64_t(w) * w, 256), 256, 0, s>>>(w, core);
+    PKM_CHECK_LAUNCH();
+    std::vector<double> diag(w);
+    PKM_HIP(hipMemcpy2DAsync(diag.data(), sizeof(double), core, sizeof(double) * (w + 1),
+                             sizeof(double), w, hipMemcpyDeviceToHost, s));
+    PKM_HIP(hipStreamSynchronize(s));
+    double mean = 0.0;
+    for (double v : diag) mean += v;
+    mean /= w;
+    PKM_REQUIRE(std::isfinite(mean) && mean > 0.0, "hybrid: S^T K S has no positive diagonal");
+    k_add_diag<<<cdiv(w, 256), 256, 0, s>>>(w, core, w, jitter * mean);
+    PKM_CHECK_LAUNCH();
+    dpotrf_lower(ctx, w, core, w, winv, dinfo);
+    int hinfo = 0;
+    read_info(ctx, dinfo, &hinfo);
+    if (hinfo != 0)
+        fail(PKM_ERR_BREAKDOWN, "hybrid: S^T K S + jitter I is not positive definite "
+                                "(dependent sketch columns need jitter > 0)");
+    dtrsm_right_lt(ctx, n, w, core, w, winv, out, w);
 }
 
 // PITC from Nystrom's Phi (already in pc->psi): block factors, Phi~, core,
@@ -290,11 +359,15 @@ static void setup_pitc(pkm_ctx* ctx, const pkm_problem* prob, int m, int b, pkm_
     PKM_HIP(hipStreamSynchronize(s));
 }
 
-void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const int32_t* idx,
-                   const double* Phi, double jitter, pkm_precond* pc, int block) {
+// aux: block size (PITC) or number of learned columns r (HYBRID: the sketch
+// is [columns of I at idx (m of them), Phi (n x r)], m + r columns in all).
+void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m_in, const int32_t* idx,
+                   const double* Phi, double jitter, pkm_precond* pc, int aux) {
     const int64_t n = prob->n;
     hipStream_t s = ctx->stream;
-    prepare(ctx, prob, true, false);
+    prepare(ctx, prob, true, kind == PKM_PC_SKETCH);
+    const int m = kind == PKM_PC_HYBRID ? m_in + aux : m_in;
+    const int block = aux;
     pc->kind = kind;
     pc->n = n;
     pc->m = m;
@@ -314,14 +387,20 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const
     int* dinfo = ctx->ws_setup[3].as<int>();
     int hinfo = 0;
 
-    if (kind == PKM_PC_NYSTROM || kind == PKM_PC_FITC || kind == PKM_PC_PITC) {
+    if (kind == PKM_PC_NYSTROM || kind == PKM_PC_FITC || kind == PKM_PC_PITC ||
+        kind == PKM_PC_HYBRID) {
         PKM_HIP(hipMemsetAsync(dinfo, 0, sizeof(int), s));
-        k_check_idx<<<cdiv(m, 256), 256, 0, s>>>(idx, m, n, dinfo);
+        k_check_idx<<<cdiv(m_in, 256), 256, 0, s>>>(idx, m_in, n, dinfo);
         PKM_CHECK_LAUNCH();
         read_info(ctx, dinfo, &hinfo);
         PKM_REQUIRE(hinfo == 0, "inducing index out of range");
         const double* xs = ctx->P().xs64.as<double>();
         const int d = prob->d;
+        if (kind == PKM_PC_HYBRID) {
+            hybrid_factor(ctx, prob, m_in, aux, idx, Phi, jitter, psi, core, winv, dinfo);
+            k_diag_d<<<cdiv(n, 256), 256, 0, s>>>(psi, n, m, 0, prob->sigma2, prob->lambda, D);
+            PKM_CHECK_LAUNCH();
+        } else {
         // K_UU + jitter I, then L_U
         rbf_cross64(s, xs, idx, m, xs, idx, m, d, prob->sigma2, core, m);
         if (jitter > 0.0) {
@@ -338,15 +417,16 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const
         rbf_cross64(s, xs, nullptr, n, xs, idx, m, d, prob->sigma2, psi, m);
         dtrsm_right_lt(ctx, n, m, core, m, winv, psi, m);
         if (kind == PKM_PC_PITC) {
+            keep_factor(ctx, pc);
             setup_pitc(ctx, prob, m, block, pc);
             return;
         }
         k_diag_d<<<cdiv(n, 256), 256, 0, s>>>(psi, n, m, kind == PKM_PC_FITC, prob->sigma2,
                                               prob->lambda, D);
         PKM_CHECK_LAUNCH();
+        }
     } else if (kind == PKM_PC_SKETCH) {
         // K S with the FP32 product (K S = (K + lambda I) S - lambda S)
-        prepare(ctx, prob, true, true);
         mvm(ctx, PKM_FP32, m, Phi, psi);
         k_axpy_neg<<<cdiv(n * m, 256), 256, 0, s>>>(n * m, prob->lambda, Phi, psi);
         PKM_CHECK_LAUNCH();
@@ -377,6 +457,7 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const
         k_diag_d<<<cdiv(n, 256), 256, 0, s>>>(psi, n, m, 0, prob->sigma2, prob->lambda, D);
         PKM_CHECK_LAUNCH();
     }
+    keep_factor(ctx, pc);
     // Phi~ = D^-1/2 Phi;  C = I + Phi~^T Phi~;  L_C;  Psi = D^-1/2 Phi~ L_C^-T
     k_row_scale_rsqrt<<<cdiv(n * m, 256), 256, 0, s>>>(n, m, D, psi);
     PKM_CHECK_LAUNCH();
@@ -551,6 +632,17 @@ static void apply_chunk(pkm_ctx* ctx, const pkm_precond* pc, int k, int c0, cons
     k_apply_z<KT><<<(unsigned)cdiv(n, 64), 256, 0, s>>>(pc->psi.as<double>(), m, T, ldt, dv, R,
                                                         k, c0, n, Z);
     PKM_CHECK_LAUNCH();
+}
+
+// Y <- Y - Phi Phi^T V (V, Y n x k; Phi the kept low-rank factor)
+void precond_sub_lowrank(pkm_ctx* ctx, const pkm_precond* pc, int k, const double* V, double* Y) {
+    const int64_t n = pc->n;
+    const int m = pc->m;
+    ctx->ws_pitc[0].ensure(sizeof(double) * int64_t(m) * k);
+    double* T = ctx->ws_pitc[0].as<double>();
+    const double* phi = pc->phi.as<double>();
+    dgemm(ctx, true, false, m, k, n, 1.0, phi, m, V, k, 0.0, T, k);
+    dgemm_large(ctx, false, false, n, k, m, -1.0, phi, m, T, k, 1.0, Y, k);
 }
 
 void precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int k, const double* R, double* Z) {

@@ -35,10 +35,8 @@ class Arm:
 class NystromArm(Arm):
     """Fresh uniform inducing points every step (Section 5)."""
 
-    name = "nystrom"
-
-    def __init__(self, n, m, seed=0, jitter=1e-8):
-        self.n, self.m, self.jitter = n, m, jitter
+    def __init__(self, n, m, seed=0, jitter=1e-8, name="nystrom"):
+        self.n, self.m, self.jitter, self.name = n, m, jitter, name
         self.rng = np.random.default_rng(seed)
 
     def setup(self, ctx, prob, step):
@@ -50,17 +48,21 @@ class NystromArm(Arm):
 
 
 class LearnedArm(Arm):
-    """Sketch-Nystrom preconditioner from the factor network, fine-tuned on
-    K Z probe pairs at every step's hyperparameters."""
+    """Nystrom enlarged by a learned sketch.  Every step draws the same fresh
+    inducing points as a NystromArm with the same seed, forms probe pairs
+    (Z, (K - Q) Z) -- the part of K that step's Nystrom approximation Q
+    misses -- fine-tunes the factor network on them, and preconditions with
+    Nystrom on the sketch [E_U, U(X)] (pkm_precond_setup_hybrid)."""
 
     name = "learned"
 
-    def __init__(self, ctx, params, d, rank, n_train_probes=64, first_steps=200,
+    def __init__(self, ctx, params, d, rank, n, m, n_train_probes=64, first_steps=200,
                  steps_per_theta=20, lr=1e-3, seed=0, jitter=1e-8, log=None):
         self.net = pk.pkm_mlp_create(ctx, params, d, 128, rank)
-        self.rank, self.nz = rank, n_train_probes
+        self.rank, self.nz, self.n, self.m = rank, n_train_probes, n, m
         self.first, self.later, self.lr, self.jitter = first_steps, steps_per_theta, lr, jitter
-        self.rng = np.random.default_rng(seed)
+        self.rng_idx = np.random.default_rng(seed)        # same draws as NystromArm(seed)
+        self.rng = np.random.default_rng(seed + 7919)     # probes
         self.train_s = 0.0
         self.losses = []
         self.log = log
@@ -69,18 +71,25 @@ class LearnedArm(Arm):
         import torch
         t0 = time.perf_counter()
         dev = prob.X.device
+        idx = np.sort(self.rng_idx.choice(self.n, size=self.m, replace=False)).astype(np.int32)
+        idx_d = torch.from_numpy(idx).to(dev)
         Z = torch.from_numpy(pk_rademacher(self.rng, prob.n, self.nz)).to(dev)
-        KZ = pk.pkm_kernel_mvm_shift(ctx, prob, Z, 0.0, pk.PKM_FP32)   # K Z
+        R = pk.pkm_kernel_mvm_shift(ctx, prob, Z, 0.0, pk.PKM_FP32)   # K Z
+        pcn = pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_NYSTROM, self.m, idx=idx_d,
+                                   jitter=self.jitter)
+        try:
+            pk.pkm_precond_sub_lowrank(ctx, pcn, Z, R)                 # (K - Q) Z
+        finally:
+            pk.pkm_precond_destroy(pcn)
         iters = self.first if step == 0 else self.later
         for it in range(iters):
-            self.losses.append(pk.pkm_mlp_train_step(ctx, self.net, prob, Z, KZ, self.lr))
+            self.losses.append(pk.pkm_mlp_train_step(ctx, self.net, prob, Z, R, self.lr))
             if self.log and (it + 1) % 50 == 0:
                 self.log(f"[learned] step {step}: Adam {it + 1}/{iters}, loss {self.losses[-1]:.4e}")
         U = pk.pkm_mlp_forward(ctx, self.net, prob, self.rank)
         torch.cuda.synchronize()
         self.train_s += time.perf_counter() - t0
-        return pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_SKETCH, self.rank, Phi=U,
-                                    jitter=self.jitter)
+        return pk.pkm_precond_setup_hybrid(ctx, prob, self.m, idx_d, U, jitter=self.jitter)
 
     def close(self):
         pk.pkm_mlp_destroy(self.net)

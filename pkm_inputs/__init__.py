@@ -152,15 +152,17 @@ def batched_problems(seed: int = 0, count: int = 64, n_lo: int = 1000,
     return out
 
 
-def mlp_params(seed: int = 0, d_in: int = 8, hidden: int = 128, rank: int = 128) -> dict:
-    """Initial weights of the factor network: W ~ N(0, 1/fan_in), zero biases."""
+def mlp_params(seed: int = 0, d_in: int = 8, hidden: int = 128, rank: int = 128,
+               out_scale: float = 1.0) -> dict:
+    """Initial weights of the factor network: W ~ N(0, 1/fan_in) (the output
+    layer additionally times ``out_scale``), zero biases."""
     rng = np.random.default_rng(seed)
     return {
         "W1": rng.standard_normal((d_in, hidden)) / math.sqrt(d_in),
         "b1": np.zeros(hidden),
         "W2": rng.standard_normal((hidden, hidden)) / math.sqrt(hidden),
         "b2": np.zeros(hidden),
-        "W3": rng.standard_normal((hidden, rank)) / math.sqrt(hidden),
+        "W3": rng.standard_normal((hidden, rank)) / math.sqrt(hidden) * out_scale,
         "b3": np.zeros(rank),
     }
 

@@ -45,8 +45,9 @@ def test_learned_and_nystrom_arms_share_a_replayed_trajectory(ctx):
     p = make("learned", seed=2, n=3000, n_probes=4)
     d = p.d
     theta0 = hyper.theta_of(1.0, p.lengthscales)
-    learned = hyper.LearnedArm(ctx, mlp_params(3, d_in=d, rank=32), d, 32, n_train_probes=32,
-                               first_steps=60, steps_per_theta=10, lr=3e-3)
+    learned = hyper.LearnedArm(ctx, mlp_params(3, d_in=d, rank=32), d, 32, p.n, 128,
+                               n_train_probes=32, first_steps=60, steps_per_theta=10, lr=3e-3,
+                               seed=4)
     try:
         arms = [hyper.NystromArm(p.n, 128, seed=4), learned]
         traj, rec = hyper.run(ctx, dev(p.X), dev(p.y), dev(p.Z), theta0, p.lam, arms, 2,

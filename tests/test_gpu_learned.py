@@ -1,0 +1,97 @@
+"""Learned correction to Nystrom: probe pairs (Z, (K - Q) Z) for training,
+the hybrid-sketch preconditioner [E_U, U], and what the trained network
+gains over the method without it."""
+import numpy as np
+import pytest
+
+from gpu_util import GpuProblem, ctx, dev, host  # noqa: F401
+from oracle import kernel as ok
+from oracle import precond as op
+from paper_1602_06693_amd import binding as pk
+from pkm_inputs import make, mlp_params, rademacher
+
+pytestmark = pytest.mark.gpu
+
+JIT = 1e-8
+U64 = 2.0 ** -53
+
+
+def test_sub_lowrank_leaves_what_nystrom_misses(ctx):
+    p = make("block_fp32", seed=41, n=800, m=60, n_probes=6)
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, 60, idx=g.idx, jitter=JIT)
+    try:
+        KZ = ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, 0.0, p.Z)
+        Y = dev(KZ)
+        pk.pkm_precond_sub_lowrank(ctx, pc, dev(p.Z), Y)
+        got = host(Y)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    P = op.nystrom(p.X, p.sigma2, p.lengthscales, p.lam, p.idx, jitter=JIT)
+    Kxu, Kuu = P.info["Kxu"], P.info["Kuu"]
+    want = KZ - Kxu @ np.linalg.solve(Kuu, Kxu.T @ p.Z)
+    # Q Z through L_U (GPU) vs a K_UU solve (oracle): about u cond(K_UU) |K Z|
+    tol = max(1e-11, 64 * U64 * np.linalg.cond(Kuu))
+    err = np.linalg.norm(got - want, axis=0) / np.linalg.norm(KZ, axis=0)
+    assert np.all(err < tol), (err, tol)
+
+
+def test_hybrid_apply_matches_oracle_sketch(ctx):
+    p = make("block_fp32", seed=42, n=700, m=40, n_probes=4)
+    g = GpuProblem(p)
+    rng = np.random.default_rng(42)
+    U = rng.standard_normal((p.n, 16)) * 0.1
+    pc = pk.pkm_precond_setup_hybrid(ctx, g.prob, 40, g.idx, dev(U), jitter=JIT)
+    try:
+        got = host(pk.pkm_precond_apply(ctx, pc, g.B))
+    finally:
+        pk.pkm_precond_destroy(pc)
+    S = np.zeros((p.n, 56))
+    S[p.idx, np.arange(40)] = 1.0
+    S[:, 40:] = U
+    P = op.sketch(p.X, p.sigma2, p.lengthscales, p.lam, S, jitter=JIT)
+    want = P(p.B)
+    # both factor C = S^T K S (+ jitter); P^-1 amplifies by cond(P)
+    tol = max(1e-11, 64 * U64 * np.linalg.cond(P.info["C"]) * np.linalg.cond(P.dense()))
+    err = np.linalg.norm(got - want, axis=0) / np.linalg.norm(want, axis=0)
+    assert np.all(err < tol), (err, tol)
+
+
+def _iters(ctx, g, pc):
+    _, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc,
+                           opts=pk.make_opts(tol=1e-6, prec=pk.PKM_FP64), allow_warning=False)
+    assert np.all(info.col_status == pk.PKM_COL_CONVERGED)
+    return int(info.iters.max())
+
+
+def test_trained_correction_reduces_iterations(ctx):
+    """Nystrom (m = 128) alone, enlarged by the untrained network's 32
+    columns, and by the trained network's: the trained correction needs the
+    fewest FP64 PCG steps (and no more than Nystrom alone)."""
+    p = make("learned", seed=43, n=4096, m=128, n_probes=4)
+    g = GpuProblem(p)
+    rank = 32
+    net = pk.pkm_mlp_create(ctx, mlp_params(5, d_in=p.d, rank=rank, out_scale=0.1), p.d, 128,
+                            rank)
+    pcs = []
+    try:
+        Z = dev(rademacher(np.random.default_rng(44), p.n, 64))
+        R = pk.pkm_kernel_mvm_shift(ctx, g.prob, Z, 0.0, pk.PKM_FP64)
+        pcn = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, 128, idx=g.idx, jitter=JIT)
+        pcs.append(pcn)
+        pk.pkm_precond_sub_lowrank(ctx, pcn, Z, R)
+        U0 = pk.pkm_mlp_forward(ctx, net, g.prob, rank)
+        pcs.append(pk.pkm_precond_setup_hybrid(ctx, g.prob, 128, g.idx, U0, jitter=JIT))
+        losses = [pk.pkm_mlp_train_step(ctx, net, g.prob, Z, R, 3e-3) for _ in range(300)]
+        U1 = pk.pkm_mlp_forward(ctx, net, g.prob, rank)
+        pcs.append(pk.pkm_precond_setup_hybrid(ctx, g.prob, 128, g.idx, U1, jitter=JIT))
+        it_nys, it_untrained, it_trained = (_iters(ctx, g, pc) for pc in pcs)
+    finally:
+        for pc in pcs:
+            pk.pkm_precond_destroy(pc)
+        pk.pkm_mlp_destroy(net)
+    print("learned correction: loss", losses[0], "->", losses[-1], "| PCG steps: nystrom",
+          it_nys, "untrained", it_untrained, "trained", it_trained)
+    assert losses[-1] < losses[0]
+    assert it_trained <= it_nys
+    assert it_trained < it_untrained
