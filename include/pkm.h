@@ -157,7 +157,7 @@ int pkm_kernel_mvm_shift(pkm_ctx* ctx, const pkm_problem* prob, int32_t k,
  *   distinct indices in [0, n); jitter >= 0 is added to the diagonal of K_UU.
  * LOWRANK: factor Phi given as a device n x m FP64 array (idx ignored).
  * SKETCH: sketch S given in Phi (device n x m FP64); K S is formed with one
- *   FP32 kernel product, S^T K S gets jitter * (mean of its diagonal) added
+ *   FP32 kernel product, S^T K S gets jitter times its own diagonal added
  *   before its FP64 Cholesky, and the factor is K S L^-T, so the low-rank
  *   part never exceeds K (P <= K_y in the positive semi-definite order).
  * The result represents P^-1 = D^-1 - Psi Psi^T (matrix inversion lemma with
@@ -180,7 +180,7 @@ int pkm_precond_setup_pitc(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
 /* Nystrom on the hybrid sketch S = [E_U, U]: E_U the m columns of the
  * identity at the inducing indices idx (device, m distinct in [0, n)), U a
  * device n x r FP64 array (e.g. the learned factor).  P = K S (S^T K S +
- * jitter * mean-diagonal I)^-1 S^T K + lambda I: the Section 3.1 Nystrom
+ * jitter * diag(S^T K S))^-1 S^T K + lambda I: the Section 3.1 Nystrom
  * preconditioner enlarged by the span of K U, so its low-rank part never
  * exceeds K and grows monotonically with the sketch.  K_XU and K U (one
  * FP64 product) in FP64.  m, r >= 1, m + r <= min(n, 4096), d <= 34.       */

@@ -140,8 +140,9 @@ def pitc(X, sigma2, lengthscales, lam, idx, block, jitter=0.0):
 
 def sketch(X, sigma2, lengthscales, lam, S, jitter=0.0):
     """Nystrom with a general sketch S (n x m): P = K S C^{-1} S^T K + lambda I,
-    C = S^T K S + jitter * mean(diag(S^T K S)) I.  With S = columns of the
-    identity at the inducing indices (and the jitter scaled alike) this is the
+    C = S^T K S + jitter * diag(S^T K S) (a relative jitter, so rescaling a
+    sketch column changes nothing).  With S = columns of the identity at the
+    inducing indices (and the jitter scaled by sigma^2) this is the
     Section 3.1 preconditioner; inverted by the same matrix inversion lemma,
     P^{-1} v = lambda^{-1} [ v - A (lambda C + A^T A)^{-1} A^T v ],  A = K S."""
     X = np.asarray(X, dtype=np.float64)
@@ -150,7 +151,7 @@ def sketch(X, sigma2, lengthscales, lam, S, jitter=0.0):
     A = K @ S
     C = S.T @ A
     C = 0.5 * (C + C.T)
-    C = C + jitter * np.mean(np.diag(C)) * np.eye(S.shape[1])
+    C = C + jitter * np.diag(np.diag(C))
     core = lam * C + A.T @ A
 
     def apply(R):

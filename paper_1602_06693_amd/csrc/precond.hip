@@ -24,6 +24,12 @@
 
 namespace pkm {
 
+// A_ii *= f (relative jitter: invariant to rescaling a sketch column)
+__global__ void k_scale_diag(int64_t m, double* __restrict__ A, int64_t lda, double f) {
+    int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i < m) A[i * lda + i] *= f;
+}
+
 __global__ void k_add_diag(int64_t m, double* __restrict__ A, int64_t lda, double v) {
     int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i < m) A[i * lda + i] += v;
@@ -273,7 +279,7 @@ static void keep_factor(pkm_ctx* ctx, pkm_precond* pc) {
 
 // Hybrid sketch S = [columns of I at idx (m_idx), U (n x r)]: the factor
 // W L^-T with W = K S (K_XU and K U in FP64) and
-// L L^T = S^T W + jitter * mean(diag) I (rows idx of W, then U^T W).
+// L L^T = S^T W + jitter * diag(S^T W) (rows idx of W, then U^T W).
 // Written to out (n x (m_idx + r)); core / winv: (m_idx + r)^2 scratch.
 static void hybrid_factor(pkm_ctx* ctx, const pkm_problem* prob, int m_idx, int r,
                           const int32_t* idx, const double* U, double jitter, double* out,
@@ -293,15 +299,7 @@ static void hybrid_factor(pkm_ctx* ctx, const pkm_problem* prob, int m_idx, int 
     dgemm(ctx, true, false, r, w, n, 1.0, U, r, out, w, 0.0, core + int64_t(m_idx) * w, w);
     k_symmetrize<<<cdiv(int64_t(w) * w, 256), 256, 0, s>>>(w, core);
     PKM_CHECK_LAUNCH();
-    std::vector<double> diag(w);
-    PKM_HIP(hipMemcpy2DAsync(diag.data(), sizeof(double), core, sizeof(double) * (w + 1),
-                             sizeof(double), w, hipMemcpyDeviceToHost, s));
-    PKM_HIP(hipStreamSynchronize(s));
-    double mean = 0.0;
-    for (double v : diag) mean += v;
-    mean /= w;
-    PKM_REQUIRE(std::isfinite(mean) && mean > 0.0, "hybrid: S^T K S has no positive diagonal");
-    k_add_diag<<<cdiv(w, 256), 256, 0, s>>>(w, core, w, jitter * mean);
+    k_scale_diag<<<cdiv(w, 256), 256, 0, s>>>(w, core, w, 1.0 + jitter);
     PKM_CHECK_LAUNCH();
     dpotrf_lower(ctx, w, core, w, winv, dinfo);
     int hinfo = 0;
@@ -430,19 +428,11 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m_in, co
         mvm(ctx, PKM_FP32, m, Phi, psi);
         k_axpy_neg<<<cdiv(n * m, 256), 256, 0, s>>>(n * m, prob->lambda, Phi, psi);
         PKM_CHECK_LAUNCH();
-        // C = S^T K S (+ jitter * mean diagonal), L = chol(C), factor = K S L^-T
+        // C = S^T K S (+ jitter * its diagonal), L = chol(C), factor = K S L^-T
         dgemm(ctx, true, false, m, m, n, 1.0, Phi, m, psi, m, 0.0, core, m);
         k_symmetrize<<<cdiv(int64_t(m) * m, 256), 256, 0, s>>>(m, core);
         PKM_CHECK_LAUNCH();
-        std::vector<double> diag(m);
-        PKM_HIP(hipMemcpy2DAsync(diag.data(), sizeof(double), core, sizeof(double) * (m + 1),
-                                 sizeof(double), m, hipMemcpyDeviceToHost, s));
-        PKM_HIP(hipStreamSynchronize(s));
-        double mean = 0.0;
-        for (double v : diag) mean += v;
-        mean /= m;
-        PKM_REQUIRE(std::isfinite(mean) && mean > 0.0, "sketch: S^T K S has no positive diagonal");
-        k_add_diag<<<cdiv(m, 256), 256, 0, s>>>(m, core, m, jitter * mean);
+        k_scale_diag<<<cdiv(m, 256), 256, 0, s>>>(m, core, m, 1.0 + jitter);
         PKM_CHECK_LAUNCH();
         dpotrf_lower(ctx, m, core, m, winv, dinfo);
         read_info(ctx, dinfo, &hinfo);

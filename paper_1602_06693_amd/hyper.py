@@ -56,8 +56,8 @@ class LearnedArm(Arm):
 
     name = "learned"
 
-    def __init__(self, ctx, params, d, rank, n, m, n_train_probes=64, first_steps=200,
-                 steps_per_theta=20, lr=1e-3, seed=0, jitter=1e-8, log=None):
+    def __init__(self, ctx, params, d, rank, n, m, n_train_probes=64, first_steps=300,
+                 steps_per_theta=50, lr=2e-3, seed=0, jitter=1e-8, log=None):
         self.net = pk.pkm_mlp_create(ctx, params, d, 128, rank)
         self.rank, self.nz, self.n, self.m = rank, n_train_probes, n, m
         self.first, self.later, self.lr, self.jitter = first_steps, steps_per_theta, lr, jitter
