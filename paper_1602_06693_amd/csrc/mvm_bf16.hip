@@ -31,13 +31,6 @@
 
 namespace pkm {
 
-#ifndef PKM_BF16_U
-#define PKM_BF16_U 4
-#endif
-#ifndef PKM_BF16_SCHED
-#define PKM_BF16_SCHED 0
-#endif
-
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -220,26 +213,19 @@ __global__ __launch_bounds__(256) void k_mvm_bf16(
         for (int qt = 0; qt < KT; ++qt)
 #pragma unroll
             for (int pp = 0; pp < NPV; ++pp) vv[qt][pp] = pv[(qt * NPV + pp) * 64];
-        // all exponent tiles first: 2 S6 U independent MFMAs keep the matrix
-        // cores busy while the vector ALUs work through the previous tiles
-        f32x4 s0[U], s1[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            s0[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-            s1[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+            f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < S6; ++s) {
-                s0[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[s], bi[u][s], s0[u], 0, 0, 0);
-                s1[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[s], bi[u][s], s1[u], 0, 0, 0);
+                s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[s], bi[u][s], s0, 0, 0, 0);
+                s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[s], bi[u][s], s1, 0, 0, 0);
             }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
             float kf[8];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                kf[r] = __builtin_amdgcn_exp2f(s0[u][r]);
-                kf[4 + r] = __builtin_amdgcn_exp2f(s1[u][r]);
+                kf[r] = __builtin_amdgcn_exp2f(s0[r]);
+                kf[4 + r] = __builtin_amdgcn_exp2f(s1[r]);
             }
             bf16x8 kh, kl;
             split_k<NP>(kf, kh, kl);
@@ -252,14 +238,6 @@ __global__ __launch_bounds__(256) void k_mvm_bf16(
                 }
             }
         }
-#if PKM_BF16_SCHED == 1
-        // interleave: one matrix-core instruction, then three vector-ALU ones
-#pragma unroll
-        for (int q = 0; q < 2 * S6 * U + NP * KT * U; ++q) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
-        }
-#endif
     }
 
     float* yo = yout + int64_t(split) * split_stride;
@@ -297,7 +275,7 @@ static void launch_bf16_s(int KT, dim3 grid, hipStream_t s, const bf16x8* js, co
                           int64_t stride) {
 #define PKM_B_CASE(kt)                                                                         \
     if (KT == kt) {                                                                            \
-        k_mvm_bf16<S6, kt, PKM_BF16_U, NP><<<grid, 256, 0, s>>>(js, is, vb, y, nchunk, nrb, jsplit, cps, \
+        k_mvm_bf16<S6, kt, 4, NP><<<grid, 256, 0, s>>>(js, is, vb, y, nchunk, nrb, jsplit, cps, \
                                                         stride);                               \
         return;                                                                                \
     }
@@ -344,7 +322,7 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     k_pack_v_bf16<<<cdiv(tot, 256), 256, 0, s>>>(V, ldv, P.n, k, nchunk, KT, KR, NPV, vb, yrp);
     PKM_CHECK_LAUNCH();
 
-    constexpr int U = PKM_BF16_U;
+    constexpr int U = 4;
     const int64_t nrb = cdiv(P.n_pad, 64 * U);
     int jsplit = 1;
     while (jsplit < 8 && nrb * jsplit < 2048 && nchunk / (jsplit * 2) >= 8) jsplit <<= 1;
