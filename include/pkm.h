@@ -75,6 +75,9 @@ extern "C" {
 #define PKM_PC_HYBRID   6   /* SKETCH with S = [columns of I at inducing points,
                                a learned n x r factor U]; set up by
                                pkm_precond_setup_hybrid                        */
+#define PKM_PC_SPECTRAL 7   /* P = Phi Phi^T + lambda I with random Fourier
+                               features (Section 3.2 spectral approximation);
+                               set up by pkm_precond_setup_spectral            */
 
 /* ---- per-column solver status ------------------------------------------ */
 #define PKM_COL_CONVERGED  0
@@ -194,6 +197,15 @@ int pkm_precond_setup_hybrid(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
  * learned correction).  Two FP64 products with the stored n x m factor.    */
 int pkm_precond_sub_lowrank(pkm_ctx* ctx, const pkm_precond* pc, int32_t k,
                             const double* V, double* Y);
+/* Spectral approximation (Section 3.2): frequencies s_r ~ N(0, Lambda /
+ * (4 pi^2)), Lambda = diag(1 / l_r^2), given through standard normal draws W
+ * (device m x d FP64, caller-owned; omega_r = 2 pi s_r = W_r / l).  Features
+ * Phi = sqrt(sigma2 / m) [cos(X omega^T), sin(X omega^T)] (n x 2m, FP64), so
+ * (Phi Phi^T)_ij = sigma2 / m sum_r cos(omega_r^T (x_i - x_j)) and
+ * diag(Phi Phi^T) = sigma2 exactly; P = Phi Phi^T + lambda I through the
+ * matrix inversion lemma.  1 <= m <= 2048.                                  */
+int pkm_precond_setup_spectral(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
+                               const double* W, pkm_precond** out);
 int pkm_precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int32_t k,
                       const double* R, double* Z);
 /* Host copy of the preconditioner's diagonal part D (n values).           */
@@ -270,6 +282,24 @@ int pkm_lml_grad(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
                  const double* y, int32_t N, const double* Z,
                  const pkm_solve_opts* opts, double* grad_host, double* sol,
                  pkm_solve_info* info);
+
+/* ---- prediction at test inputs ---------------------------------------------
+ * The GP predictive equations the paper's Section 2.1 refers to for test
+ * data, with every solve a PCG solve (one per test point for the variance).
+ * pkm_cross_mvm: Y = K(X_star, X) V, X_star device n_star x d FP64, V device
+ * n x k, Y device n_star x k (FP64 MFMA product; d <= 34).
+ * pkm_predict: mean (device n_star) = K(X_star, X) K_y^-1 y; if var (device
+ * n_star) is not NULL, the latent variances sigma2 - k_*^T K_y^-1 k_* (add
+ * lambda for a noisy target), from one block solve with the n_star columns
+ * K(X, X_star) as right-hand sides (n_star <= 256 then).  pc and opts as for
+ * pkm_solve; info_mean (1 column) and info_var (n_star columns) may be NULL.
+ * Returns the worse of the two solves' status.                              */
+int pkm_cross_mvm(pkm_ctx* ctx, const pkm_problem* prob, int64_t n_star,
+                  const double* X_star, int32_t k, const double* V, double* Y);
+int pkm_predict(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
+                const double* y, int64_t n_star, const double* X_star,
+                const pkm_solve_opts* opts, double* mean, double* var,
+                pkm_solve_info* info_mean, pkm_solve_info* info_var);
 
 /* ---- learned low-rank factor (Section 3.2 form P = U U^T + lambda I) -------
  * A network maps each scaled input row x_i / l to a row of U (n x rank):

@@ -10,7 +10,10 @@ this plain definition is the reference for every solution.
 Pinned by (tests/test_oracle_direct.py): n = 1 and n = 2 closed forms of the
 log-marginal likelihood (scalar Gaussian density, 2x2 determinant and
 inverse); residual of the returned solution through the independent
-row-blocked product of ``oracle.kernel``.
+row-blocked product of ``oracle.kernel``; prediction: at a training input
+with tiny noise the mean reproduces the target and the variance vanishes,
+far from the data the mean is 0 and the variance sigma2, and the n = 1
+closed form k* y / (sigma2 + lambda), sigma2 - k*^2 / (sigma2 + lambda).
 """
 from __future__ import annotations
 
@@ -19,7 +22,7 @@ import math
 import numpy as np
 import scipy.linalg as sla
 
-from .kernel import kernel_matrix
+from .kernel import kernel_matrix, rbf_block
 
 
 def _factor(X, sigma2, lengthscales, lam):
@@ -41,3 +44,16 @@ def log_marginal_likelihood(X, sigma2, lengthscales, lam, y):
     logdet = 2.0 * np.sum(np.log(np.diag(L)))
     n = X.shape[0]
     return -0.5 * logdet - 0.5 * float(y @ alpha) - 0.5 * n * math.log(2.0 * math.pi)
+
+
+def predict(X, sigma2, lengthscales, lam, y, Xs):
+    """GP predictive mean K(X_*, X) K_y^-1 y and latent variance
+    sigma2 - diag(K(X_*, X) K_y^-1 K(X, X_*)) by Cholesky (the predictive
+    equations the paper refers to for test data, Section 2.1)."""
+    X = np.asarray(X, dtype=np.float64)
+    Xs = np.asarray(Xs, dtype=np.float64)
+    c = _factor(X, sigma2, lengthscales, lam)
+    Ks = rbf_block(Xs, X, sigma2, lengthscales)
+    mean = Ks @ sla.cho_solve(c, np.asarray(y, dtype=np.float64))
+    var = sigma2 - np.sum(Ks * sla.cho_solve(c, Ks.T).T, axis=1)
+    return mean, var

@@ -23,6 +23,13 @@ Section 3.2 (factor form): P = Phi Phi^T + lambda I,
     P^{-1} v = lambda^{-1} [ v - Phi (lambda I + Phi^T Phi)^{-1} Phi^T v ],
 again with lambda restored in the core (printed as I + Phi^T Phi).
 
+Section 3.2 (spectral approximation, random Fourier features): with m
+frequencies s_r drawn from N(0, Lambda / (4 pi^2)), Lambda = diag(1 / l^2),
+    K_hat_ij = sigma^2 / m sum_r cos(2 pi s_r^T (x_i - x_j)) = (Phi Phi^T)_ij,
+    Phi = sqrt(sigma^2 / m) [cos(2 pi S X^T)^T, sin(2 pi S X^T)^T]  (n x 2m),
+and P = Phi Phi^T + lambda I as in the factor form.  The caller passes
+standard normal draws W (m x d); 2 pi s_r = W_r / l.
+
 K_UU carries a jitter delta I (the caller's value; the same on both sides),
 which changes P but never the solution of the preconditioned system.
 
@@ -161,6 +168,22 @@ def sketch(X, sigma2, lengthscales, lam, S, jitter=0.0):
         return A @ np.linalg.solve(C, A.T) + lam * np.eye(X.shape[0])
 
     return Preconditioner(apply, dense, {"C": C, "A": A})
+
+
+def spectral_features(X, sigma2, lengthscales, W):
+    """Phi (n x 2m): columns cos(omega_r^T x) then sin(omega_r^T x) for each r,
+    times sqrt(sigma2 / m), omega_r = W_r / l (= 2 pi s_r)."""
+    X = np.asarray(X, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    m = W.shape[0]
+    omega = W / np.asarray(lengthscales, dtype=np.float64)[None, :]
+    A = X @ omega.T                               # (n, m): omega_r^T x_i
+    scale = np.sqrt(sigma2 / m)
+    return np.concatenate([np.cos(A), np.sin(A)], axis=1) * scale
+
+
+def spectral(X, sigma2, lengthscales, lam, W):
+    return lowrank(spectral_features(X, sigma2, lengthscales, W), lam)
 
 
 def lowrank(Phi, lam):

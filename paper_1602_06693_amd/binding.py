@@ -35,6 +35,7 @@ PKM_PC_LOWRANK = 3
 PKM_PC_SKETCH = 4
 PKM_PC_PITC = 5
 PKM_PC_HYBRID = 6
+PKM_PC_SPECTRAL = 7
 
 PKM_COL_CONVERGED = 0
 PKM_COL_MAX_ITER = 1
@@ -45,8 +46,9 @@ EXPORTS = (
     "pkm_create", "pkm_destroy", "pkm_last_error", "pkm_version", "pkm_kernel_mvm",
     "pkm_kernel_mvm_shift",
     "pkm_precond_setup", "pkm_precond_setup_pitc",
-    "pkm_precond_setup_hybrid", "pkm_precond_sub_lowrank", "pkm_precond_apply", "pkm_precond_diag", "pkm_precond_destroy",
-    "pkm_solve", "pkm_solve_batched", "pkm_grad_pass", "pkm_lml_grad", "pkm_timing_enable", "pkm_mvm_stats",
+    "pkm_precond_setup_hybrid", "pkm_precond_setup_spectral", "pkm_precond_sub_lowrank",
+    "pkm_precond_apply", "pkm_precond_diag", "pkm_precond_destroy",
+    "pkm_solve", "pkm_solve_batched", "pkm_cross_mvm", "pkm_predict", "pkm_grad_pass", "pkm_lml_grad", "pkm_timing_enable", "pkm_mvm_stats",
     "pkm_mvm_stats_reset", "pkm_mlp_create", "pkm_mlp_destroy", "pkm_mlp_params",
     "pkm_mlp_forward", "pkm_mlp_loss_grad", "pkm_mlp_train_step", "pkm_adagrad_step",
 )
@@ -102,6 +104,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "pkm_precond_setup_pitc": (C.c_int, [vp, P(pkm_problem), i32, vp, i32, dbl, P(vp)]),
         "pkm_precond_setup_hybrid": (C.c_int, [vp, P(pkm_problem), i32, vp, i32, vp, dbl,
                                                P(vp)]),
+        "pkm_precond_setup_spectral": (C.c_int, [vp, P(pkm_problem), i32, vp, P(vp)]),
         "pkm_precond_sub_lowrank": (C.c_int, [vp, vp, i32, vp, vp]),
         "pkm_precond_apply": (C.c_int, [vp, vp, i32, vp, vp]),
         "pkm_precond_diag": (C.c_int, [vp, vp, P(dbl)]),
@@ -110,6 +113,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                 P(pkm_solve_info)]),
         "pkm_solve_batched": (C.c_int, [vp, i32, P(pkm_problem), P(vp), i32, P(vp), P(vp),
                                         P(pkm_solve_opts), P(pkm_solve_info)]),
+        "pkm_cross_mvm": (C.c_int, [vp, P(pkm_problem), i64, vp, i32, vp, vp]),
+        "pkm_predict": (C.c_int, [vp, P(pkm_problem), vp, vp, i64, vp, P(pkm_solve_opts), vp, vp,
+                                  P(pkm_solve_info), P(pkm_solve_info)]),
         "pkm_grad_pass": (C.c_int, [vp, P(pkm_problem), i32, vp, vp, P(dbl)]),
         "pkm_lml_grad": (C.c_int, [vp, P(pkm_problem), vp, vp, i32, vp, P(pkm_solve_opts),
                                    P(dbl), vp, P(pkm_solve_info)]),
@@ -241,6 +247,14 @@ def pkm_precond_setup_hybrid(ctx, prob: Problem, m, idx, U, jitter=0.0):
     return out
 
 
+def pkm_precond_setup_spectral(ctx, prob: Problem, W):
+    """W: device (m, d) float64 standard normal draws."""
+    out = C.c_void_p()
+    _check(load().pkm_precond_setup_spectral(ctx, prob.ref, int(W.shape[0]), _ptr(W),
+                                             C.byref(out)), ctx)
+    return out
+
+
 def pkm_precond_sub_lowrank(ctx, pc, V, Y):
     """Y <- Y - Phi Phi^T V in place; returns Y."""
     k = V.shape[1] if V.dim() == 2 else 1
@@ -316,6 +330,33 @@ def pkm_solve(ctx, prob: Problem, B, pc=None, X=None, opts=None, allow_warning=T
     info.rc = rc
     _check(rc, ctx, allow=(PKM_OK, PKM_NOT_CONVERGED) if allow_warning else (PKM_OK,))
     return X, info
+
+
+def pkm_cross_mvm(ctx, prob: Problem, X_star, V):
+    """K(X_star, X) V."""
+    import torch
+    k = V.shape[1] if V.dim() == 2 else 1
+    Y = torch.empty((X_star.shape[0], k), dtype=torch.float64, device=V.device)
+    _check(load().pkm_cross_mvm(ctx, prob.ref, int(X_star.shape[0]), _ptr(X_star), k, _ptr(V),
+                                _ptr(Y)), ctx)
+    return Y
+
+
+def pkm_predict(ctx, prob: Problem, y, X_star, pc=None, opts=None, variance=True):
+    """Returns (mean, var or None, SolveInfo of the mean solve, SolveInfo of the
+    variance solve or None)."""
+    import torch
+    ns = X_star.shape[0]
+    mean = torch.empty(ns, dtype=torch.float64, device=y.device)
+    var = torch.empty(ns, dtype=torch.float64, device=y.device) if variance else None
+    im = SolveInfo(1)
+    iv = SolveInfo(ns) if variance else None
+    opts = opts or make_opts()
+    rc = load().pkm_predict(ctx, prob.ref, pc, _ptr(y), int(ns), _ptr(X_star), C.byref(opts),
+                            _ptr(mean), _ptr(var) if variance else None, C.byref(im.struct),
+                            C.byref(iv.struct) if variance else None)
+    _check(rc, ctx, allow=(PKM_OK, PKM_NOT_CONVERGED))
+    return mean, var, im, iv
 
 
 def pkm_grad_pass(ctx, prob: Problem, N, AS, YZ):

@@ -12,6 +12,9 @@ namespace pkm {
 void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const int32_t* idx,
                    const double* Phi, double jitter, pkm_precond* pc, int aux);
 void precond_sub_lowrank(pkm_ctx* ctx, const pkm_precond* pc, int k, const double* V, double* Y);
+int predict(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, const double* y,
+            int64_t ns, const double* Xs, const pkm_solve_opts* o, double* mean, double* var,
+            pkm_solve_info* info_mean, pkm_solve_info* info_var);
 int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, const double* B,
           double* X, const pkm_solve_opts* o, pkm_solve_info* info);
 int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_precond* const* pcs,
@@ -63,6 +66,8 @@ static int guarded(pkm_ctx* ctx, F&& f) {
         return PKM_ERR_HIP;
     }
 }
+
+static void fill_opts(const pkm_solve_opts* in, pkm_solve_opts* o);
 
 static void check_prec(int prec, int d) {
     PKM_REQUIRE(prec >= PKM_FP64 && prec <= PKM_BF16X3, "unknown precision");
@@ -130,6 +135,8 @@ int pkm_destroy(pkm_ctx* ctx) {
     for (auto& b : ctx->pcg) b.release();
     for (auto& b : ctx->ws_setup) b.release();
     for (auto& b : ctx->ws_pitc) b.release();
+    for (auto& b : ctx->cross) b.release();
+    for (auto& b : ctx->pred) b.release();
     for (auto& b : ctx->batch) b.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -252,6 +259,69 @@ int pkm_precond_setup_hybrid(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
     }
     *out = pc;
     return PKM_OK;
+}
+
+int pkm_precond_setup_spectral(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
+                               const double* W, pkm_precond** out) {
+    if (!ctx) return PKM_ERR_INVALID;
+    if (out) *out = nullptr;
+    pkm_precond* pc = nullptr;
+    int rc = guarded(ctx, [&] {
+        PKM_REQUIRE(out != nullptr, "out is NULL");
+        validate_problem(prob);
+        PKM_REQUIRE(m >= 1 && m <= 2048, "m must be in [1, 2048] (2 m features)");
+        require_dev(W, "W");
+        pc = new pkm_precond();
+        precond_setup(ctx, prob, PKM_PC_SPECTRAL, m, nullptr, W, 0.0, pc, 0);
+        return PKM_OK;
+    });
+    if (rc != PKM_OK) {
+        if (pc) pkm_precond_destroy(pc);
+        return rc;
+    }
+    *out = pc;
+    return PKM_OK;
+}
+
+int pkm_cross_mvm(pkm_ctx* ctx, const pkm_problem* prob, int64_t n_star, const double* X_star,
+                  int32_t k, const double* V, double* Y) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        validate_problem(prob);
+        PKM_REQUIRE(prob->d <= 34, "cross product needs d <= 34");
+        PKM_REQUIRE(n_star >= 1 && n_star <= (int64_t(1) << 31) - 4096, "bad n_star");
+        PKM_REQUIRE(k >= 1 && k <= 4096, "k must be in [1, 4096]");
+        require_dev(X_star, "X_star");
+        require_dev(V, "V");
+        require_dev(Y, "Y");
+        PKM_REQUIRE((reinterpret_cast<uintptr_t>(X_star) & 7) == 0, "X_star must be 8-byte aligned");
+        cross_k64(ctx, prob, X_star, n_star, prob->X, prob->n, k, V, Y);
+        return PKM_OK;
+    });
+}
+
+int pkm_predict(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, const double* y,
+                int64_t n_star, const double* X_star, const pkm_solve_opts* opts, double* mean,
+                double* var, pkm_solve_info* info_mean, pkm_solve_info* info_var) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        validate_problem(prob);
+        PKM_REQUIRE(prob->d <= 34, "prediction needs d <= 34");
+        PKM_REQUIRE(n_star >= 1 && (var == nullptr || n_star <= 256),
+                    "n_star must be >= 1 (and <= 256 when variances are requested)");
+        require_dev(y, "y");
+        require_dev(X_star, "X_star");
+        require_dev(mean, "mean");
+        if (pc) {
+            PKM_REQUIRE(pc->n == prob->n, "preconditioner built for another n");
+            PKM_REQUIRE(pc->device == ctx->device, "preconditioner on another device");
+        }
+        pkm_solve_opts o;
+        fill_opts(opts, &o);
+        check_prec(o.prec, prob->d);
+        if (var) require_dev(var, "var");
+        return predict(ctx, prob, pc, y, n_star, X_star, &o, mean, var, info_mean, info_var);
+    });
 }
 
 int pkm_precond_sub_lowrank(pkm_ctx* ctx, const pkm_precond* pc, int32_t k, const double* V,

@@ -335,6 +335,7 @@ __global__ __launch_bounds__(256) void k_mvm_f64x(const double* __restrict__ jsi
                                                   const double* __restrict__ iside,
                                                   const double* __restrict__ V, int64_t ldv,
                                                   int kcols, int64_t n, int64_t ntiles,
+                                                  int64_t n_out,
                                                   double* __restrict__ part, int64_t ldp,
                                                   int64_t split_stride, int64_t tiles_per_split) {
     __shared__ double tab[64];
@@ -395,19 +396,19 @@ __global__ __launch_bounds__(256) void k_mvm_f64x(const double* __restrict__ jsi
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = (itile0 + u) * 16 + g + 4 * r;
                 const int c = 16 * q + cc;
-                if (i < n && c < kcols) po[i * ldp + c] = acc[u][q][r];
+                if (i < n_out && c < kcols) po[i * ldp + c] = acc[u][q][r];
             }
 }
 
 template <int S4>
 static void launch_f64x(int KT, dim3 grid, hipStream_t s, const double* js, const double* is,
-                        const double* V, int64_t ldv, int k, int64_t n, int64_t ntiles,
+                        const double* V, int64_t ldv, int k, int64_t n, int64_t ntiles, int64_t n_out,
                         double* part, int64_t ldp, int64_t sstride, int64_t tps) {
     switch (KT) {
-        case 1: k_mvm_f64x<S4, 1, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, part, ldp, sstride, tps); break;
-        case 2: k_mvm_f64x<S4, 2, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, part, ldp, sstride, tps); break;
-        case 3: k_mvm_f64x<S4, 3, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, part, ldp, sstride, tps); break;
-        case 4: k_mvm_f64x<S4, 4, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, part, ldp, sstride, tps); break;
+        case 1: k_mvm_f64x<S4, 1, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, n_out, part, ldp, sstride, tps); break;
+        case 2: k_mvm_f64x<S4, 2, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, n_out, part, ldp, sstride, tps); break;
+        case 3: k_mvm_f64x<S4, 3, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, n_out, part, ldp, sstride, tps); break;
+        case 4: k_mvm_f64x<S4, 4, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, n_out, part, ldp, sstride, tps); break;
         default: fail(PKM_ERR_UNSUPPORTED, "FP64 MFMA product: bad column tiling");
     }
 }
@@ -477,7 +478,7 @@ void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy) 
             switch (P.d4 / 4) {
 #define PKM_F64X(S4)                                                                          \
     case S4:                                                                                  \
-        launch_f64x<S4>(KT, grid, s, js, is, V + col0, ldv, kc, n, ntiles, part + col0, k, \
+        launch_f64x<S4>(KT, grid, s, js, is, V + col0, ldv, kc, n, ntiles, n, part + col0, k, \
                         sstride, tps);                                                        \
         break;
                 PKM_F64X(1) PKM_F64X(2) PKM_F64X(3) PKM_F64X(4) PKM_F64X(5)
@@ -521,6 +522,48 @@ void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy) 
     }
     int64_t tot = n * k;
     k_sum_splits64<<<cdiv(tot, 256), 256, 0, s>>>(part, jsplit, sstride, n, k, k, Y, ldy);
+    PKM_CHECK_LAUNCH();
+}
+
+void cross_k64(pkm_ctx* ctx, const pkm_problem* prob, const double* Xa, int64_t na,
+               const double* Xb, int64_t nb, int k, const double* V, double* Y) {
+    hipStream_t s = ctx->stream;
+    const int d4 = int(round_up(prob->d + 2, 4));
+    PKM_REQUIRE(d4 <= kAug64MaxD4, "cross product needs d <= 34");
+    const int64_t nap = round_up(na, 256), nbp = round_up(nb, 256);
+    ctx->cross[0].ensure(sizeof(double) * nbp * d4);
+    ctx->cross[1].ensure(sizeof(double) * nap * d4);
+    ctx->cross[2].ensure(sizeof(double) * std::max(nap, nbp) * d4);
+    double* js = ctx->cross[0].as<double>();
+    double* is = ctx->cross[1].as<double>();
+    prepare_cross64(ctx, prob, Xa, na, Xb, nb, js, is, ctx->cross[2].as<double>());
+    const int64_t nrb = cdiv(na, 128);
+    int jsplit = 1;
+    while (jsplit < 64 && nrb * jsplit < 2048 && nb / (jsplit * 2) >= 256) jsplit <<= 1;
+    const int64_t jps = round_up(cdiv(nb, jsplit), 64);
+    jsplit = int(cdiv(nb, jps));
+    const int64_t sstride = na * int64_t(k);
+    ctx->y64pad.ensure(sizeof(double) * sstride * jsplit);
+    double* part = ctx->y64pad.as<double>();
+    const dim3 grid((unsigned)nrb, (unsigned)jsplit);
+    const int64_t ntiles = nbp / 16, tps = jps / 16;
+    for (int col0 = 0; col0 < k; col0 += 64) {
+        const int kc = std::min(64, k - col0);
+        const int KT = int(cdiv(kc, 16));
+        switch (d4 / 4) {
+#define PKM_F64C(S4)                                                                            \
+    case S4:                                                                                    \
+        launch_f64x<S4>(KT, grid, s, js, is, V + col0, k, kc, nb, ntiles, na, part + col0, k, \
+                        sstride, tps);                                                          \
+        break;
+            PKM_F64C(1) PKM_F64C(2) PKM_F64C(3) PKM_F64C(4) PKM_F64C(5)
+            PKM_F64C(6) PKM_F64C(7) PKM_F64C(8) PKM_F64C(9)
+#undef PKM_F64C
+            default: fail(PKM_ERR_UNSUPPORTED, "cross product: augmented length");
+        }
+        PKM_CHECK_LAUNCH();
+    }
+    k_sum_splits64<<<cdiv(na * k, 256), 256, 0, s>>>(part, jsplit, sstride, na, k, k, Y, k);
     PKM_CHECK_LAUNCH();
 }
 

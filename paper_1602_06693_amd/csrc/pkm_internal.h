@@ -138,6 +138,8 @@ struct pkm_ctx {
     pkm::DevBuf vbf, v32, y32, v64pad, y64pad, red, red2, scal, state, pcg[8], grad;
     pkm::DevBuf ws_split, ws_tmp, ws_setup[4];
     pkm::DevBuf ws_pitc[2];             // PITC setup: block inverses, L_D^-1 Phi
+    pkm::DevBuf cross[4];               // cross-product operands and prediction scratch
+    pkm::DevBuf pred[3];                // predictive variance: I, K(X, X_*), solutions
     pkm::DevBuf batch[16];              // batched-solve workspace
     void* pinned = nullptr;   // pinned host staging area (PKM_PINNED_BYTES)
 };
@@ -193,6 +195,14 @@ F32Out mvm_k32(pkm_ctx* ctx, int k, const double* V, int ldv);
 // BF16 products (prec PKM_BF16X1 / PKM_BF16X3), same partial-sum layout.
 F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv);
 void prepare_bf16(pkm_ctx* ctx);
+
+// ---- cross products (prediction) ----
+void prepare_cross64(pkm_ctx* ctx, const pkm_problem* prob, const double* Xa, int64_t na,
+                     const double* Xb, int64_t nb, double* jside, double* iside,
+                     double* scratch);
+// Y (na x k) = K(Xa, Xb) V, V nb x k; FP64 MFMA product, d + 2 <= 36.
+void cross_k64(pkm_ctx* ctx, const pkm_problem* prob, const double* Xa, int64_t na,
+               const double* Xb, int64_t nb, int k, const double* V, double* Y);
 
 // ---- setup BLAS (blas64.hip) ----
 // C[M x N] = alpha * op(A) op(B) + beta * C, FP64, row-major with leading

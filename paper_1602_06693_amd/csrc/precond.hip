@@ -11,6 +11,8 @@
 //   LOWRANK  Phi given by the caller, D = lambda I.
 //   SKETCH   Phi = K S L^-T (L L^T = S^T K S + jitter), D = lambda I.
 //   PITC     Nystrom's Phi, D block diagonal (see the PITC kernels below).
+//   HYBRID   SKETCH with S = [columns of I at idx, caller's U].
+//   SPECTRAL Phi = random Fourier features (Section 3.2), D = lambda I.
 // Scaling Phi by D^-1/2 before forming C keeps the core well conditioned:
 // C's eigenvalues are 1 + (those of Phi^T D^-1 Phi) >= 1.
 //
@@ -254,6 +256,25 @@ __global__ void k_put_cols(int64_t rows, int cols, const double* __restrict__ sr
     dst[i * ldd + col0 + c] = src[e];
 }
 
+// Random Fourier features (Section 3.2, spectral approximation): omega_r =
+// W_r / l (W standard normal, m x d), Phi (n x 2m) row i = sqrt(sigma2 / m)
+// [cos(omega_1^T x_i) .. cos(omega_m^T x_i), sin(omega_1^T x_i) .. ].
+__global__ void k_spectral_features(const double* __restrict__ X, int64_t n, int d,
+                                    const double* __restrict__ inv_l,
+                                    const double* __restrict__ W, int m, double scale,
+                                    double* __restrict__ Phi) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= n * m) return;
+    const int64_t i = e / m;
+    const int r = int(e - i * m);
+    double a = 0.0;
+    for (int t = 0; t < d; ++t) a = fma(X[i * d + t], W[int64_t(r) * d + t] * inv_l[t], a);
+    double sn, cs;
+    sincos(a, &sn, &cs);
+    Phi[i * 2 * m + r] = scale * cs;
+    Phi[i * 2 * m + m + r] = scale * sn;
+}
+
 // out[t, :] = W[idx[t], :] for t < m (W and out with row length w)
 __global__ void k_gather_rows(const double* __restrict__ W, const int32_t* __restrict__ idx,
                               int m, int w, double* __restrict__ out) {
@@ -364,7 +385,7 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m_in, co
     const int64_t n = prob->n;
     hipStream_t s = ctx->stream;
     prepare(ctx, prob, true, kind == PKM_PC_SKETCH);
-    const int m = kind == PKM_PC_HYBRID ? m_in + aux : m_in;
+    const int m = kind == PKM_PC_HYBRID ? m_in + aux : kind == PKM_PC_SPECTRAL ? 2 * m_in : m_in;
     const int block = aux;
     pc->kind = kind;
     pc->n = n;
@@ -440,6 +461,14 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m_in, co
             fail(PKM_ERR_BREAKDOWN, "sketch: S^T K S + jitter I is not positive definite "
                                     "(dependent sketch columns need jitter > 0)");
         dtrsm_right_lt(ctx, n, m, core, m, winv, psi, m);
+        k_diag_d<<<cdiv(n, 256), 256, 0, s>>>(psi, n, m, 0, prob->sigma2, prob->lambda, D);
+        PKM_CHECK_LAUNCH();
+    } else if (kind == PKM_PC_SPECTRAL) {
+        // Phi holds the m x d standard normal draws; m (here) = 2 m_in features
+        const double* inv_l = ctx->scal.as<double>();   // written by prepare()
+        k_spectral_features<<<cdiv(n * m_in, 256), 256, 0, s>>>(
+            prob->X, n, prob->d, inv_l, Phi, m_in, std::sqrt(prob->sigma2 / m_in), psi);
+        PKM_CHECK_LAUNCH();
         k_diag_d<<<cdiv(n, 256), 256, 0, s>>>(psi, n, m, 0, prob->sigma2, prob->lambda, D);
         PKM_CHECK_LAUNCH();
     } else {

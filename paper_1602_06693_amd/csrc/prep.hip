@@ -181,6 +181,36 @@ void prepare(pkm_ctx* ctx, const pkm_problem* prob, bool need64, bool need32) {
     PKM_HIP(hipStreamSynchronize(s));
 }
 
+// FP64 augmented operands of a cross product K(Xa, Xb): b_j from Xb (written
+// to jside, nb rounded up to 256 rows), a_i from Xa (to iside, na rounded up
+// to 256); both centred by Xb's column mean (the kernel is translation
+// invariant, one shared centre keeps a_i . b_j = log2 sigma2 - |xh_i - xh_j|^2).
+// scratch holds the unused side of each call (max of the two padded sizes).
+void prepare_cross64(pkm_ctx* ctx, const pkm_problem* prob, const double* Xa, int64_t na,
+                     const double* Xb, int64_t nb, double* jside, double* iside,
+                     double* scratch) {
+    hipStream_t s = ctx->stream;
+    const int d = prob->d;
+    const int d4 = int(round_up(d + 2, 4));
+    ctx->scal.ensure(4096);
+    double* inv_l = ctx->scal.as<double>();
+    double* mean = inv_l + 64;
+    double hbuf[64];
+    for (int r = 0; r < d; ++r) hbuf[r] = 1.0 / prob->lengthscales[r];
+    PKM_HIP(hipMemcpyAsync(inv_l, hbuf, sizeof(double) * d, hipMemcpyHostToDevice, s));
+    k_colmean<<<d, 256, 0, s>>>(Xb, nb, d, mean);
+    PKM_CHECK_LAUNCH();
+    const double l2s = std::log2(prob->sigma2);
+    const int64_t nbp = round_up(nb, 256), nap = round_up(na, 256);
+    k_aug<double><<<cdiv(nbp, 256), 256, 0, s>>>(Xb, nb, nbp, d, d4, inv_l, mean, l2s, jside,
+                                                  scratch);
+    PKM_CHECK_LAUNCH();
+    k_aug<double><<<cdiv(nap, 256), 256, 0, s>>>(Xa, na, nap, d, d4, inv_l, mean, l2s, scratch,
+                                                  iside);
+    PKM_CHECK_LAUNCH();
+    PKM_HIP(hipStreamSynchronize(s));   // hbuf is host stack memory
+}
+
 // Out[i][j] = sigma2 exp(-1/2 |xa_ia(i) - xb_ib(j)|^2) with optional row
 // gathers ia / ib (NULL: identity).  One thread per output entry.
 __global__ void k_rbf_cross64(const double* __restrict__ xa, const int32_t* __restrict__ ia,

@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 
 from oracle import direct as od
 from oracle import kernel as ok
@@ -35,3 +36,28 @@ def test_solution_residual_through_independent_product():
     x = od.solve(p.X, p.sigma2, p.lengthscales, p.lam, p.B)
     r = p.B - ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, x)
     assert np.all(np.linalg.norm(r, axis=0) / np.linalg.norm(p.B, axis=0) < 1e-12)
+
+
+def test_predict_closed_forms():
+    """n = 1 closed form; interpolation at a training input with tiny noise;
+    prior mean and variance far from the data."""
+    import math
+    from oracle import direct as od2
+    x = np.array([[0.3, 0.1]])
+    ls = np.array([0.5, 0.8])
+    s2, lam, yv = 1.7, 0.2, 0.9
+    xs = np.array([[0.5, -0.2]])
+    k = s2 * math.exp(-0.5 * ((0.2 / 0.5) ** 2 + (0.3 / 0.8) ** 2))
+    m, v = od2.predict(x, s2, ls, lam, np.array([yv]), xs)
+    assert m[0] == pytest.approx(k * yv / (s2 + lam), rel=1e-13)
+    assert v[0] == pytest.approx(s2 - k * k / (s2 + lam), rel=1e-13)
+    rng = np.random.default_rng(7)
+    X = rng.random((30, 2))
+    y = np.sin(3 * X).sum(axis=1)
+    m, v = od2.predict(X, 1.0, ls, 1e-10, y, X[:5])
+    # m = y - lambda K_y^-1 y: off by lambda |alpha| (K_y is ill-conditioned)
+    np.testing.assert_allclose(m, y[:5], rtol=0, atol=1e-5)
+    assert np.all(np.abs(v) < 1e-5)
+    m, v = od2.predict(X, 1.0, ls, 1e-2, y, X[:3] + 100.0)
+    np.testing.assert_allclose(m, 0.0, atol=1e-12)
+    np.testing.assert_allclose(v, 1.0, rtol=1e-12)

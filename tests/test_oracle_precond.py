@@ -144,3 +144,27 @@ def test_pitc_limits_fitc_and_exact():
     b = np.sin(3 * X).sum(axis=1)
     res = pcg(lambda v: Ky @ v, b, precond=Pn, tol=1e-10)
     assert res.iters <= 2
+
+
+def test_spectral_features_closed_forms():
+    """Section 3.2 spectral approximation: (Phi Phi^T)_ij equals the printed
+    sum of cosines of frequency-projected differences; its diagonal is sigma^2
+    exactly (cos^2 + sin^2 = 1); with many frequencies it approaches K (the
+    RBF kernel is the expectation of cos(omega^T (x - x')) for omega ~
+    N(0, diag(1/l^2)))."""
+    rng = np.random.default_rng(31)
+    X = rng.random((40, 3))
+    ls = np.array([0.6, 0.9, 1.4])
+    s2 = 1.7
+    W = rng.standard_normal((25, 3))
+    Phi = op.spectral_features(X, s2, ls, W)
+    Khat = Phi @ Phi.T
+    omega = W / ls
+    D = X[:, None, :] - X[None, :, :]
+    printed = s2 / 25 * np.cos(np.einsum("ijd,rd->ijr", D, omega)).sum(axis=2)
+    np.testing.assert_allclose(Khat, printed, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(np.diag(Khat), s2, rtol=1e-14)
+    Wbig = np.random.default_rng(32).standard_normal((200000, 3))
+    Kbig = op.spectral_features(X, s2, ls, Wbig)
+    err = np.abs(Kbig @ Kbig.T - ok.kernel_matrix(X, s2, ls)).max()
+    assert err < 5 * s2 / np.sqrt(200000)   # Monte Carlo, ~1/sqrt(m)
