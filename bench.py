@@ -249,6 +249,53 @@ def batched_mode(pk, ctx, a):
     print(json.dumps(out), flush=True)
 
 
+def laplace_mode(pk, ctx, a):
+    """GP classification by the Laplace approximation (probit): Newton mode,
+    stochastic gradient (16 Rademacher probes) and predictive probabilities
+    at 128 test inputs, with every B = I + W^1/2 K W^1/2 system solved by PCG
+    with the Nystrom-derived preconditioner, then by plain CG."""
+    import torch
+
+    from pkm_inputs import classification, rademacher
+    n = a.n or 16384
+    X, y, ls, s2, idx = classification(seed=a.seed, n=n, d=14)
+    dev = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).to("cuda:0")
+    prob = pk.Problem(dev(X), ls, s2, 1.0)
+    yd = dev(y)
+    R = dev(rademacher(np.random.default_rng(a.seed + 1), n, 16))
+    Xs = dev(np.random.default_rng(a.seed + 2).random((128, 14)))
+    precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x3": pk.PKM_BF16X3}
+    # B solves to 1e-8 so that the Newton iterations reach the same mode in
+    # both arms (Newton stops when Psi changes by <= 1e-10 relative)
+    opts = pk.make_opts(tol=1e-8, prec=precs.get(a.prec, pk.PKM_FP64), reliable_every=a.reliable)
+    out = {"mode": "laplace", "n": n, "d": 14, "m": len(idx), "probes": 16, "test_points": 128,
+           "product": a.prec if a.prec in precs else "fp64", "tol": 1e-8, "newton_tol": 1e-10}
+    for label, use_pc in (("nystrom", True), ("plain", False)):
+        for rep in range(a.warmup + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pc = (pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_NYSTROM, len(idx), idx=dev(idx),
+                                       jitter=1e-8) if use_pc else None)
+            try:
+                f, _, info = pk.pkm_laplace_mode(ctx, prob, yd, pc=pc, opts=opts, tol=1e-10)
+                t1 = time.perf_counter()
+                g, gsteps = pk.pkm_laplace_grad(ctx, prob, yd, f, R, pc=pc, opts=opts)
+                t2 = time.perf_counter()
+                m, v, p = pk.pkm_laplace_predict(ctx, prob, yd, f, Xs, pc=pc, opts=opts)
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+            finally:
+                if pc is not None:
+                    pk.pkm_precond_destroy(pc)
+        out[label] = {"total_s": t3 - t0, "mode_s": t1 - t0, "grad_s": t2 - t1,
+                      "predict_s": t3 - t2, "newton_iters": info.newton_iters,
+                      "mode_pcg_steps": int(info.pcg_steps), "grad_pcg_steps": int(gsteps),
+                      "psi": info.psi, "grad": [float(v) for v in g]}
+        print(f"[laplace {label}] {out[label]['total_s']:.3f} s", file=sys.stderr, flush=True)
+    out["speedup_nystrom_vs_plain"] = out["plain"]["total_s"] / out["nystrom"]["total_s"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,7 +316,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the workload's n")
     ap.add_argument("--rank", type=int, default=128)
     ap.add_argument("--count", type=int, default=64, help="batched mode: number of problems")
-    ap.add_argument("--mode", choices=("step", "mvm", "hyper", "batched"), default="step",
+    ap.add_argument("--mode", choices=("step", "mvm", "hyper", "batched", "laplace"),
+                    default="step",
                     help="mvm: only --steps FP32 kernel products of the workload's size, "
                          "then one 1 GiB device copy (counter calibration for profiles)")
     a = ap.parse_args()
@@ -299,6 +347,10 @@ def main():
         return
     if a.mode == "batched":
         batched_mode(pk, ctx, a)
+        pk.pkm_destroy(ctx)
+        return
+    if a.mode == "laplace":
+        laplace_mode(pk, ctx, a)
         pk.pkm_destroy(ctx)
         return
     if a.mode == "mvm":

@@ -301,6 +301,41 @@ int pkm_predict(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
                 const pkm_solve_opts* opts, double* mean, double* var,
                 pkm_solve_info* info_mean, pkm_solve_info* info_var);
 
+/* ---- GP classification: Laplace approximation (Section 2.2) --------------
+ * Probit likelihood p(y_i | f_i) = Phi(y_i f_i), labels y (device n) in
+ * {-1, +1}; prob's X, sigma2 and lengthscales define K (its lambda is not
+ * used).  Every linear system is a PCG solve with
+ * B = I + W^1/2 K W^1/2 (W = -d^2 log p / df^2, diagonal), with opts as for
+ * pkm_solve; pc (NULL or a NYSTROM / FITC / PITC / LOWRANK / SKETCH / HYBRID /
+ * SPECTRAL preconditioner of K for the same problem) supplies its low-rank
+ * factor Phi for B's preconditioner I + (W^1/2 Phi)(W^1/2 Phi)^T.
+ * pkm_laplace_mode: Newton iterations (b = W f + dlog p, B z = W^1/2 K b,
+ *   a = b - W^1/2 z, f = K a) from f = 0 until Psi = log p(y|f) - f^T a / 2
+ *   changes by <= tol relative; f, a device n outputs (a = K^-1 f).
+ * pkm_laplace_grad: the three-term stochastic gradient of the approximate
+ *   log-marginal likelihood at the mode f (explicit trace term with the N
+ *   probe columns R, device n x N, 1 <= N <= 255; data-fit term; implicit
+ *   term through dW/df), grad host d + 1 values for (log sigma2, log l_r).
+ * pkm_laplace_predict: at n_star <= 256 test inputs, latent mean, variance
+ *   and p(y_* = +1) = Phi(m / sqrt(1 + s^2)) (device n_star each).         */
+typedef struct {
+    int32_t newton_iters;
+    int32_t reserved;
+    int64_t pcg_steps;        /* PCG steps of all B solves                  */
+    double  psi;              /* log p(y | f_hat) - f_hat^T a / 2           */
+    double  ms;
+} pkm_laplace_info;
+int pkm_laplace_mode(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
+                     const double* y, const pkm_solve_opts* opts, int32_t max_newton,
+                     double tol, double* f, double* a, pkm_laplace_info* info);
+int pkm_laplace_grad(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
+                     const double* y, const double* f, int32_t N, const double* R,
+                     const pkm_solve_opts* opts, double* grad, int64_t* pcg_steps);
+int pkm_laplace_predict(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
+                        const double* y, const double* f, int64_t n_star,
+                        const double* X_star, const pkm_solve_opts* opts, double* mean,
+                        double* var, double* p);
+
 /* ---- learned low-rank factor (Section 3.2 form P = U U^T + lambda I) -------
  * A network maps each scaled input row x_i / l to a row of U (n x rank):
  *   a1 = x W1 + b1, h1 = gelu(a1), a2 = h1 W2 + b2, h2 = gelu(a2),

@@ -48,7 +48,8 @@ EXPORTS = (
     "pkm_precond_setup", "pkm_precond_setup_pitc",
     "pkm_precond_setup_hybrid", "pkm_precond_setup_spectral", "pkm_precond_sub_lowrank",
     "pkm_precond_apply", "pkm_precond_diag", "pkm_precond_destroy",
-    "pkm_solve", "pkm_solve_batched", "pkm_cross_mvm", "pkm_predict", "pkm_grad_pass", "pkm_lml_grad", "pkm_timing_enable", "pkm_mvm_stats",
+    "pkm_solve", "pkm_solve_batched", "pkm_cross_mvm", "pkm_predict",
+    "pkm_laplace_mode", "pkm_laplace_grad", "pkm_laplace_predict", "pkm_grad_pass", "pkm_lml_grad", "pkm_timing_enable", "pkm_mvm_stats",
     "pkm_mvm_stats_reset", "pkm_mlp_create", "pkm_mlp_destroy", "pkm_mlp_params",
     "pkm_mlp_forward", "pkm_mlp_loss_grad", "pkm_mlp_train_step", "pkm_adagrad_step",
 )
@@ -71,6 +72,11 @@ class pkm_solve_info(C.Structure):
                 ("relres_rec", C.POINTER(C.c_double)), ("col_status", C.POINTER(C.c_int32)),
                 ("total_iters", C.c_int64), ("true_residuals", C.c_int64),
                 ("solve_ms", C.c_double), ("prec_final", C.c_int32), ("reserved", C.c_int32)]
+
+
+class pkm_laplace_info(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("reserved", C.c_int32), ("pcg_steps", C.c_int64),
+                ("psi", C.c_double), ("ms", C.c_double)]
 
 
 class PkmError(RuntimeError):
@@ -116,6 +122,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "pkm_cross_mvm": (C.c_int, [vp, P(pkm_problem), i64, vp, i32, vp, vp]),
         "pkm_predict": (C.c_int, [vp, P(pkm_problem), vp, vp, i64, vp, P(pkm_solve_opts), vp, vp,
                                   P(pkm_solve_info), P(pkm_solve_info)]),
+        "pkm_laplace_mode": (C.c_int, [vp, P(pkm_problem), vp, vp, P(pkm_solve_opts), i32, dbl,
+                                       vp, vp, P(pkm_laplace_info)]),
+        "pkm_laplace_grad": (C.c_int, [vp, P(pkm_problem), vp, vp, vp, i32, vp,
+                                       P(pkm_solve_opts), P(dbl), P(i64)]),
+        "pkm_laplace_predict": (C.c_int, [vp, P(pkm_problem), vp, vp, vp, i64, vp,
+                                          P(pkm_solve_opts), vp, vp, vp]),
         "pkm_grad_pass": (C.c_int, [vp, P(pkm_problem), i32, vp, vp, P(dbl)]),
         "pkm_lml_grad": (C.c_int, [vp, P(pkm_problem), vp, vp, i32, vp, P(pkm_solve_opts),
                                    P(dbl), vp, P(pkm_solve_info)]),
@@ -357,6 +369,45 @@ def pkm_predict(ctx, prob: Problem, y, X_star, pc=None, opts=None, variance=True
                             C.byref(iv.struct) if variance else None)
     _check(rc, ctx, allow=(PKM_OK, PKM_NOT_CONVERGED))
     return mean, var, im, iv
+
+
+def pkm_laplace_mode(ctx, prob: Problem, y, pc=None, opts=None, max_newton=50, tol=1e-10):
+    """Returns (f_hat, a, pkm_laplace_info)."""
+    import torch
+    f = torch.empty_like(y)
+    a = torch.empty_like(y)
+    info = pkm_laplace_info()
+    opts = opts or make_opts()
+    rc = load().pkm_laplace_mode(ctx, prob.ref, pc, _ptr(y), C.byref(opts), int(max_newton),
+                                 float(tol), _ptr(f), _ptr(a), C.byref(info))
+    _check(rc, ctx, allow=(PKM_OK, PKM_NOT_CONVERGED))
+    return f, a, info
+
+
+def pkm_laplace_grad(ctx, prob: Problem, y, f, R, pc=None, opts=None):
+    """Returns (grad (d + 1,), PCG steps)."""
+    g = np.zeros(prob.d + 1)
+    steps = C.c_int64(0)
+    opts = opts or make_opts()
+    rc = load().pkm_laplace_grad(ctx, prob.ref, pc, _ptr(y), _ptr(f), int(R.shape[1]), _ptr(R),
+                                 C.byref(opts), g.ctypes.data_as(C.POINTER(C.c_double)),
+                                 C.byref(steps))
+    _check(rc, ctx, allow=(PKM_OK, PKM_NOT_CONVERGED))
+    return g, steps.value
+
+
+def pkm_laplace_predict(ctx, prob: Problem, y, f, X_star, pc=None, opts=None):
+    """Returns (mean, var, p) device tensors."""
+    import torch
+    ns = X_star.shape[0]
+    mean = torch.empty(ns, dtype=torch.float64, device=y.device)
+    var = torch.empty_like(mean)
+    p = torch.empty_like(mean)
+    opts = opts or make_opts()
+    rc = load().pkm_laplace_predict(ctx, prob.ref, pc, _ptr(y), _ptr(f), int(ns), _ptr(X_star),
+                                    C.byref(opts), _ptr(mean), _ptr(var), _ptr(p))
+    _check(rc, ctx, allow=(PKM_OK, PKM_NOT_CONVERGED))
+    return mean, var, p
 
 
 def pkm_grad_pass(ctx, prob: Problem, N, AS, YZ):

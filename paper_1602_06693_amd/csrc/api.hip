@@ -12,11 +12,18 @@ namespace pkm {
 void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const int32_t* idx,
                    const double* Phi, double jitter, pkm_precond* pc, int aux);
 void precond_sub_lowrank(pkm_ctx* ctx, const pkm_precond* pc, int k, const double* V, double* Y);
+int laplace_mode(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* base, const double* y,
+                 const pkm_solve_opts* o, int max_newton, double tol, double* f, double* a,
+                 pkm_laplace_info* info);
+int laplace_grad(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* base, const double* y,
+                 const double* f, int N, const double* R, const pkm_solve_opts* o, double* grad,
+                 int64_t* pcg_steps);
+int laplace_predict(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* base,
+                    const double* y, const double* f, int64_t ns, const double* Xs,
+                    const pkm_solve_opts* o, double* mean, double* var, double* prob_out);
 int predict(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, const double* y,
             int64_t ns, const double* Xs, const pkm_solve_opts* o, double* mean, double* var,
             pkm_solve_info* info_mean, pkm_solve_info* info_var);
-int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, const double* B,
-          double* X, const pkm_solve_opts* o, pkm_solve_info* info);
 int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_precond* const* pcs,
                   int k, const double* const* B, double* const* X, const pkm_solve_opts* o,
                   pkm_solve_info* infos);
@@ -137,6 +144,7 @@ int pkm_destroy(pkm_ctx* ctx) {
     for (auto& b : ctx->ws_pitc) b.release();
     for (auto& b : ctx->cross) b.release();
     for (auto& b : ctx->pred) b.release();
+    for (auto& b : ctx->lap) b.release();
     for (auto& b : ctx->batch) b.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -321,6 +329,71 @@ int pkm_predict(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, co
         check_prec(o.prec, prob->d);
         if (var) require_dev(var, "var");
         return predict(ctx, prob, pc, y, n_star, X_star, &o, mean, var, info_mean, info_var);
+    });
+}
+
+static void check_laplace_args(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
+                               const double* y) {
+    validate_problem(prob);
+    PKM_REQUIRE(prob->d <= 34, "Laplace approximation needs d <= 34");
+    require_dev(y, "y");
+    if (pc) {
+        PKM_REQUIRE(pc->n == prob->n, "preconditioner built for another n");
+        PKM_REQUIRE(pc->device == ctx->device, "preconditioner on another device");
+        PKM_REQUIRE(pc->phi.p != nullptr, "preconditioner has no low-rank factor");
+    }
+}
+
+int pkm_laplace_mode(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
+                     const double* y, const pkm_solve_opts* opts, int32_t max_newton,
+                     double tol, double* f, double* a, pkm_laplace_info* info) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        check_laplace_args(ctx, prob, pc, y);
+        PKM_REQUIRE(max_newton >= 1 && std::isfinite(tol) && tol > 0.0, "bad Newton controls");
+        require_dev(f, "f");
+        require_dev(a, "a");
+        pkm_solve_opts o;
+        fill_opts(opts, &o);
+        check_prec(o.prec, prob->d);
+        return laplace_mode(ctx, prob, pc, y, &o, max_newton, tol, f, a, info);
+    });
+}
+
+int pkm_laplace_grad(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
+                     const double* y, const double* f, int32_t N, const double* R,
+                     const pkm_solve_opts* opts, double* grad, int64_t* pcg_steps) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        check_laplace_args(ctx, prob, pc, y);
+        PKM_REQUIRE(N >= 1 && N <= 255, "N must be in [1, 255]");
+        require_dev(f, "f");
+        require_dev(R, "R");
+        PKM_REQUIRE(grad != nullptr, "grad is NULL");
+        pkm_solve_opts o;
+        fill_opts(opts, &o);
+        check_prec(o.prec, prob->d);
+        return laplace_grad(ctx, prob, pc, y, f, N, R, &o, grad, pcg_steps);
+    });
+}
+
+int pkm_laplace_predict(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
+                        const double* y, const double* f, int64_t n_star,
+                        const double* X_star, const pkm_solve_opts* opts, double* mean,
+                        double* var, double* p) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        check_laplace_args(ctx, prob, pc, y);
+        PKM_REQUIRE(n_star >= 1 && n_star <= 256, "n_star must be in [1, 256]");
+        require_dev(f, "f");
+        require_dev(X_star, "X_star");
+        require_dev(mean, "mean");
+        require_dev(var, "var");
+        require_dev(p, "p");
+        pkm_solve_opts o;
+        fill_opts(opts, &o);
+        check_prec(o.prec, prob->d);
+        return laplace_predict(ctx, prob, pc, y, f, n_star, X_star, &o, mean, var, p);
     });
 }
 

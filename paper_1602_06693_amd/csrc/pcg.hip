@@ -310,14 +310,33 @@ __global__ void k_sub(int64_t tot, const double* __restrict__ a, const double* _
     if (e < tot) out[e] = a[e] - b[e];
 }
 
+// out = w o V (rows scaled by w), n x k
+__global__ void k_scale_rows(int64_t n, int k, const double* __restrict__ w,
+                             const double* __restrict__ V, double* __restrict__ out) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= n * k) return;
+    out[e] = w[e / k] * V[e];
+}
+
+// Y = w o Y + shift V
+__global__ void k_scale_rows_add(int64_t n, int k, const double* __restrict__ w,
+                                 const double* __restrict__ V, double shift,
+                                 double* __restrict__ Y) {
+    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= n * k) return;
+    Y[e] = fma(w[e / k], Y[e], shift * V[e]);
+}
+
 static void dot_part(pkm_ctx* ctx, const double* u, const double* v, int64_t n, int k,
                      double* part) {
     k_dot_part<<<NRED, 256, 0, ctx->stream>>>(u, v, n, k, part);
     PKM_CHECK_LAUNCH();
 }
 
+// The system matrix is K_y = K + lambda I, or, when wscale is given (device
+// n), the Laplace matrix B = I + diag(w) K diag(w) (w = W^1/2).
 int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, const double* B,
-          double* X, const pkm_solve_opts* o, pkm_solve_info* info) {
+          double* X, const pkm_solve_opts* o, pkm_solve_info* info, const double* wscale) {
     const int64_t n = prob->n;
     hipStream_t s = ctx->stream;
     const int prec = o->prec;
@@ -340,6 +359,20 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     Flags* hfl = static_cast<Flags*>(ctx->pinned);
     const int64_t tot = n * k;
     const unsigned gb = unsigned(cdiv(tot, 256));
+    if (wscale) ctx->pcg[5].ensure(vec);
+    // Y = A V for the system matrix A (see above), product arithmetic `pr`
+    auto apply_A = [&](int pr, const double* V, double* Y) {
+        if (!wscale) {
+            mvm(ctx, pr, k, V, Y);
+            return;
+        }
+        double* sv = ctx->pcg[5].as<double>();
+        k_scale_rows<<<gb, 256, 0, s>>>(n, k, wscale, V, sv);
+        PKM_CHECK_LAUNCH();
+        mvm_shift(ctx, pr, k, sv, Y, 0.0);
+        k_scale_rows_add<<<gb, 256, 0, s>>>(n, k, wscale, V, 1.0, Y);
+        PKM_CHECK_LAUNCH();
+    };
 
     auto precond = [&](const double* R, double* Zo) {
         if (pc) precond_apply(ctx, pc, k, R, Zo);
@@ -352,7 +385,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     };
     int64_t true_count = 0;
     auto true_residual = [&]() {   // r <- b - K_y x in FP64 for live columns
-        mvm(ctx, PKM_FP64, k, X, tmp);
+        apply_A(PKM_FP64, X, tmp);
         k_true_res<<<gb, 256, 0, s>>>(n, k, st, B, tmp, r);
         PKM_CHECK_LAUNCH();
         dot_part(ctx, r, r, n, k, partA);
@@ -363,7 +396,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
 
     // r0 = b - K_y x0, z0 = P^-1 r0, p0 = z0
     if (o->use_x0) {
-        mvm(ctx, PKM_FP64, k, X, tmp);
+        apply_A(PKM_FP64, X, tmp);
         k_sub<<<gb, 256, 0, s>>>(tot, B, tmp, r);
         PKM_CHECK_LAUNCH();
         ++true_count;
@@ -431,7 +464,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     const int check = o->check_every;
     const int reliable = o->reliable_every;
     while (f.live > 0 && it < o->max_iter) {
-        mvm(ctx, cur, k, p, Ap);
+        apply_A(cur, p, Ap);
         dot_part(ctx, p, Ap, n, k, partA);
         k_alpha<<<1, 256, 0, s>>>(partA, k, st);
         PKM_CHECK_LAUNCH();
@@ -474,7 +507,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     k_mark_maxiter<<<1, 256, 0, s>>>(k, st);
     PKM_CHECK_LAUNCH();
     // final FP64 true residual of every column for the report
-    mvm(ctx, PKM_FP64, k, X, tmp);
+    apply_A(PKM_FP64, X, tmp);
     k_sub<<<gb, 256, 0, s>>>(tot, B, tmp, tmp);
     PKM_CHECK_LAUNCH();
     dot_part(ctx, tmp, tmp, n, k, partA);

@@ -140,6 +140,7 @@ struct pkm_ctx {
     pkm::DevBuf ws_pitc[2];             // PITC setup: block inverses, L_D^-1 Phi
     pkm::DevBuf cross[4];               // cross-product operands and prediction scratch
     pkm::DevBuf pred[3];                // predictive variance: I, K(X, X_*), solutions
+    pkm::DevBuf lap[14];                // Laplace approximation vectors and blocks
     pkm::DevBuf batch[16];              // batched-solve workspace
     void* pinned = nullptr;   // pinned host staging area (PKM_PINNED_BYTES)
 };
@@ -195,6 +196,11 @@ F32Out mvm_k32(pkm_ctx* ctx, int k, const double* V, int ldv);
 // BF16 products (prec PKM_BF16X1 / PKM_BF16X3), same partial-sum layout.
 F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv);
 void prepare_bf16(pkm_ctx* ctx);
+
+// ---- PCG (pcg.hip): K_y X = B, or B_laplace X = B when wscale (W^1/2) is given
+int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, const double* B,
+          double* X, const pkm_solve_opts* o, pkm_solve_info* info,
+          const double* wscale = nullptr);
 
 // ---- cross products (prediction) ----
 void prepare_cross64(pkm_ctx* ctx, const pkm_problem* prob, const double* Xa, int64_t na,

@@ -10,8 +10,6 @@
 
 namespace pkm {
 
-int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, const double* B,
-          double* X, const pkm_solve_opts* o, pkm_solve_info* info);
 
 // I (k x k) on the device
 __global__ void k_eye(int64_t k, double* __restrict__ I) {

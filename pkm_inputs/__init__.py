@@ -36,7 +36,7 @@ import math
 import numpy as np
 
 __all__ = ["Problem", "make", "WORKLOADS", "rademacher", "inducing_indices",
-           "batched_problems", "mlp_params"]
+           "batched_problems", "mlp_params", "classification"]
 
 
 @dataclasses.dataclass
@@ -165,6 +165,22 @@ def mlp_params(seed: int = 0, d_in: int = 8, hidden: int = 128, rank: int = 128,
         "W3": rng.standard_normal((hidden, rank)) / math.sqrt(hidden) * out_scale,
         "b3": np.zeros(rank),
     }
+
+
+def classification(seed: int = 0, n: int = 4096, d: int = 14, m: int | None = None):
+    """Binary labels for GP classification: X ~ U[0,1]^d, latent
+    g = sum_k sin(3 x_k) + 0.3 eps, y = +1 where g is above its median, -1
+    below (balanced classes); lengthscales LogU[0.5 sqrt(d), sqrt(d)],
+    sigma2 = 1; m = sqrt(n) inducing indices (rounded to 16).  Returns
+    (X, y, lengthscales, sigma2, idx)."""
+    rng = np.random.default_rng(seed)
+    X = rng.random((n, d))
+    g = np.sin(3.0 * X).sum(axis=1) + 0.3 * rng.standard_normal(n)
+    y = np.where(g > np.median(g), 1.0, -1.0)
+    ls = _loguniform(rng, 0.5 * math.sqrt(d), math.sqrt(d), size=d)
+    m = m if m is not None else max(16, 16 * round(math.sqrt(n) / 16))
+    idx = inducing_indices(rng, n, min(m, n))
+    return np.ascontiguousarray(X), y, ls, 1.0, idx
 
 
 WORKLOADS = ("small_fp64", "block_fp32", "mixed", "learned")
