@@ -306,7 +306,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", default="bf16x3", choices=("fp32", "bf16x3", "bf16x1", "fp64"),
                     help="arithmetic of the kernel product inside the loop (the mixed path)")
-    ap.add_argument("--plain", default="fp32", choices=("fp32", "none"),
+    ap.add_argument("--plain", default="fp32", choices=("fp32", "fp64", "none"),
                     help="also time this product arithmetic for the mixed-vs-plain comparison")
     ap.add_argument("--reliable", type=int, default=50)
     ap.add_argument("--ks", default="", help="mvm mode: comma-separated column counts")
