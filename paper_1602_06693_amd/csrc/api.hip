@@ -113,6 +113,7 @@ int pkm_create(pkm_ctx** out, int device, void* stream) {
         ctx->stream = static_cast<hipStream_t>(stream);
         PKM_HIP(hipEventCreate(&ctx->ev0));
         PKM_HIP(hipEventCreate(&ctx->ev1));
+        for (auto& e : ctx->poll_ev) PKM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         PKM_HIP(hipHostMalloc(&ctx->pinned, PKM_PINNED_BYTES, hipHostMallocDefault));
         return PKM_OK;
     });
@@ -148,6 +149,8 @@ int pkm_destroy(pkm_ctx* ctx) {
     for (auto& b : ctx->batch) b.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    for (auto& e : ctx->poll_ev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
     return PKM_OK;

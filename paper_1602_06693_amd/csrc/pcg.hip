@@ -378,10 +378,29 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         if (pc) precond_apply(ctx, pc, k, R, Zo);
         else PKM_HIP(hipMemcpyAsync(Zo, R, vec, hipMemcpyDeviceToDevice, s));
     };
+    // Lag-one polling: the flags of a step go to pinned slot 1 or 2 behind
+    // that step's kernels, and the host reads the previous poll's slot while
+    // the current step runs, so the stream never drains between steps.  The
+    // conditions read that way only ever hold from then on (no live column,
+    // no stepping column, a breakdown) until the host itself acts on them, so
+    // a stale copy costs at most one idle step.
+    int lag_slot = -1;   // slot whose copy is still unread (-1: none)
     auto poll = [&]() {
         PKM_HIP(hipMemcpyAsync(hfl, fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
         PKM_HIP(hipStreamSynchronize(s));
+        lag_slot = -1;   // in-flight copies completed and are superseded
         return *hfl;
+    };
+    auto poll_lagged = [&](Flags& out) {
+        const int slot = lag_slot == 1 ? 2 : 1;
+        PKM_HIP(hipMemcpyAsync(hfl + slot, fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
+        PKM_HIP(hipEventRecord(ctx->poll_ev[slot - 1], s));
+        const int prev = lag_slot;
+        lag_slot = slot;
+        if (prev < 0) return false;
+        PKM_HIP(hipEventSynchronize(ctx->poll_ev[prev - 1]));
+        out = hfl[prev];
+        return true;
     };
     int64_t true_count = 0;
     auto true_residual = [&]() {   // r <- b - K_y x in FP64 for live columns
@@ -476,7 +495,15 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         ++it;
         bool do_true = cur != PKM_FP64 && reliable > 0 && it % reliable == 0;
         if (!do_true && (it % check == 0 || it == o->max_iter)) {
-            f = poll();
+            Flags lagged;
+            if (it == o->max_iter) {
+                f = poll();
+            } else if (poll_lagged(lagged)) {
+                f = lagged;
+            } else {
+                f.broke = 0;   // first poll of the loop: nothing read yet
+                f.pending = 1;
+            }
             if (f.broke > 0 && cur != PKM_FP64) {
                 f = escalate();
             } else {

@@ -131,6 +131,7 @@ struct pkm_ctx {
     bool timing = false;
     pkm::MvmStats stats[4];
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};   // lag-one status polls of the solvers
     pkm::Prepared prep;                 // the context's own prepared inputs
     pkm::Prepared* active = &prep;      // inputs the kernels use (batched solves switch it)
     pkm::Prepared& P() { return *active; }
