@@ -507,7 +507,12 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // FP64 MFMA.  Wave w owns the 16 Psi columns j0 .. j0 + 15; lane l feeds
 // A[j0 + l % 16][i] = Psi[i][j0 + l % 16] and B[i][c] = R[i][c0 + 16 kt + l % 16]
 // for rows i = ib + 4 (l / 16) + q, so each load instruction reads four rows
-// of 16 consecutive doubles (whole 128-byte lines of Psi).
+// of 16 consecutive doubles (whole 128-byte lines of Psi).  Whole 16-row
+// blocks load without guards -- a lane past the last column or past column
+// kc reads a clamped in-bounds address, which only feeds output entries that
+// are never stored -- and the next block's loads are issued before this
+// block's MFMAs, so a wave keeps a block of HBM reads in flight behind its
+// matrix-core work; the ragged last block of a chunk loads under guards.
 template <int KT>
 __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, int m,
                                                 const double* __restrict__ R, int k, int c0,
@@ -520,29 +525,61 @@ __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, 
     const int64_t i0 = int64_t(blockIdx.y) * rows_per_chunk;
     const int64_t i1 = min(n, i0 + rows_per_chunk);
     const int jj = j0 + cc;
-    const bool jv = jj < m;
+    const int jc = min(jj, m - 1);
+    int col[KT];
     bool cv[KT];
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt) cv[kt] = 16 * kt + cc < kc;
+    for (int kt = 0; kt < KT; ++kt) {
+        cv[kt] = 16 * kt + cc < kc;
+        col[kt] = c0 + min(16 * kt + cc, kc - 1);
+    }
     f64x4 acc[KT];
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) acc[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t ib = i0; ib < i1; ib += 16) {
-        double a[4], b[4][KT];
+    const int64_t ifull = i0 + ((i1 - i0) & ~int64_t(15));
+    double a[4], b[4][KT];
+    auto load = [&](int64_t ib, double (&la)[4], double (&lb)[4][KT]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t i = ib + 4 * g + q;
-            const bool iv = i < i1;
-            a[q] = (iv && jv) ? psi[i * m + jj] : 0.0;
+            la[q] = psi[i * m + jc];
 #pragma unroll
-            for (int kt = 0; kt < KT; ++kt)
-                b[q][kt] = (iv && cv[kt]) ? R[i * k + c0 + 16 * kt + cc] : 0.0;
+            for (int kt = 0; kt < KT; ++kt) lb[q][kt] = R[i * k + col[kt]];
         }
+    };
+    auto step = [&](const double (&la)[4], const double (&lb)[4][KT]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt)
-                acc[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q][kt], acc[kt], 0, 0, 0);
+                acc[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[q], lb[q][kt], acc[kt], 0, 0, 0);
+    };
+    // two register buffers in turn: a block's loads are issued one block
+    // ahead of its MFMAs and never copied (a copy would wait for them)
+    // (unconditional loads -- past the end they re-read the last block -- so
+    // that every wait counts exactly the loads it needs)
+    double a2[4], b2[4][KT];
+    if (i0 < ifull) {
+        const int64_t last = ifull - 16;
+        load(i0, a, b);
+        for (int64_t ib = i0; ib < ifull; ib += 32) {
+            load(min(ib + 16, last), a2, b2);
+            step(a, b);
+            if (ib + 16 >= ifull) break;
+            load(min(ib + 32, last), a, b);
+            step(a2, b2);
+        }
+    }
+    if (ifull < i1) {   // ragged last block: rows past i1 contribute zero
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = ifull + 4 * g + q;
+            const bool iv = i < i1;
+            a[q] = iv ? psi[i * m + jc] : 0.0;
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) b[q][kt] = iv ? R[i * k + col[kt]] : 0.0;
+        }
+        step(a, b);
     }
     // FP64 16x16x4 results: lane l holds rows l / 16 + 4 r (here: Psi columns)
 #pragma unroll
@@ -576,10 +613,15 @@ __global__ __launch_bounds__(256) void k_sum_chunks(const double* __restrict__ p
 }
 
 // Phase 2: Z = D^-1 R - Psi T for columns [c0, c0 + 16 KT).  Each wave owns
-// 16 rows; lane l reads Psi[row0 + l % 16][m0 + 4 (l / 16) + q], q = 0..3,
-// so four lanes cover a 128-byte line of a row, and feeds 16x16x4 FP64 MFMAs
-// whose reduction index q pairs with the matching rows of T.
-template <int KT>
+// U 16-row tiles, so every T value it reads (T is zero-padded to
+// m_pad x 16 KT, read without guards) feeds U MFMAs (U = 2 halves the T
+// traffic from L2 once T has two or more column tiles); lane l reads
+// Psi[row + l % 16][m0 + 4 (l / 16) + q], q = 0..3 (32 contiguous bytes; four
+// lanes cover a 128-byte line of a row) for each tile, and the reduction
+// index q pairs with the matching rows of T.  Whole 16-column blocks load
+// without guards (a row past n reads row 0 and is never stored) and one
+// block ahead of their MFMAs; a ragged last block loads under guards.
+template <int KT, int U>
 __global__ __launch_bounds__(256) void k_apply_z(const double* __restrict__ psi, int m,
                                                  const double* __restrict__ T, int ldt,
                                                  const double* __restrict__ dinv,
@@ -587,39 +629,81 @@ __global__ __launch_bounds__(256) void k_apply_z(const double* __restrict__ psi,
                                                  int64_t n, double* __restrict__ Z) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane >> 4, rr = lane & 15;
-    const int64_t row0 = (int64_t(blockIdx.x) * 4 + w) * 16;
+    const int64_t row0 = (int64_t(blockIdx.x) * 4 + w) * 16 * U;
     if (row0 >= n) return;
-    const int64_t row = row0 + rr;
-    const bool rv = row < n;
-    const double* prow = psi + (rv ? row : 0) * m;
-    f64x4 acc[KT];
+    const double* prow[U];
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt) acc[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int m0 = 0; m0 < m; m0 += 16) {
-        double a[4];
+    for (int u = 0; u < U; ++u) {
+        const int64_t row = row0 + 16 * u + rr;
+        prow[u] = psi + (row < n ? row : 0) * m;
+    }
+    f64x4 acc[U][KT];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int mm = m0 + 4 * g + q;
-            a[q] = (rv && mm < m) ? prow[mm] : 0.0;
-        }
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double* trow = T + int64_t(m0 + 4 * g + q) * ldt + rr;
+        for (int kt = 0; kt < KT; ++kt) acc[u][kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int mfull = m & ~15;
+    double a[U][4], t[4][KT];
+    auto load_t = [&](int m0, double (&lt)[4][KT]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt)
-                acc[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], trow[16 * kt], acc[kt], 0, 0, 0);
+                lt[q][kt] = T[int64_t(m0 + 4 * g + q) * ldt + rr + 16 * kt];
+    };
+    auto load = [&](int m0, double (&la)[U][4], double (&lt)[4][KT]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) la[u][q] = prow[u][m0 + 4 * g + q];
+        load_t(m0, lt);
+    };
+    auto step = [&](const double (&la)[U][4], const double (&lt)[4][KT]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    acc[u][kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[u][q], lt[q][kt],
+                                                                      acc[u][kt], 0, 0, 0);
+    };
+    // two register buffers in turn (see k_psit_r)
+    double a2[U][4], t2[4][KT];
+    if (mfull > 0) {
+        const int last = mfull - 16;
+        load(0, a, t);
+        for (int m0 = 0; m0 < mfull; m0 += 32) {
+            load(min(m0 + 16, last), a2, t2);
+            step(a, t);
+            if (m0 + 16 >= mfull) break;
+            load(min(m0 + 32, last), a, t);
+            step(a2, t2);
         }
+    }
+    if (mfull < m) {   // ragged last block: columns past m contribute zero
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int mm = mfull + 4 * g + q;
+                a[u][q] = mm < m ? prow[u][mm] : 0.0;
+            }
+        load_t(mfull, t);
+        step(a, t);
     }
     // FP64 16x16x4 results: lane l holds rows l / 16 + 4 r of column l % 16
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t i = row0 + g + 4 * r;
-            const int c = c0 + 16 * kt + rr;
-            if (i < n && c < k)
-                Z[i * k + c] = (dinv ? dinv[i] * R[i * k + c] : Z[i * k + c]) - acc[kt][r];
-        }
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = row0 + 16 * u + g + 4 * r;
+                const int c = c0 + 16 * kt + rr;
+                if (i < n && c < k)
+                    Z[i * k + c] = (dinv ? dinv[i] * R[i * k + c] : Z[i * k + c]) - acc[u][kt][r];
+            }
 }
 
 template <int KC>
@@ -648,8 +732,9 @@ static void apply_chunk(pkm_ctx* ctx, const pkm_precond* pc, int k, int c0, cons
     PKM_CHECK_LAUNCH();
     // PITC: Z already holds blockdiag(D^-1) R; the kernel subtracts Psi T
     const double* dv = pc->kind == PKM_PC_PITC ? nullptr : pc->dinv.as<double>();
-    k_apply_z<KT><<<(unsigned)cdiv(n, 64), 256, 0, s>>>(pc->psi.as<double>(), m, T, ldt, dv, R,
-                                                        k, c0, n, Z);
+    constexpr int U = KT >= 2 ? 2 : 1;
+    k_apply_z<KT, U><<<(unsigned)cdiv(n, 64 * U), 256, 0, s>>>(pc->psi.as<double>(), m, T, ldt,
+                                                              dv, R, k, c0, n, Z);
     PKM_CHECK_LAUNCH();
 }
 
