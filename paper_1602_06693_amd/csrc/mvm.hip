@@ -328,9 +328,14 @@ __device__ inline double exp2_tab(double S, const double* __restrict__ tab) {
 // r = 0..3 -- exactly the A operands of four K V MFMAs whose B operands are
 // V[j0 + 4 r + l / 16][16 q + l % 16].  exp2 runs on the vector ALUs in
 // FP64 (exp2_tab).  Wave: U i-tiles of 16 rows; grid.y splits the j tiles.
+// KR = 1: one column past the KT MFMA tiles (k = 16 KT + 1, e.g. a target
+// and 16 probes) is summed on the vector ALUs -- four FP64 FMAs per lane and
+// tile against the four MFMAs a further 16-column tile would cost on this
+// matrix-core-bound kernel -- and reduced across the four lanes of a row
+// (l % 16 equal) at the end.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <int S4, int KT, int U>
+template <int S4, int KT, int U, int KR = 0>
 __global__ __launch_bounds__(256) void k_mvm_f64x(const double* __restrict__ jside,
                                                   const double* __restrict__ iside,
                                                   const double* __restrict__ V, int64_t ldv,
@@ -356,11 +361,14 @@ __global__ __launch_bounds__(256) void k_mvm_f64x(const double* __restrict__ jsi
     for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int q = 0; q < KT; ++q) acc[u][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double racc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) racc[u] = 0.0;
     for (int64_t t = t0; t < t1; ++t) {
         double bj[S4];
 #pragma unroll
         for (int q = 0; q < S4; ++q) bj[q] = jside[(t * 64 + lane) * S4 + q];
-        double vb[KT][4];
+        double vb[KT][4], vr[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t j = t * 16 + 4 * r + g;
@@ -369,6 +377,7 @@ __global__ __launch_bounds__(256) void k_mvm_f64x(const double* __restrict__ jsi
                 const int c = 16 * q + cc;
                 vb[q][r] = (j < n && c < kcols) ? V[j * ldv + c] : 0.0;
             }
+            if (KR) vr[r] = j < n ? V[j * ldv + 16 * KT] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -384,10 +393,24 @@ __global__ __launch_bounds__(256) void k_mvm_f64x(const double* __restrict__ jsi
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     acc[u][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[r], vb[q][r], acc[u][q], 0, 0, 0);
+            if (KR) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) racc[u] = fma(kv[r], vr[r], racc[u]);
+            }
         }
     }
     // FP64 16x16x4 results: lane l holds rows l / 16 + 4 r, column l % 16
     double* po = part + blockIdx.y * split_stride;
+    if (KR) {   // lane l holds row l % 16's sum over the j with j % 4 = l / 16
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double v = racc[u];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            const int64_t i = (itile0 + u) * 16 + cc;
+            if (g == 0 && i < n_out) po[i * ldp + 16 * KT] = v;
+        }
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -404,6 +427,14 @@ template <int S4>
 static void launch_f64x(int KT, dim3 grid, hipStream_t s, const double* js, const double* is,
                         const double* V, int64_t ldv, int k, int64_t n, int64_t ntiles, int64_t n_out,
                         double* part, int64_t ldp, int64_t sstride, int64_t tps) {
+    if (k % 16 == 1 && k > 16) {   // KT MFMA tiles and one column on the vector ALUs
+        switch (k / 16) {
+            case 1: k_mvm_f64x<S4, 1, 2, 1><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, n_out, part, ldp, sstride, tps); return;
+            case 2: k_mvm_f64x<S4, 2, 2, 1><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, n_out, part, ldp, sstride, tps); return;
+            case 3: k_mvm_f64x<S4, 3, 2, 1><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, n_out, part, ldp, sstride, tps); return;
+            default: break;
+        }
+    }
     switch (KT) {
         case 1: k_mvm_f64x<S4, 1, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, n_out, part, ldp, sstride, tps); break;
         case 2: k_mvm_f64x<S4, 2, 2><<<grid, 256, 0, s>>>(js, is, V, ldv, k, n, ntiles, n_out, part, ldp, sstride, tps); break;
