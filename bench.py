@@ -38,6 +38,33 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0   # dense
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# Issue costs on gfx950 measured with throughput probes (cycles per wave64
+# instruction at 2.4 GHz): a BF16 16x16x32 MFMA holds the SIMD's vector issue
+# for about half of its 17 cycles, v_exp_f32 takes 8, a full-rate VALU op 4.
+ISSUE_MFMA_HALF, ISSUE_EXP, ISSUE_VALU, SIMDS, CLOCK_HZ = 8.5, 8.0, 4.0, 1024, 2.4e9
+
+
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs, calibrated on a 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE
+# x 1.0): (workload, product, n, k) -> bytes.  Valid while the kernel is
+# unchanged since the counters were taken.
+RECORDED_TRAFFIC = {("block_fp32", "bf16x3", 65536, 17): (43070.6 * 2.0 + 65536.0) * 1024}
+
+
+def _recorded_traffic(p, prec):
+    return RECORDED_TRAFFIC.get((p.name, prec, p.n, p.B.shape[1]))
+
+
+def bf16_issue_model_ms(n, d, k, split3):
+    """Lower bound on the BF16 product's time from its vector-issue budget:
+    per 512 kernel entries (16 rows x 32 columns) and lane, 8 exp2, 24 other
+    VALU ops with split 3 (4 with split 1), and 2 ceil((6 d + 6) / 32) exponent
+    plus (3 or 1) ceil(k / 16) K V MFMAs at half their duration."""
+    s6 = -(-(6 * d + 6) // 32)
+    kt = -(-k // 16)
+    mfma = 2 * s6 + (3 if split3 else 1) * kt
+    cycles = 8 * ISSUE_EXP + (24 if split3 else 4) * ISSUE_VALU + mfma * ISSUE_MFMA_HALF
+    return (n * n / 512.0) * cycles / (SIMDS * CLOCK_HZ) * 1e3
 
 
 _INPUTS = {
@@ -48,11 +75,18 @@ _INPUTS = {
 }
 
 
+def _replacement(reliable):
+    if reliable < 0:
+        return (f"FP64 residual replacement every {-reliable} steps, doubling while the "
+                f"true/recursive residual ratio stays <= 2 (up to {-8 * reliable})")
+    return f"FP64 residual replacement every {reliable} steps"
+
+
 def _describe(p, m, prec, reliable):
     return (f"{p.name}: n={p.n}, d={p.d}, {_INPUTS.get(p.name, '')}, "
             f"sigma2={p.sigma2}, lambda={p.lam}, k=1+{p.Z.shape[1]} (y + Rademacher probes), "
             f"Nystrom m={m}, tol={p.tol} (certified FP64 true residual), {prec} kernel "
-            f"products, FP64 vectors, FP64 residual replacement every {reliable} steps; "
+            f"products, FP64 vectors, {_replacement(reliable)}; "
             f"step = preconditioner setup + block PCG solve + gradient pass")
 
 
@@ -183,7 +217,11 @@ def batched_mode(pk, ctx, a):
     gps = [pk.Problem(dev(p.X), p.lengthscales, p.sigma2, p.lam) for p in probs]
     Bs = [dev(p.B) for p in probs]
     idxs = [dev(p.idx) for p in probs]
-    opts = pk.make_opts(tol=1e-6, prec=prec, reliable_every=a.reliable)
+    # max_iter 20000: a solve that cannot reach the tolerance ends (and reports
+    # it) instead of running the library default of 100000 steps
+    # both arms replace every |reliable| steps (the batched solver has no
+    # adaptive period), so the comparison is like for like
+    opts = pk.make_opts(tol=1e-6, prec=prec, reliable_every=abs(a.reliable), max_iter=20000)
     log = lambda msg: print(msg, file=sys.stderr, flush=True)
 
     def setups():
@@ -308,7 +346,8 @@ def main():
                     help="arithmetic of the kernel product inside the loop (the mixed path)")
     ap.add_argument("--plain", default="fp32", choices=("fp32", "fp64", "none"),
                     help="also time this product arithmetic for the mixed-vs-plain comparison")
-    ap.add_argument("--reliable", type=int, default=50)
+    ap.add_argument("--reliable", type=int, default=-50,
+                    help="FP64 replacement period; negative: adaptive from its magnitude")
     ap.add_argument("--ks", default="", help="mvm mode: comma-separated column counts")
     ap.add_argument("--mvm-precs", default="bf16x3",
                     help="mvm mode: comma-separated arithmetics (fp64,fp32,bf16x1,bf16x3)")
@@ -442,10 +481,17 @@ def main():
         "mvm_ms": mixed["mvm_ms"],
         "fp64_true_residual_ms": mixed["fp64_ms"],
         "roofline": {"bound": "mfma", "achieved": mixed["tflops"], "peak": peak,
-                     "unit": "TFLOP/s", "frac": mixed["tflops"] / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": mixed["tflops"] / peak,
+                     "traffic": _recorded_traffic(p, a.prec),
                      "kernel": kname, "flops_per_launch": mixed["flops_per_launch"],
                      "flop_count": "n^2 (2 d + 2 k) per product"},
     }
+    if bf16:   # the product's actual bound: vector-ALU issue (exp2, splits) + MFMA issue
+        model = bf16_issue_model_ms(p.n, p.d, p.B.shape[1], a.prec == "bf16x3")
+        out["roofline"]["issue_bound"] = {
+            "model_ms": model, "achieved_ms": mixed["mvm_ms"], "frac": model / mixed["mvm_ms"],
+            "model": "per 512 entries and lane: 8 exp2 x 8 cycles + (24|4) VALU x 4 + "
+                     "MFMAs x 8.5 (half of 17), over 1024 SIMDs at 2.4 GHz"}
     if plain is not None:
         out["plain"] = {"product": a.plain, "value": statistics.median(plain["times"]),
                         "iters": int(plain["info"].total_iters),

@@ -110,7 +110,16 @@ typedef struct {
                                 for the product inside the loop; default
                                 PKM_FP32                                    */
     int32_t reliable_every;  /* FP64 true-residual replacement period (non-FP64
-                                products only); default 25                  */
+                                products only); default 25.  Negative: the
+                                period adapts (pkm_solve): it starts at
+                                -reliable_every, doubles (up to 8x the start)
+                                after a replacement whose largest
+                                true/recursive residual ratio is at most 2 and
+                                whose largest true residual fell below 0.7 of
+                                its previous value, and returns to the start
+                                after any other;
+                                pkm_solve_batched uses the magnitude as a
+                                fixed period                                */
     int32_t check_every;     /* host convergence poll period; default 1     */
     int32_t use_x0;          /* nonzero: X holds x0 on entry; else x0 = 0    */
 } pkm_solve_opts;
@@ -128,7 +137,8 @@ typedef struct {
     int32_t  prec_final;     /* product arithmetic in use at the end: the
                                 requested one, or a more accurate one if the
                                 solve escalated (see pkm_solve)             */
-    int32_t  reserved;
+    int32_t  refined;        /* 1 if the columns entered refinement mode (see
+                                pkm_solve) at some point, else 0            */
 } pkm_solve_info;
 
 /* ---- context ------------------------------------------------------------
@@ -223,8 +233,9 @@ int pkm_precond_destroy(pkm_precond* pc);
  * also runs every reliable_every steps.  A reduced-precision product whose
  * error is too large for lambda shows as a largest true residual that stops
  * decreasing (three replacements in a row without falling below 0.7 of its
- * best value), as a true residual above |b| while the recursive one is 100
- * times smaller, or as a column breakdown.  On the first stall the columns
+ * best value -- and at least 150 steps unless it grew at the latest one), as
+ * a true residual above |b| while the recursive one is 100 times smaller, or
+ * as a column breakdown.  On the first stall the columns
  * switch to refinement mode: they restart their directions (p = z) at every
  * replacement and stop stepping once the recursive residual is 1e-3 below
  * the last true one (outer FP64 iterative refinement around short inner

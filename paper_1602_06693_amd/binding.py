@@ -71,7 +71,7 @@ class pkm_solve_info(C.Structure):
     _fields_ = [("iters", C.POINTER(C.c_int64)), ("relres_true", C.POINTER(C.c_double)),
                 ("relres_rec", C.POINTER(C.c_double)), ("col_status", C.POINTER(C.c_int32)),
                 ("total_iters", C.c_int64), ("true_residuals", C.c_int64),
-                ("solve_ms", C.c_double), ("prec_final", C.c_int32), ("reserved", C.c_int32)]
+                ("solve_ms", C.c_double), ("prec_final", C.c_int32), ("refined", C.c_int32)]
 
 
 class pkm_laplace_info(C.Structure):
@@ -321,6 +321,10 @@ class SolveInfo:
     @property
     def prec_final(self):
         return self.struct.prec_final
+
+    @property
+    def refined(self):
+        return bool(self.struct.refined)
 
 
 def make_opts(tol=1e-6, max_iter=100000, prec=PKM_FP32, reliable_every=25, check_every=1,

@@ -46,7 +46,7 @@ int mlp_d_in(const pkm_mlp* net);
 using namespace pkm;
 
 static thread_local std::string g_last_error = "no error";
-static constexpr size_t PKM_PINNED_BYTES = 1 << 16;
+static constexpr size_t PKM_PINNED_BYTES = 1 << 18;   // 3 batched status slots at P = 4096
 
 template <class F>
 static int guarded(pkm_ctx* ctx, F&& f) {
@@ -465,7 +465,10 @@ static void fill_opts(const pkm_solve_opts* in, pkm_solve_opts* o) {
     PKM_REQUIRE(std::isfinite(o->tol) && o->tol > 0.0, "tol must be > 0");
     PKM_REQUIRE(o->max_iter >= 1, "max_iter must be >= 1");
     PKM_REQUIRE(o->prec >= PKM_FP64 && o->prec <= PKM_BF16X3, "unknown precision");
-    PKM_REQUIRE(o->reliable_every >= 1 && o->check_every >= 1, "periods must be >= 1");
+    PKM_REQUIRE(o->reliable_every != 0 && o->check_every >= 1,
+                "periods must be >= 1 (a negative replacement period adapts)");
+    PKM_REQUIRE(o->reliable_every >= -(1 << 24) && o->reliable_every <= (1 << 24),
+                "replacement period must be at most 2^24 steps");
 }
 
 int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int32_t k,

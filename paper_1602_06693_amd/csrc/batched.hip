@@ -24,6 +24,9 @@
 
 #include "pkm_internal.h"
 
+#include <cstdio>
+#include <cstdlib>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -259,9 +262,20 @@ __global__ void k_binit(const double* __restrict__ pbb, const double* __restrict
     st[e] = s;
 }
 
+// Also clears the status accumulators that k_brr fills later in the same
+// step (the previous step's copies to the host were queued before this
+// kernel; no kernel in between reads them).
 __global__ void k_balpha(const double* __restrict__ ppap, const int* __restrict__ rbrange, int P,
-                         int k, BCol* __restrict__ st) {
+                         int k, BCol* __restrict__ st, BFlags* __restrict__ fl,
+                         int* __restrict__ live_prob, int* __restrict__ broke_prob,
+                         int* __restrict__ act_prob) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) *fl = BFlags{};
+    if (e < P) {
+        live_prob[e] = 0;
+        broke_prob[e] = 0;
+        act_prob[e] = 0;
+    }
     if (e >= P * k) return;
     const int b = e / k, c = e - b * k;
     BCol s = st[e];
@@ -868,9 +882,19 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     const int64_t tot = ntot * k;
     const unsigned gb = unsigned(cdiv(tot, 256));
     const unsigned gpk = unsigned(cdiv(int64_t(P) * k, 256));
-    BFlags* hfl = static_cast<BFlags*>(ctx->pinned);
-    int* hact = reinterpret_cast<int*>(static_cast<char*>(ctx->pinned) + 64);   // P ints
-    int* hstep = hact + P;                                                        // P ints
+    // pinned status slots: slot 0 for synchronous polls, 1 and 2 for the
+    // lag-one polls of the loop; each holds the flags, then P ints of "has
+    // active columns", then P ints of "has stepping columns"
+    const size_t slot_bytes = round_up(size_t(64) + sizeof(int) * 2 * size_t(P), 256);
+    auto slot_flags = [&](int q) {
+        return reinterpret_cast<BFlags*>(static_cast<char*>(ctx->pinned) + q * slot_bytes);
+    };
+    auto slot_act = [&](int q) {
+        return reinterpret_cast<int*>(static_cast<char*>(ctx->pinned) + q * slot_bytes + 64);
+    };
+    BFlags* hfl = slot_flags(0);
+    int* hact = slot_act(0);
+    int* hstep = hact + P;
 
     auto dots = [&](const double* u, const double* v, double* out) {
         k_bdot_part<<<nrb, 256, 0, s>>>(u, v, k, out);
@@ -884,17 +908,42 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     // host copies (as of the last poll) of the per-problem flags: act = has
     // active columns, ready = has active columns and all of them parked
     std::vector<int> act(P, 1), ready(P, 0), stepping(P, 1);
-    auto poll = [&]() {
-        PKM_HIP(hipMemcpyAsync(hfl, fl, sizeof(BFlags), hipMemcpyDeviceToHost, s));
-        PKM_HIP(hipMemcpyAsync(hact, actp, sizeof(int) * P, hipMemcpyDeviceToHost, s));
-        PKM_HIP(hipMemcpyAsync(hstep, live, sizeof(int) * P, hipMemcpyDeviceToHost, s));
-        PKM_HIP(hipStreamSynchronize(s));
+    auto take = [&](int q) {
+        const int* ha = slot_act(q);
         for (int b = 0; b < P; ++b) {
-            act[b] = hact[b];
-            stepping[b] = hstep[b];
-            ready[b] = hact[b] && !hstep[b];
+            act[b] = ha[b];
+            stepping[b] = ha[P + b];
+            ready[b] = ha[b] && !ha[P + b];
         }
-        return *hfl;
+        return *slot_flags(q);
+    };
+    auto enqueue_copy = [&](int q) {
+        PKM_HIP(hipMemcpyAsync(slot_flags(q), fl, sizeof(BFlags), hipMemcpyDeviceToHost, s));
+        PKM_HIP(hipMemcpyAsync(slot_act(q), actp, sizeof(int) * P, hipMemcpyDeviceToHost, s));
+        PKM_HIP(hipMemcpyAsync(slot_act(q) + P, live, sizeof(int) * P, hipMemcpyDeviceToHost, s));
+    };
+    int lag_slot = -1;   // lagged slot whose copy is still unread (-1: none)
+    auto poll = [&]() {
+        enqueue_copy(0);
+        PKM_HIP(hipStreamSynchronize(s));
+        lag_slot = -1;   // in-flight copies completed and are superseded
+        return take(0);
+    };
+    // Lag-one poll (as in pkm_solve): this step's status goes to slot 1 or 2
+    // and the host reads the previous poll's slot, so the stream does not
+    // drain between steps.  What the loop acts on -- no live column, a
+    // problem whose active columns are all parked, a breakdown -- holds until
+    // the host itself acts on it, so a late read costs at most one idle step.
+    auto poll_lagged = [&](BFlags& out) {
+        const int q = lag_slot == 1 ? 2 : 1;
+        enqueue_copy(q);
+        PKM_HIP(hipEventRecord(ctx->poll_ev[q - 1], s));
+        const int prev = lag_slot;
+        lag_slot = q;
+        if (prev < 0) return false;
+        PKM_HIP(hipEventSynchronize(ctx->poll_ev[prev - 1]));
+        out = take(prev);
+        return true;
     };
     auto apply = [&](const double* R, double* Zo) {
         if (!it1.empty()) {
@@ -1065,7 +1114,8 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     // h_escm then marks those problems (they need a fresh true residual).
     std::vector<StallMonitor> mon(P);
     std::vector<unsigned long long> h_maxtru(2 * P);   // largest true residual, largest gap
-    std::vector<int> h_broke(P), h_esc(P), h_escm(P), refining(P, 0);
+    std::vector<int> h_broke(P), h_esc(P), h_escm(P), refining(P, 0), refined(P, 0);
+    int64_t it = 0;   // PCG steps so far
     auto escalate_check = [&](bool after_true) -> bool {
         if (prec == PKM_FP64) return false;
         PKM_HIP(hipMemcpyAsync(h_broke.data(), brokep, sizeof(int) * P, hipMemcpyDeviceToHost, s));
@@ -1079,15 +1129,11 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             h_escm[b] = 0;
             if (use64[b]) continue;
             bool stalled = false;
-            if (after_true) {
-                double mt;
-                std::memcpy(&mt, &h_maxtru[b], sizeof(double));
-                stalled = mon[b].stalled(mt);
-            }
             double mt = 0.0, mg = 0.0;
             if (after_true) {
                 std::memcpy(&mt, &h_maxtru[b], sizeof(double));
                 std::memcpy(&mg, &h_maxtru[P + b], sizeof(double));
+                stalled = mon[b].stalled(mt, it);
             }
             // diverging (true residual above the right-hand side while the
             // recursion believes it 100 times smaller), broken, or stalled
@@ -1103,6 +1149,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             } else if (stalled) {
                 h_esc[b] = 2;
                 refining[b] = 1;
+                refined[b] = 1;
                 mon[b].reset();
                 any = true;
             }
@@ -1133,6 +1180,8 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     PKM_CHECK_LAUNCH();
     BFlags f = poll();
     // FP64 replacement for the problems in mask, then the escalation test
+    // PKM_VERBOSE=1 reports every replacement round on stderr (long solves)
+    static const bool verbose = std::getenv("PKM_VERBOSE") != nullptr;
     auto replace = [&](const std::vector<int>& mask) {
         true_residual(mask);
         f = poll();
@@ -1140,28 +1189,46 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             true_residual(h_escm);
             f = poll();
         }
+        if (verbose) {
+            int n64 = 0, nref = 0, nact = 0;
+            for (int b = 0; b < P; ++b) {
+                n64 += use64[b];
+                nref += refining[b];
+                nact += act[b];
+            }
+            std::fprintf(stderr, "pkm_solve_batched: step %lld, %d of %d problems live, "
+                         "%d in refinement mode, %d on FP64 products, %d live columns\n",
+                         (long long)it, nact, P, nref, n64, f.live);
+        }
     };
     auto any_of = [](const std::vector<int>& v) {
         return std::any_of(v.begin(), v.end(), [](int q) { return q != 0; });
     };
     if (f.live > 0 && any_of(ready)) replace(ready);
-    int64_t it = 0;
     while (f.live > 0 && it < o->max_iter) {
         product(p, Ap);
         dots(p, Ap, partA);
-        k_balpha<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, st);
+        k_balpha<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, st, fl, live, brokep, actp);
         PKM_CHECK_LAUNCH();
         k_bupdate_xr<<<gb, 256, 0, s>>>(tot, k, d_rbprob, st, p, Ap, x, r);
         PKM_CHECK_LAUNCH();
         dots(r, r, partA);
-        reset_flags();
-        PKM_HIP(hipMemsetAsync(brokep, 0, sizeof(int) * P, s));
         k_brr<<<gpk, 256, 0, s>>>(partA, d_rbrange, P, k, o->tol, st, fl, live, brokep, actp);
         PKM_CHECK_LAUNCH();
         ++it;
-        bool do_true = prec != PKM_FP64 && o->reliable_every > 0 && it % o->reliable_every == 0;
+        // (a negative period is taken as its magnitude, fixed)
+        const int every = o->reliable_every < 0 ? -o->reliable_every : o->reliable_every;
+        bool do_true = prec != PKM_FP64 && it % every == 0;
+        bool have = false;
         if (!do_true && (it % o->check_every == 0 || it == o->max_iter)) {
-            f = poll();
+            if (it == o->max_iter) {
+                f = poll();
+                have = true;
+            } else {
+                have = poll_lagged(f);
+            }
+        }
+        if (have) {
             if (f.broke > 0 && escalate_check(false)) {
                 true_residual(h_escm);   // reactivated columns get their FP64 residual
                 f = poll();
@@ -1232,6 +1299,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     if (infos)
         for (int b = 0; b < P; ++b) {
             infos[b].prec_final = use64[b] ? PKM_FP64 : prec;
+            infos[b].refined = refined[b];
             infos[b].total_iters = it;
             infos[b].true_residuals = true_count;
             infos[b].solve_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();

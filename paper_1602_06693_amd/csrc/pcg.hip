@@ -446,10 +446,11 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     // FP64), broken columns resume, and every column restarts from its FP64
     // true residual in plain replacement mode.
     int cur = prec;
-    bool refining = false;
+    bool refining = false, ever_refined = false;
     // PKM_VERBOSE=1 reports every FP64 replacement on stderr (long solves)
     static const bool verbose = std::getenv("PKM_VERBOSE") != nullptr;
     StallMonitor mon;
+    int64_t it = 0;   // PCG steps so far
     auto escalate = [&]() {
         cur = (cur == PKM_BF16X1 || cur == PKM_BF16X3) ? PKM_FP32 : PKM_FP64;
         refining = false;
@@ -469,9 +470,10 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         // too coarse for lambda (PCG residual norms alone may rise early on)
         if (fl_now.live > 0 && fl_now.max_tru > 1.0 && fl_now.max_gap > 100.0)
             return escalate();
-        if (fl_now.live > 0 && mon.stalled(fl_now.max_tru)) {
+        if (fl_now.live > 0 && mon.stalled(fl_now.max_tru, it)) {
             if (refining) return escalate();
             refining = true;
+            ever_refined = true;
             k_set_restart<<<1, 256, 0, s>>>(k, st, kRefineEta);
             PKM_CHECK_LAUNCH();
             mon.reset();
@@ -479,9 +481,9 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         return fl_now;
     };
 
-    int64_t it = 0;
     const int check = o->check_every;
-    const int reliable = o->reliable_every;
+    ReplacementPeriod period(o->reliable_every);
+    int64_t last_true = 0;   // step of the last FP64 replacement
     while (f.live > 0 && it < o->max_iter) {
         apply_A(cur, p, Ap);
         dot_part(ctx, p, Ap, n, k, partA);
@@ -493,7 +495,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         k_rr<<<1, 256, 0, s>>>(partA, k, o->tol, st, fl);
         PKM_CHECK_LAUNCH();
         ++it;
-        bool do_true = cur != PKM_FP64 && reliable > 0 && it % reliable == 0;
+        bool do_true = cur != PKM_FP64 && it - last_true >= period.cur;
         if (!do_true && (it % check == 0 || it == o->max_iter)) {
             Flags lagged;
             if (it == o->max_iter) {
@@ -513,11 +515,14 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         }
         if (do_true) {
             true_residual();
+            last_true = it;
             f = judge(poll());
+            period.update(f.max_gap, f.max_tru);
             if (verbose)
                 std::fprintf(stderr, "pkm_solve: step %lld, product %d%s, live columns %d, "
-                             "largest true relative residual %.3e\n", (long long)it, cur,
-                             refining ? " (refinement mode)" : "", f.live, f.max_tru);
+                             "largest true relative residual %.3e, true/recursive %.3g\n",
+                             (long long)it, cur, refining ? " (refinement mode)" : "", f.live,
+                             f.max_tru, f.max_gap);
             if (f.live == 0) break;
         }
         if (verbose && cur == PKM_FP64 && it % 25 == 0)
@@ -573,6 +578,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         info->total_iters = it;
         info->true_residuals = true_count;
         info->prec_final = cur;
+        info->refined = ever_refined ? 1 : 0;
         info->solve_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
     }
     return code;

@@ -45,20 +45,55 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 
 // lambda; past that the true residual hovers around a floor.  "Stalled" means
 // three replacements in a row without dropping below 0.7 of the best value
 // seen at the current arithmetic.
+// Stall of the reduced-precision product: the largest true residual has not
+// fallen below 0.7 of its best value for three replacements in a row and,
+// unless it grew at the latest one, for at least kStallSteps PCG steps (the
+// step floor keeps a short replacement period from reading the early pace
+// of PCG as a stall; a growing residual needs no such patience).
+constexpr double kStallGap = 2.0;   // true / recursive ratio of a faithful recursion
+constexpr int64_t kStallSteps = 150;
+
 struct StallMonitor {
-    double best = 1e300;
+    double best = 1e300, last = 1e300;
     int since = 0;
-    bool stalled(double max_true) {
+    int64_t step_best = 0;
+    bool stalled(double max_true, int64_t step) {
         if (!(max_true > 0.0)) return false;   // nothing live
+        const bool grew = !(max_true < last);
+        last = max_true;
         if (max_true < 0.7 * best) {
             best = max_true;
             since = 0;
+            step_best = step;
         } else {
             ++since;
         }
-        return since >= 3;
+        return since >= 3 && (grew || step - step_best >= kStallSteps);
     }
-    void reset() { best = 1e300; since = 0; }
+    void reset() { best = last = 1e300; since = 0; step_best = 0; }
+};
+
+// Adaptive replacement period (a negative reliable_every): starts at
+// base = -reliable_every and doubles (up to 8 base) after a replacement that
+// finds the recursion faithful (largest true / recursive residual at most
+// kStallGap) and the largest true residual below 0.7 of its value at the
+// previous replacement -- progress that no stall test could fault -- and
+// returns to base after any other, so that a slow or stalling solve keeps
+// the base cadence of its stall test.
+struct ReplacementPeriod {
+    int base = 0, cur = 0;
+    bool adaptive = false;
+    double last = 1e300;
+    explicit ReplacementPeriod(int every)
+        : base(every < 0 ? -every : every), cur(every < 0 ? -every : every),
+          adaptive(every < 0) {}
+    void update(double max_gap, double max_true) {
+        if (!adaptive) return;
+        const bool fast = max_true < 0.7 * last;
+        last = max_true;
+        if (max_gap <= kStallGap && fast) cur = cur * 2 > 8 * base ? 8 * base : cur * 2;
+        else cur = base;
+    }
 };
 
 // Refinement mode: an inner PCG solve with the fast product ends once its

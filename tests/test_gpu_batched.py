@@ -45,8 +45,8 @@ def test_batched_matches_oracle_and_single_solves(ctx, prec, tmp_path):
                 pk.pkm_precond_destroy(pc)
     assert rc == pk.PKM_OK
     for p, X, inf, one in zip(probs, Xs, infos, singles):
-        print(p.name, p.n, p.d, p.lam, "batched", inf.prec_final, inf.iters.max(),
-              "single", one.prec_final, one.iters.max())
+        print(p.name, p.n, p.d, p.lam, "batched", inf.prec_final, inf.refined, inf.iters.max(),
+              "single", one.prec_final, one.refined, one.iters.max())
         tr = _true_relres(p, host(X))
         assert np.all(tr <= 1e-6 * 1.001), (p.name, tr)
         # The solver's own FP64 true residual agrees with the oracle's up to
@@ -57,10 +57,13 @@ def test_batched_matches_oracle_and_single_solves(ctx, prec, tmp_path):
         assert np.allclose(inf.relres_true, tr, rtol=1e-3, atol=1e-12), (inf.relres_true, tr)
         assert np.all(inf.col_status == pk.PKM_COL_CONVERGED)
         # same recurrences and product arithmetic as the single-problem path;
-        # a problem whose FP32 products were raised to FP64 counts the
-        # iterations of both phases, and the two solvers may raise at
-        # different replacement points, so only unraised problems compare
-        if inf.prec_final == prec and one.prec_final == prec:
+        # a problem whose FP32 products were raised to FP64, or that switched
+        # to refinement mode, took its own path (the two products differ in
+        # summation order, and near the FP32 limit that decides whether and
+        # when a replacement counts as a stall), so only problems that did
+        # neither in both solvers compare
+        if (inf.prec_final == prec and one.prec_final == prec
+                and not inf.refined and not one.refined):
             assert np.all(np.abs(inf.iters - one.iters) <= 0.1 * one.iters + 3), (inf.iters, one.iters)
     if prec == pk.PKM_FP32:
         lines = open(tmp_path / "tune.jsonl").read().strip().splitlines()

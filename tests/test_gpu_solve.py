@@ -181,3 +181,34 @@ def test_bf16_breakdown_escalates_at_small_lambda(ctx):
         pk.pkm_precond_destroy(pc)
     assert np.all(true_relres(p, host(X)) <= 1e-6 * 1.001)
     assert info.prec_final != pk.PKM_BF16X1
+
+
+def test_adaptive_replacement_period(ctx):
+    """A negative reliable_every adapts the FP64 replacement period: with
+    BF16x3 products on a 6000-point block_fp32 problem the recursion stays
+    faithful (true/recursive ratio ~1), so the period doubles and the solve
+    needs fewer replacements than with the fixed period, reaches the same
+    certified tolerance, and -- slow but faithful convergence being no stall
+    -- neither refines nor raises the product arithmetic."""
+    p = make("block_fp32", seed=21, n=6000, m=128, n_probes=8)
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, len(p.idx), idx=g.idx, jitter=JIT)
+    try:
+        infos = {}
+        for every in (50, -50):
+            X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc,
+                                   opts=pk.make_opts(tol=1e-6, prec=pk.PKM_BF16X3,
+                                                     reliable_every=every),
+                                   allow_warning=False)
+            tr = true_relres(p, host(X))
+            assert np.all(tr <= 1e-6 * 1.001), (every, tr)
+            assert info.prec_final == pk.PKM_BF16X3 and not info.refined, every
+            infos[every] = info
+    finally:
+        pk.pkm_precond_destroy(pc)
+    fixed, adaptive = infos[50], infos[-50]
+    print("replacements fixed", fixed.true_residuals, "adaptive", adaptive.true_residuals,
+          "steps", fixed.total_iters, adaptive.total_iters)
+    assert adaptive.true_residuals < fixed.true_residuals
+    assert abs(adaptive.total_iters - fixed.total_iters) <= 0.1 * fixed.total_iters + 5
+
