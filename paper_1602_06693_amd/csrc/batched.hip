@@ -119,24 +119,29 @@ __global__ __launch_bounds__(256) void k_bmvm_f32(const BDesc* __restrict__ desc
 #pragma unroll
             for (int e = 0; e < (KR > 0 ? KR : 1); ++e) racc[u][e] = 0.f;
         }
-        for (int64_t t = t_beg; t < t_end; ++t) {
+        // one j-tile's operands, two register sets in turn (as k_mvm_f32)
+        struct Tile {
             float aj[S4];
-#pragma unroll
-            for (int s = 0; s < S4; ++s) aj[s] = D.jside[(t * 64 + lane) * S4 + s];
-            const float* vt = vs + (D.tile0 + t) * 16 * KP;
             f32x4 vv[KT > 0 ? KT : 1];
-#pragma unroll
-            for (int q = 0; q < KT; ++q) vv[q] = *reinterpret_cast<const f32x4*>(vt + q * 256 + lane * 4);
             f32x4 yr[KR > 0 ? KR : 1];
+        };
+        auto load = [&](int64_t t, Tile& T) {
+#pragma unroll
+            for (int s = 0; s < S4; ++s) T.aj[s] = D.jside[(t * 64 + lane) * S4 + s];
+            const float* vt = vs + (D.tile0 + t) * 16 * KP;
+#pragma unroll
+            for (int q = 0; q < KT; ++q) T.vv[q] = *reinterpret_cast<const f32x4*>(vt + q * 256 + lane * 4);
 #pragma unroll
             for (int e = 0; e < KR; ++e)
-                yr[e] = *reinterpret_cast<const f32x4*>(vt + KT * 256 + e * 16 + g * 4);
+                T.yr[e] = *reinterpret_cast<const f32x4*>(vt + KT * 256 + e * 16 + g * 4);
+        };
+        auto step = [&](const Tile& T) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 f32x4 st = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int s = 0; s < S4; ++s)
-                    st = __builtin_amdgcn_mfma_f32_16x16x4f32(aj[s], bi[u][s], st, 0, 0, 0);
+                    st = __builtin_amdgcn_mfma_f32_16x16x4f32(T.aj[s], bi[u][s], st, 0, 0, 0);
                 float kv[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) kv[r] = __builtin_amdgcn_exp2f(st[r]);
@@ -144,10 +149,22 @@ __global__ __launch_bounds__(256) void k_bmvm_f32(const BDesc* __restrict__ desc
                 for (int q = 0; q < KT; ++q)
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        acc[u][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[r], vv[q][r], acc[u][q], 0, 0, 0);
+                        acc[u][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[r], T.vv[q][r], acc[u][q], 0, 0, 0);
 #pragma unroll
                 for (int e = 0; e < KR; ++e)
-                    racc[u][e] += kv[0] * yr[e][0] + kv[1] * yr[e][1] + kv[2] * yr[e][2] + kv[3] * yr[e][3];
+                    racc[u][e] += kv[0] * T.yr[e][0] + kv[1] * T.yr[e][1] + kv[2] * T.yr[e][2] +
+                                  kv[3] * T.yr[e][3];
+            }
+        };
+        if (t_beg < t_end) {
+            Tile A, B;
+            load(t_beg, A);
+            for (int64_t t = t_beg; t < t_end; t += 2) {
+                load(min(t + 1, t_end - 1), B);
+                step(A);
+                if (t + 1 >= t_end) break;
+                load(min(t + 2, t_end - 1), A);
+                step(B);
             }
         }
 #pragma unroll
