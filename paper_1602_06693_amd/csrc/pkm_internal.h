@@ -42,16 +42,16 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 
 // Watches the largest FP64 true relative residual of a problem's live columns
 // across residual replacements.  Refinement with a reduced-precision product
 // converges only while the product's perturbation of K stays small against
-// lambda; past that the true residual hovers around a floor.  "Stalled" means
-// three replacements in a row without dropping below 0.7 of the best value
-// seen at the current arithmetic.
-// Stall of the reduced-precision product: the largest true residual has not
-// fallen below 0.7 of its best value for three replacements in a row and,
+// lambda; past that the true residual hovers around a floor (or grows).
+// "Stalled": the largest true residual has not fallen below 0.7 of its best
+// value at the current arithmetic for three replacements in a row and,
 // unless it grew at the latest one, for at least kStallSteps PCG steps (the
 // step floor keeps a short replacement period from reading the early pace
 // of PCG as a stall; a growing residual needs no such patience).
-constexpr double kStallGap = 2.0;   // true / recursive ratio of a faithful recursion
 constexpr int64_t kStallSteps = 150;
+// True / recursive residual ratio up to which the recursion counts as
+// faithful (adaptive replacement period below).
+constexpr double kStallGap = 2.0;
 
 struct StallMonitor {
     double best = 1e300, last = 1e300;
