@@ -55,15 +55,18 @@ def _recorded_traffic(p, prec):
     return RECORDED_TRAFFIC.get((p.name, prec, p.n, p.B.shape[1]))
 
 
-def bf16_issue_model_ms(n, d, k, split3):
-    """Lower bound on the BF16 product's time from its vector-issue budget:
-    per 512 kernel entries (16 rows x 32 columns) and lane, 8 exp2, 24 other
-    VALU ops with split 3 (4 with split 1), and 2 ceil((6 d + 6) / 32) exponent
-    plus (3 or 1) ceil(k / 16) K V MFMAs at half their duration."""
+def bf16_issue_model_ms(n, d, k, prec):
+    """Lower bound on a 16-bit product's time from its vector-issue budget:
+    per 512 kernel entries (16 rows x 32 columns) and lane, 8 exp2 and the
+    split's other VALU ops (BF16 split 3: 24; FP16 split 3: 16; split 1: 4),
+    and 2 ceil((6 d + 6) / 32) exponent plus (3 or 1) ceil(k / 16) K V MFMAs
+    at half their duration."""
     s6 = -(-(6 * d + 6) // 32)
     kt = -(-k // 16)
+    split3 = prec in ("bf16x3", "f16x3")
     mfma = 2 * s6 + (3 if split3 else 1) * kt
-    cycles = 8 * ISSUE_EXP + (24 if split3 else 4) * ISSUE_VALU + mfma * ISSUE_MFMA_HALF
+    valu = {"bf16x3": 24, "f16x3": 16}.get(prec, 4)
+    cycles = 8 * ISSUE_EXP + valu * ISSUE_VALU + mfma * ISSUE_MFMA_HALF
     return (n * n / 512.0) * cycles / (SIMDS * CLOCK_HZ) * 1e3
 
 
@@ -130,7 +133,7 @@ def mvm_only(pk, ctx, prob, p, steps, prec_names, ks):
     """Kernel products alone (k-sweep per arithmetic), then a 1 GiB calibration copy."""
     import torch
     precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x1": pk.PKM_BF16X1,
-             "bf16x3": pk.PKM_BF16X3}
+             "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3}
     rng = np.random.default_rng(1)
     for name in prec_names:
         prec = precs[name]
@@ -171,7 +174,7 @@ def hyper_mode(pk, ctx, p, a):
     from pkm_inputs import mlp_params
     dev = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).to("cuda:0")
     precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x1": pk.PKM_BF16X1,
-             "bf16x3": pk.PKM_BF16X3}
+             "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3}
     opts = pk.make_opts(tol=p.tol, prec=precs[a.prec], reliable_every=a.reliable)
     theta0 = hyper.theta_of(p.sigma2, p.lengthscales)
     log = lambda msg: print(msg, file=sys.stderr, flush=True)
@@ -302,7 +305,7 @@ def laplace_mode(pk, ctx, a):
     yd = dev(y)
     R = dev(rademacher(np.random.default_rng(a.seed + 1), n, 16))
     Xs = dev(np.random.default_rng(a.seed + 2).random((128, 14)))
-    precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x3": pk.PKM_BF16X3}
+    precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3}
     # B solves to 1e-8 so that the Newton iterations reach the same mode in
     # both arms (Newton stops when Psi changes by <= 1e-10 relative)
     opts = pk.make_opts(tol=1e-8, prec=precs.get(a.prec, pk.PKM_FP64), reliable_every=a.reliable)
@@ -342,7 +345,7 @@ def main():
     ap.add_argument("--workload", default="block_fp32")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--prec", default="bf16x3", choices=("fp32", "bf16x3", "bf16x1", "fp64"),
+    ap.add_argument("--prec", default="bf16x3", choices=("fp32", "bf16x3", "bf16x1", "f16x3", "fp64"),
                     help="arithmetic of the kernel product inside the loop (the mixed path)")
     ap.add_argument("--plain", default="fp32", choices=("fp32", "fp64", "none"),
                     help="also time this product arithmetic for the mixed-vs-plain comparison")
@@ -399,7 +402,7 @@ def main():
         return
 
     precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x1": pk.PKM_BF16X1,
-             "bf16x3": pk.PKM_BF16X3}
+             "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3}
 
     def run_variant(prec, steps, warmup, label):
         opts = pk.make_opts(tol=p.tol, prec=prec, reliable_every=a.reliable)
@@ -451,12 +454,13 @@ def main():
 
     info = mixed["info"]
     value = statistics.median(mixed["times"])
-    bf16 = a.prec.startswith("bf16")
+    bf16 = a.prec in ("bf16x1", "bf16x3", "f16x3")   # 16-bit MFMA products (same dense peak)
     peak = PEAK_BF16_MFMA_TFLOPS if bf16 else (PEAK_FP64_TFLOPS if a.prec == "fp64"
                                                  else PEAK_FP32_MFMA_TFLOPS)
     kname = {"fp32": "k_mvm_f32 (FP32 MFMA distance + exp2 + FP32 MFMA K V)",
              "bf16x3": "k_mvm_bf16<NP=3> (BF16x6-split distance + exp2 + BF16x3 K V, FP32 acc)",
              "bf16x1": "k_mvm_bf16<NP=1> (BF16x6-split distance + exp2 + BF16 K V, FP32 acc)",
+             "f16x3": "k_mvm_bf16<NP=4> (BF16x6-split distance + exp2 + FP16x3 K V, FP32 acc)",
              "fp64": "k_mvm_f64x (FP64 MFMA distance + table exp2 + FP64 MFMA K V)"}[a.prec]
     out = {
         "metric": METRIC,
@@ -469,7 +473,8 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if bf16 else ("f64" if a.prec == "fp64" else "f32"),
+        "dtype": ("f16" if a.prec == "f16x3" else "bf16") if bf16 else (
+            "f64" if a.prec == "fp64" else "f32"),
         "data": "synthetic",
         "config": {"workload": _describe(p, m, a.prec, a.reliable), "n": p.n, "d": p.d,
                    "k": 1 + N, "m": m, "preconditioner": "nystrom", "product": a.prec,
@@ -487,11 +492,12 @@ def main():
                      "flop_count": "n^2 (2 d + 2 k) per product"},
     }
     if bf16:   # the product's actual bound: vector-ALU issue (exp2, splits) + MFMA issue
-        model = bf16_issue_model_ms(p.n, p.d, p.B.shape[1], a.prec == "bf16x3")
+        model = bf16_issue_model_ms(p.n, p.d, p.B.shape[1], a.prec)
         out["roofline"]["issue_bound"] = {
             "model_ms": model, "achieved_ms": mixed["mvm_ms"], "frac": model / mixed["mvm_ms"],
-            "model": "per 512 entries and lane: 8 exp2 x 8 cycles + (24|4) VALU x 4 + "
-                     "MFMAs x 8.5 (half of 17), over 1024 SIMDs at 2.4 GHz"}
+            "model": "per 512 entries and lane: 8 exp2 x 8 cycles + (24|16|4) VALU x 4 "
+                     "(BF16x3|FP16x3|x1 splits) + MFMAs x 8.5 (half of 17), over 1024 SIMDs "
+                     "at 2.4 GHz"}
     if plain is not None:
         out["plain"] = {"product": a.plain, "value": statistics.median(plain["times"]),
                         "iters": int(plain["info"].total_iters),

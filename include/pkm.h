@@ -60,6 +60,11 @@ extern "C" {
                           once, FP32 accumulation                          */
 #define PKM_BF16X3 3   /* as PKM_BF16X1 with K and V split in two BF16 parts:
                           K_h V_h + K_h V_l + K_l V_h                      */
+#define PKM_F16X3  4   /* as PKM_BF16X3 with FP16 parts on FP16 MFMA: K is
+                          taken as K / sigma2 in (0, 1]; each V column is
+                          scaled by a power of two (largest magnitude in
+                          [2^14, 2^15)) and unscaled in the epilogue;
+                          relative ~2^-22 per entry.  V must be finite.    */
 
 /* ---- preconditioner kinds ---------------------------------------------- */
 #define PKM_PC_NONE     0
@@ -106,8 +111,9 @@ typedef struct {
     double  tol;             /* relative residual |b - K_y x|_2 / |b|_2 per
                                 column; default 1e-6                         */
     int64_t max_iter;        /* default 100000 (the paper's cap, Section 4)  */
-    int32_t prec;            /* PKM_FP64, PKM_FP32, PKM_BF16X1 or PKM_BF16X3
-                                for the product inside the loop; default
+    int32_t prec;            /* PKM_FP64, PKM_FP32, PKM_BF16X1, PKM_BF16X3 or
+                                PKM_F16X3 for the product inside the loop;
+                                default
                                 PKM_FP32                                    */
     int32_t reliable_every;  /* FP64 true-residual replacement period (non-FP64
                                 products only); default 25.  Negative: the
@@ -156,7 +162,7 @@ const char* pkm_version(void);
 /* ---- kernel product (Section 2.1: the O(n^2) operation of every CG step) --
  * Y = (K + lambda I) V for V, Y device n x k FP64 (k >= 1).  prec selects
  * the arithmetic of the K V part (the lambda V term is always FP64): any
- * PKM_FP64 .. PKM_BF16X3; FP32 needs d <= 34, BF16 d <= 36.
+ * PKM_FP64 .. PKM_F16X3; FP32 needs d <= 34, the 16-bit products d <= 36.
  * Y may not alias V.                                                         */
 int pkm_kernel_mvm(pkm_ctx* ctx, const pkm_problem* prob, int32_t k,
                    int32_t prec, const double* V, double* Y);

@@ -77,9 +77,9 @@ static int guarded(pkm_ctx* ctx, F&& f) {
 static void fill_opts(const pkm_solve_opts* in, pkm_solve_opts* o);
 
 static void check_prec(int prec, int d) {
-    PKM_REQUIRE(prec >= PKM_FP64 && prec <= PKM_BF16X3, "unknown precision");
+    PKM_REQUIRE(prec >= PKM_FP64 && prec <= PKM_F16X3, "unknown precision");
     PKM_REQUIRE(prec != PKM_FP32 || d <= 34, "FP32 product supports d <= 34");
-    PKM_REQUIRE(prec < PKM_BF16X1 || d <= 36, "BF16 product supports d <= 36");
+    PKM_REQUIRE(prec < PKM_BF16X1 || d <= 36, "16-bit products support d <= 36");
 }
 
 static void require_dev(const void* p, const char* what) {
@@ -464,7 +464,7 @@ static void fill_opts(const pkm_solve_opts* in, pkm_solve_opts* o) {
     if (!in) o->prec = PKM_FP32;
     PKM_REQUIRE(std::isfinite(o->tol) && o->tol > 0.0, "tol must be > 0");
     PKM_REQUIRE(o->max_iter >= 1, "max_iter must be >= 1");
-    PKM_REQUIRE(o->prec >= PKM_FP64 && o->prec <= PKM_BF16X3, "unknown precision");
+    PKM_REQUIRE(o->prec >= PKM_FP64 && o->prec <= PKM_F16X3, "unknown precision");
     PKM_REQUIRE(o->reliable_every != 0 && o->check_every >= 1,
                 "periods must be >= 1 (a negative replacement period adapts)");
     PKM_REQUIRE(o->reliable_every >= -(1 << 24) && o->reliable_every <= (1 << 24),
@@ -690,7 +690,7 @@ int pkm_timing_enable(pkm_ctx* ctx, int32_t on) {
 
 int pkm_mvm_stats(pkm_ctx* ctx, int32_t prec, int64_t* launches, double* ms, double* pairs,
                   double* flops) {
-    if (!ctx || prec < PKM_FP64 || prec > PKM_BF16X3) return PKM_ERR_INVALID;
+    if (!ctx || prec < PKM_FP64 || prec > PKM_F16X3) return PKM_ERR_INVALID;
     const MvmStats& s = ctx->stats[prec];
     if (launches) *launches = s.launches;
     if (ms) *ms = s.ms;

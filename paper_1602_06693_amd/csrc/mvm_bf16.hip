@@ -1,4 +1,4 @@
-// Mixed-precision kernel product K V on BF16 matrix cores (FP32 accumulation).
+// Mixed-precision kernel product K V on 16-bit matrix cores (FP32 accumulation).
 //
 // Distances: the augmented contraction a_i . b_j (see prep.hip) carried out
 // with every FP32 operand split exactly into three BF16 parts,
@@ -9,12 +9,24 @@
 // contraction runs on 16x16x32 BF16 MFMA: (6 d + 6) slots per entry instead of
 // the FP32 path's d + 2 slots at one eighth of the rate.  Slots:
 //     6 per dimension r:  (2 xh_ir part) x (xh_jr part) as listed above
-//     3:                  (c_i part) x 1        c_i = log2 sigma2 - |xh_i|^2
+//     3:                  (c_i part) x 1        c_i = -|xh_i|^2
 //     3:                  1 x (c_j part)        c_j = -|xh_j|^2
+// The signal variance is not in the exponent: the tile holds K / sigma2 =
+// exp2(S) <= 1 (up to rounding), and sigma2 multiplies the FP32 result.
 //
-// K V: K = exp2(S) in FP32 registers, rounded to BF16 (K_h) -- one product
-// K_h V_h (split 1) -- or split once more, K_l = bf16(K - K_h), for three
-// products K_h V_h + K_h V_l + K_l V_h (split 3, relative error ~2^-17).
+// K V, three arithmetics:
+//   BF16X1  K_h V_h with K_h = bf16(K), V_h = bf16(V): relative 2^-9.
+//   BF16X3  K_h V_h + K_h V_l + K_l V_h, every part BF16 (K_l = bf16(K - K_h)):
+//           relative ~2^-17.
+//   F16X3   the same three products with FP16 parts.  K / sigma2 lies in
+//           (0, 1], inside FP16's range; each V column is scaled by a power
+//           of two that puts its largest magnitude in [2^14, 2^15) (exact),
+//           and the scale is undone in the epilogue.  Parts carry 11
+//           significant bits each: relative ~2^-22 per entry, with an
+//           absolute floor of 2^-25 (of sigma2, resp. of the column's scaled
+//           maximum) where a part falls below FP16's normal range.  The
+//           remainder K - K_h takes one mixed FMA per entry that reads the
+//           FP16 half straight from the packed dword (no conversion back).
 // The column count is padded to a multiple of 16; the vector ALUs, which
 // bound this kernel (exp2 and the splits), carry no column-dependent work.
 //
@@ -36,6 +48,8 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 __device__ inline void split3(float v, __bf16& h, __bf16& m, __bf16& l) {
     h = (__bf16)v;
@@ -48,7 +62,7 @@ __device__ inline void split3(float v, __bf16& h, __bf16& m, __bf16& l) {
 // One thread per point: writes its 32 S6 slots on both sides.
 __global__ void k_aug_bf16(const double* __restrict__ X, int64_t n, int64_t n_pad, int d,
                            int S6, const double* __restrict__ inv_l,
-                           const double* __restrict__ mean, double log2s2,
+                           const double* __restrict__ mean,
                            __bf16* __restrict__ jsb, __bf16* __restrict__ isb) {
     int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i >= n_pad) return;
@@ -81,10 +95,10 @@ __global__ void k_aug_bf16(const double* __restrict__ X, int64_t n, int64_t n_pa
                 jsb[addr(6 * r + q)] = jb[q];
             }
         }
-        ci = float(log2s2 - nrm);
-        cj = float(-nrm);
+        ci = float(-nrm);
+        cj = ci;
     } else {
-        ci = float(log2s2);
+        ci = 0.0f;
         cj = -1.0e30f;
     }
     __bf16 h, m, l;
@@ -102,13 +116,46 @@ __global__ void k_aug_bf16(const double* __restrict__ X, int64_t n, int64_t n_pa
     }
 }
 
+// Largest |V[:, c]| of each column as the bit pattern of a non-negative
+// double (ordered like its value), max-reduced into colmax[c] (zeroed by the
+// caller).  Thread t reads column t % k of rows t / k, t / k + L, ... with
+// L = blockDim / k rows per pass, so a pass reads consecutive addresses.
+__global__ void k_colmax(const double* __restrict__ V, int64_t ldv, int64_t n, int k,
+                         unsigned long long* __restrict__ colmax) {
+    __shared__ unsigned long long sm[128];
+    const int t = threadIdx.x;
+    if (t < k) sm[t] = 0ull;
+    __syncthreads();
+    const int L = blockDim.x / k;
+    if (t < L * k) {
+        const int col = t % k;
+        double m = 0.0;
+        for (int64_t row = int64_t(blockIdx.x) * L + t / k; row < n; row += int64_t(gridDim.x) * L)
+            m = fmax(m, fabs(V[row * ldv + col]));
+        atomicMax(&sm[col], (unsigned long long)__double_as_longlong(m));
+    }
+    __syncthreads();
+    if (t < k) atomicMax(&colmax[t], sm[t]);
+}
+
+// Power-of-two exponent that takes column c's largest magnitude into
+// [2^14, 2^15); 0 for an all-zero or non-finite column.
+__device__ inline int col_shift(const unsigned long long* colmax, int c) {
+    const double m = __longlong_as_double((long long)colmax[c]);
+    if (!(m > 0.0) || !(m <= 1.7976931348623157e308)) return 0;
+    return 14 - ilogb(m);
+}
+
 // Pack V (n x k FP64) for split NP: parts h (and l when NP == 3) in the
-// permuted 32-row chunk order, plus the FP32 remainder columns.
+// permuted 32-row chunk order, plus the FP32 remainder columns.  With colmax
+// (FP16 parts) each column is first scaled by 2^col_shift; otherwise the
+// parts are BF16.
 //   vb[((T KT + qt) NPV + part) 64 + lane][q]
 //   yr[((T KR + e) 4 + g) 8 + q]
 __global__ void k_pack_v_bf16(const double* __restrict__ V, int64_t ldv, int64_t n, int k,
-                              int nchunk, int KT, int KR, int NPV, __bf16* __restrict__ vb,
-                              float* __restrict__ yr) {
+                              int nchunk, int KT, int KR, int NPV,
+                              const unsigned long long* __restrict__ colmax,
+                              __bf16* __restrict__ vb, float* __restrict__ yr) {
     int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     const int64_t per_chunk_v = int64_t(KT) * 64 * 8;   // one part
     const int64_t per_chunk_y = int64_t(KR) * 32;
@@ -123,11 +170,19 @@ __global__ void k_pack_v_bf16(const double* __restrict__ V, int64_t ldv, int64_t
         int g = lane >> 4;
         int64_t j = 32 * T + 16 * (q >> 2) + 4 * g + (q & 3);
         int col = 16 * qt + (lane & 15);
-        float v = (j < n && col < k) ? float(V[j * ldv + col]) : 0.0f;
-        __bf16 h = (__bf16)v;
         int64_t base = ((T * KT + qt) * NPV) * 512 + lane * 8 + q;
-        vb[base] = h;
-        if (NPV == 2) vb[base + 512] = (__bf16)(v - (float)h);
+        if (colmax) {
+            const float v = (j < n && col < k) ? float(ldexp(V[j * ldv + col], col_shift(colmax, col)))
+                                               : 0.0f;
+            const _Float16 h = (_Float16)v;
+            vb[base] = __builtin_bit_cast(__bf16, h);
+            if (NPV == 2) vb[base + 512] = __builtin_bit_cast(__bf16, (_Float16)(v - (float)h));
+        } else {
+            const float v = (j < n && col < k) ? float(V[j * ldv + col]) : 0.0f;
+            const __bf16 h = (__bf16)v;
+            vb[base] = h;
+            if (NPV == 2) vb[base + 512] = (__bf16)(v - (float)h);
+        }
     } else {
         int64_t w2 = w - per_chunk_v;
         int ee = int(w2 / 32);
@@ -165,13 +220,42 @@ __device__ inline void split_k(const float (&kf)[8], bf16x8& kh, bf16x8& kl) {
     if (NP == 3) kl = __builtin_bit_cast(bf16x8, l);
 }
 
+// Two floats -> one dword of two FP16 (round to nearest even).
+__device__ inline uint32_t pack_f16x2(float a, float b) {
+    f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
+}
+
+// K (8 floats in (0, 1]) -> K_h = f16(K), K_l = f16(K - K_h).  The remainder
+// is exact in FP32; v_fma_mix_f32 forms it as fma(-K_h, 1, K) with K_h read
+// as the FP16 half (op_sel) of the packed dword.  The compiler keeps a
+// conversion back to FP32 plus a subtraction for the same expression.
+__device__ inline void split_k_f16(const float (&kf)[8], f16x8& kh, f16x8& kl) {
+    u32x4 h, l;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const uint32_t w = pack_f16x2(kf[2 * p], kf[2 * p + 1]);
+        h[p] = w;
+        float a, b;
+        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(a) : "v"(w), "v"(kf[2 * p]));
+        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+            : "=v"(b) : "v"(w), "v"(kf[2 * p + 1]));
+        l[p] = pack_f16x2(a, b);
+    }
+    kh = __builtin_bit_cast(f16x8, h);
+    kl = __builtin_bit_cast(f16x8, l);
+}
+
 // Work-group: 4 waves x U i-tiles of 16 rows; loops over 32-row j-chunks of
 // its j-split.  All k columns (padded to 16 KT) run on the matrix cores.
+// NP: 1 = BF16X1, 3 = BF16X3, 4 = F16X3 (three FP16 products; colmax holds
+// the column scales).  The epilogue multiplies by sigma2 (and 2^-col_shift).
 template <int S6, int KT, int U, int NP>
 __global__ __launch_bounds__(256) void k_mvm_bf16(
     const bf16x8* __restrict__ jsb, const bf16x8* __restrict__ isb,
     const bf16x8* __restrict__ vb, float* __restrict__ yout, int nchunk, int nrb, int jsplit,
-    int chunks_per_split, int64_t split_stride) {
+    int chunks_per_split, int64_t split_stride, const unsigned long long* __restrict__ colmax,
+    float s2) {
     constexpr int KP = 16 * KT;
     constexpr int NPV = NP == 1 ? 1 : 2;
     const int lane = threadIdx.x & 63;
@@ -227,19 +311,37 @@ __global__ __launch_bounds__(256) void k_mvm_bf16(
                 kf[r] = __builtin_amdgcn_exp2f(s0[r]);
                 kf[4 + r] = __builtin_amdgcn_exp2f(s1[r]);
             }
-            bf16x8 kh, kl;
-            split_k<NP>(kf, kh, kl);
+            if (NP == 4) {
+                f16x8 kh, kl;
+                split_k_f16(kf, kh, kl);
 #pragma unroll
-            for (int qt = 0; qt < KT; ++qt) {
-                acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vv[qt][0], acc[u][qt], 0, 0, 0);
-                if (NP == 3) {
-                    acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vv[qt][NPV - 1], acc[u][qt], 0, 0, 0);
-                    acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl, vv[qt][0], acc[u][qt], 0, 0, 0);
+                for (int qt = 0; qt < KT; ++qt) {
+                    const f16x8 vh = __builtin_bit_cast(f16x8, vv[qt][0]);
+                    const f16x8 vl = __builtin_bit_cast(f16x8, vv[qt][NPV - 1]);
+                    acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh, vh, acc[u][qt], 0, 0, 0);
+                    acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh, vl, acc[u][qt], 0, 0, 0);
+                    acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kl, vh, acc[u][qt], 0, 0, 0);
+                }
+            } else {
+                bf16x8 kh, kl;
+                split_k<NP>(kf, kh, kl);
+#pragma unroll
+                for (int qt = 0; qt < KT; ++qt) {
+                    acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vv[qt][0], acc[u][qt], 0, 0, 0);
+                    if (NP == 3) {
+                        acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vv[qt][NPV - 1], acc[u][qt], 0, 0, 0);
+                        acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl, vv[qt][0], acc[u][qt], 0, 0, 0);
+                    }
                 }
             }
         }
     }
 
+    // undo the column scale first (exact while the result stays normal),
+    // then one rounding for sigma2
+    int sh[KT];
+#pragma unroll
+    for (int qt = 0; qt < KT; ++qt) sh[qt] = NP == 4 ? -col_shift(colmax, 16 * qt + (lane & 15)) : 0;
     float* yo = yout + int64_t(split) * split_stride;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -247,8 +349,10 @@ __global__ __launch_bounds__(256) void k_mvm_bf16(
 #pragma unroll
         for (int qt = 0; qt < KT; ++qt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                yo[(row0 + 4 * g + r) * KP + 16 * qt + (lane & 15)] = acc[u][qt][r];
+            for (int r = 0; r < 4; ++r) {
+                const float a = NP == 4 ? ldexpf(acc[u][qt][r], sh[qt]) : acc[u][qt][r];
+                yo[(row0 + 4 * g + r) * KP + 16 * qt + (lane & 15)] = a * s2;
+            }
     }
 }
 
@@ -263,8 +367,7 @@ void prepare_bf16(pkm_ctx* ctx) {
     const double* inv_l = ctx->scal.as<double>();
     const double* mean = inv_l + 64;
     k_aug_bf16<<<cdiv(P.n_pad, 128), 128, 0, ctx->stream>>>(
-        P.X, P.n, P.n_pad, P.d, P.s6, inv_l, mean, std::log2(P.sigma2), P.jsb.as<__bf16>(),
-        P.isb.as<__bf16>());
+        P.X, P.n, P.n_pad, P.d, P.s6, inv_l, mean, P.jsb.as<__bf16>(), P.isb.as<__bf16>());
     PKM_CHECK_LAUNCH();
     P.validb = true;
 }
@@ -272,11 +375,11 @@ void prepare_bf16(pkm_ctx* ctx) {
 template <int S6, int NP>
 static void launch_bf16_s(int KT, dim3 grid, hipStream_t s, const bf16x8* js, const bf16x8* is,
                           const bf16x8* vb, float* y, int nchunk, int nrb, int jsplit, int cps,
-                          int64_t stride) {
+                          int64_t stride, const unsigned long long* colmax, float s2) {
 #define PKM_B_CASE(kt)                                                                         \
     if (KT == kt) {                                                                            \
         k_mvm_bf16<S6, kt, 4, NP><<<grid, 256, 0, s>>>(js, is, vb, y, nchunk, nrb, jsplit, cps, \
-                                                        stride);                               \
+                                                        stride, colmax, s2);                   \
         return;                                                                                \
     }
     PKM_B_CASE(1) PKM_B_CASE(2) PKM_B_CASE(3) PKM_B_CASE(4) PKM_B_CASE(5)
@@ -287,24 +390,26 @@ static void launch_bf16_s(int KT, dim3 grid, hipStream_t s, const bf16x8* js, co
 template <int NP>
 static void launch_bf16(int S6, int KT, dim3 grid, hipStream_t s, const bf16x8* js,
                         const bf16x8* is, const bf16x8* vb, float* y, int nchunk, int nrb,
-                        int jsplit, int cps, int64_t stride) {
+                        int jsplit, int cps, int64_t stride, const unsigned long long* colmax,
+                        float s2) {
+#define PKM_S_CASE(s6)                                                                          \
+    case s6:                                                                                    \
+        launch_bf16_s<s6, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride,     \
+                              colmax, s2);                                                      \
+        break;
     switch (S6) {
-        case 1: launch_bf16_s<1, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
-        case 2: launch_bf16_s<2, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
-        case 3: launch_bf16_s<3, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
-        case 4: launch_bf16_s<4, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
-        case 5: launch_bf16_s<5, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
-        case 6: launch_bf16_s<6, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
-        case 7: launch_bf16_s<7, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride); break;
+        PKM_S_CASE(1) PKM_S_CASE(2) PKM_S_CASE(3) PKM_S_CASE(4) PKM_S_CASE(5) PKM_S_CASE(6)
+        PKM_S_CASE(7)
         default: fail(PKM_ERR_UNSUPPORTED, "BF16 product: d must be <= 36");
     }
+#undef PKM_S_CASE
 }
 
 F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     Prepared& P = ctx->P();
     prepare_bf16(ctx);
-    PKM_REQUIRE(k >= 1 && k <= 80, "BF16 product supports 1 <= k <= 80 columns per call");
-    const int NP = prec == PKM_BF16X3 ? 3 : 1;
+    PKM_REQUIRE(k >= 1 && k <= 80, "16-bit product supports 1 <= k <= 80 columns per call");
+    const int NP = prec == PKM_F16X3 ? 4 : prec == PKM_BF16X3 ? 3 : 1;
     const int NPV = NP == 1 ? 1 : 2;
     const int KT = int(cdiv(k, 16));   // every column on the matrix cores
     const int KR = 0;
@@ -313,13 +418,23 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     hipStream_t s = ctx->stream;
     const int64_t vb_elems = int64_t(nchunk) * KT * NPV * 512;
     const int64_t yr_elems = int64_t(nchunk) * KR * 32;
-    ctx->vbf.ensure(sizeof(__bf16) * std::max<int64_t>(vb_elems, 8) +
-                    sizeof(float) * std::max<int64_t>(yr_elems, 4) + 256);
+    const size_t vb_bytes = round_up(sizeof(__bf16) * std::max<int64_t>(vb_elems, 8), 256);
+    const size_t yr_bytes = round_up(sizeof(float) * std::max<int64_t>(yr_elems, 4), 256);
+    ctx->vbf.ensure(vb_bytes + yr_bytes + 128 * sizeof(unsigned long long));
     __bf16* vb = ctx->vbf.as<__bf16>();
-    float* yrp = reinterpret_cast<float*>(
-        reinterpret_cast<char*>(vb) + round_up(sizeof(__bf16) * std::max<int64_t>(vb_elems, 8), 256));
+    float* yrp = reinterpret_cast<float*>(reinterpret_cast<char*>(vb) + vb_bytes);
+    unsigned long long* colmax = nullptr;
+    if (NP == 4) {   // column scales for the FP16 parts (128 slots; padded columns stay 0)
+        colmax = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(vb) + vb_bytes + yr_bytes);
+        PKM_HIP(hipMemsetAsync(colmax, 0, 128 * sizeof(unsigned long long), s));
+        const int rows_per_pass = 256 / k;
+        const int64_t blocks = std::min<int64_t>(512, cdiv(P.n, rows_per_pass));
+        k_colmax<<<(unsigned)blocks, 256, 0, s>>>(V, ldv, P.n, k, colmax);
+        PKM_CHECK_LAUNCH();
+    }
     const int64_t tot = int64_t(nchunk) * (int64_t(KT) * 512 + int64_t(KR) * 32);
-    k_pack_v_bf16<<<cdiv(tot, 256), 256, 0, s>>>(V, ldv, P.n, k, nchunk, KT, KR, NPV, vb, yrp);
+    k_pack_v_bf16<<<cdiv(tot, 256), 256, 0, s>>>(V, ldv, P.n, k, nchunk, KT, KR, NPV, colmax, vb,
+                                                  yrp);
     PKM_CHECK_LAUNCH();
 
     constexpr int U = 4;
@@ -338,8 +453,13 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     const bf16x8* js = P.jsb.as<bf16x8>();
     const bf16x8* is = P.isb.as<bf16x8>();
     const bf16x8* vbv = reinterpret_cast<const bf16x8*>(vb);
-    if (NP == 1) launch_bf16<1>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride);
-    else launch_bf16<3>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride);
+    const float s2 = float(P.sigma2);
+    if (NP == 1)
+        launch_bf16<1>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride, colmax, s2);
+    else if (NP == 3)
+        launch_bf16<3>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride, colmax, s2);
+    else
+        launch_bf16<4>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride, colmax, s2);
     PKM_CHECK_LAUNCH();
     if (ctx->timing) {
         PKM_HIP(hipEventRecord(ctx->ev1, s));

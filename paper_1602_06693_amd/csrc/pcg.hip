@@ -452,7 +452,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     StallMonitor mon;
     int64_t it = 0;   // PCG steps so far
     auto escalate = [&]() {
-        cur = (cur == PKM_BF16X1 || cur == PKM_BF16X3) ? PKM_FP32 : PKM_FP64;
+        cur = (cur == PKM_BF16X1 || cur == PKM_BF16X3 || cur == PKM_F16X3) ? PKM_FP32 : PKM_FP64;
         refining = false;
         k_reactivate<<<1, 256, 0, s>>>(k, st);
         PKM_CHECK_LAUNCH();

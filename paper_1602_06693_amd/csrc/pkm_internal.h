@@ -164,7 +164,7 @@ struct pkm_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     bool timing = false;
-    pkm::MvmStats stats[4];
+    pkm::MvmStats stats[5];
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t poll_ev[2] = {nullptr, nullptr};   // lag-one status polls of the solvers
     pkm::Prepared prep;                 // the context's own prepared inputs

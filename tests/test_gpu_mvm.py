@@ -91,11 +91,14 @@ def test_invalid_arguments_rejected(ctx):
     assert e.value.code == pk.PKM_ERR_INVALID
 
 
-# BF16 products.  Exponents keep FP32-class accuracy (exact 3-part splits);
+# 16-bit products.  Exponents keep FP32-class accuracy (exact 3-part splits);
 # K and V are rounded to BF16: relative 2^-9 per entry (split 1), or carried
-# as two parts with ~2^-17 relative error (split 3).  Norm-wise bounds with
-# margin for the random-sign probe columns: 1e-2 and 1e-4.
-@pytest.mark.parametrize("prec,tol", [(pk.PKM_BF16X1, 1e-2), (pk.PKM_BF16X3, 1e-4)])
+# as two parts with ~2^-17 relative error (split 3); FP16 parts of K / sigma2
+# and of the power-of-two-scaled V columns carry ~2^-22, so the FP32-class
+# exponent dominates as in the FP32 product.  Norm-wise bounds with margin for
+# the random-sign probe columns: 1e-2, 1e-4 and the FP32 bound.
+@pytest.mark.parametrize("prec,tol", [(pk.PKM_BF16X1, 1e-2), (pk.PKM_BF16X3, 1e-4),
+                                      (pk.PKM_F16X3, TOL32)])
 @pytest.mark.parametrize("n,k", [(1000, 1), (777, 17), (600, 33), (513, 64), (300, 65), (1, 1),
                                  (40, 2), (257, 7)])
 def test_bf16_product(ctx, prec, tol, n, k):
@@ -108,8 +111,9 @@ def test_bf16_product(ctx, prec, tol, n, k):
     assert np.all(err < tol), err
 
 
+@pytest.mark.parametrize("prec,tol", [(pk.PKM_BF16X3, 1e-4), (pk.PKM_F16X3, TOL32)])
 @pytest.mark.parametrize("d", [1, 4, 16, 32, 36])
-def test_bf16x3_product_dimensions(ctx, d):
+def test_16bit_product_dimensions(ctx, d, prec, tol):
     rng = np.random.default_rng(100 + d)
     n, k = 700, 9
     X = rng.random((n, d))
@@ -117,8 +121,32 @@ def test_bf16x3_product_dimensions(ctx, d):
     V = rng.standard_normal((n, k))
     prob = pk.Problem(dev(X), ls, 0.7, 1e-3)
     want = ok.kernel_mvm(X, 0.7, ls, 1e-3, V)
-    got = host(pk.pkm_kernel_mvm(ctx, prob, dev(V), pk.PKM_BF16X3))
-    assert np.all(rel_err(got, want) < 1e-4)
+    got = host(pk.pkm_kernel_mvm(ctx, prob, dev(V), prec))
+    assert np.all(rel_err(got, want) < tol)
+
+
+@pytest.mark.parametrize("sigma2", [1e-6, 1.0, 3e5])
+def test_f16x3_column_scales_and_signal_variance(ctx, sigma2):
+    """FP16 parts need K / sigma2 (in (0, 1]) and power-of-two column scales:
+    columns 1e-25 and 1e+25 in size, an all-zero column and a column with one
+    nonzero entry all keep the FP32-class bound, at tiny and large sigma2
+    (where K itself would leave FP16's range); the zero column stays zero."""
+    p = make("block_fp32", seed=18, n=900, n_probes=5)
+    g = GpuProblem(p)
+    V = p.B.copy()
+    V[:, 1] *= 1e-25
+    V[:, 2] *= 1e25
+    V[:, 3] = 0.0
+    V[:, 4] = 0.0
+    V[123, 4] = -7.5
+    lam = 1e-3 * sigma2
+    prob = pk.Problem(g.X, p.lengthscales, sigma2, lam)
+    want = ok.kernel_mvm(p.X, sigma2, p.lengthscales, lam, V)
+    got = host(pk.pkm_kernel_mvm(ctx, prob, dev(V), pk.PKM_F16X3))
+    assert np.all(got[:, 3] == 0.0)
+    keep = [0, 1, 2, 4, 5]
+    err = rel_err(got[:, keep], want[:, keep])
+    assert np.all(err < TOL32), err
 
 
 def test_bf16_exponent_matches_fp32_path(ctx):
@@ -135,13 +163,28 @@ def test_bf16_exponent_matches_fp32_path(ctx):
     assert np.max(np.abs(a - want)[big] / np.abs(want)[big]) < 2e-5
 
 
-def test_bf16_full_size_sampled_rows(ctx):
+@pytest.mark.parametrize("prec,tol", [(pk.PKM_BF16X3, 1e-4), (pk.PKM_F16X3, TOL32)])
+def test_16bit_full_size_sampled_rows(ctx, prec, tol):
     p = make("block_fp32", seed=0)
     g = GpuProblem(p)
-    got = host(pk.pkm_kernel_mvm(ctx, g.prob, g.B, pk.PKM_BF16X3))
+    got = host(pk.pkm_kernel_mvm(ctx, g.prob, g.B, prec))
     rows = np.random.default_rng(6).choice(p.n, size=64, replace=False)
     want = ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, p.B, rows=rows)
-    assert rel_err(got[rows], want, axis=None) < 1e-4
+    assert rel_err(got[rows], want, axis=None) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [(pk.PKM_FP64, TOL64), (pk.PKM_FP32, TOL32),
+                                      (pk.PKM_BF16X3, 1e-4), (pk.PKM_F16X3, TOL32)])
+def test_mixed_workload_full_size_sampled_rows(ctx, prec, tol):
+    """The 262,144-point, d = 16 workload with its 1 + 32 right-hand sides, in
+    the launch shape its solves use; 32 sampled output rows recomputed by the
+    oracle (FP64 product: about 0.15 s per launch)."""
+    p = make("mixed", seed=0)
+    g = GpuProblem(p)
+    got = host(pk.pkm_kernel_mvm(ctx, g.prob, g.B, prec))
+    rows = np.random.default_rng(7).choice(p.n, size=32, replace=False)
+    want = ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, p.B, rows=rows)
+    assert rel_err(got[rows], want, axis=None) < tol
 
 
 @pytest.mark.parametrize("prec,tol", [(pk.PKM_FP64, TOL64), (pk.PKM_FP32, TOL32)])

@@ -126,7 +126,8 @@ def test_nan_input_is_breakdown(ctx):
     assert e.value.code == pk.PKM_ERR_BREAKDOWN
 
 
-@pytest.mark.parametrize("prec,lam", [(pk.PKM_BF16X3, None), (pk.PKM_BF16X1, 0.1)])
+@pytest.mark.parametrize("prec,lam", [(pk.PKM_BF16X3, None), (pk.PKM_F16X3, None),
+                                      (pk.PKM_BF16X1, 0.1)])
 def test_bf16_products_reach_tolerance_with_reliable_updates(ctx, prec, lam):
     """Mixed precision inside the loop, FP64 x and FP64 true residuals: the
     returned solution meets 1e-6 in FP64 against the exact K.  Split-1 BF16
