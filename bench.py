@@ -48,7 +48,7 @@ ISSUE_MFMA_HALF, ISSUE_EXP, ISSUE_VALU, SIMDS, CLOCK_HZ = 8.5, 8.0, 4.0, 1024, 2
 # WRITE_SIZE runs, calibrated on a 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE
 # x 1.0): (workload, product, n, k) -> bytes.  Valid while the kernel is
 # unchanged since the counters were taken.
-RECORDED_TRAFFIC = {("block_fp32", "bf16x3", 65536, 17): (43070.6 * 2.0 + 65536.0) * 1024}
+RECORDED_TRAFFIC = {("block_fp32", "f16x3", 65536, 17): (43444.5 * 2.0 + 65536.0) * 1024}
 
 
 def _recorded_traffic(p, prec):
@@ -345,15 +345,18 @@ def main():
     ap.add_argument("--workload", default="block_fp32")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--prec", default="bf16x3", choices=("fp32", "bf16x3", "bf16x1", "f16x3", "fp64"),
+    ap.add_argument("--prec", default="f16x3", choices=("fp32", "bf16x3", "bf16x1", "f16x3", "fp64"),
                     help="arithmetic of the kernel product inside the loop (the mixed path)")
+    ap.add_argument("--alt", default="bf16x3", choices=("fp32", "bf16x3", "bf16x1", "f16x3", "fp64",
+                                                        "none"),
+                    help="also time this mixed arithmetic (reported beside the headline)")
     ap.add_argument("--plain", default="fp32", choices=("fp32", "fp64", "none"),
                     help="also time this product arithmetic for the mixed-vs-plain comparison")
     ap.add_argument("--reliable", type=int, default=-50,
                     help="FP64 replacement period; negative: adaptive from its magnitude")
     ap.add_argument("--ks", default="", help="mvm mode: comma-separated column counts")
-    ap.add_argument("--mvm-precs", default="bf16x3",
-                    help="mvm mode: comma-separated arithmetics (fp64,fp32,bf16x1,bf16x3)")
+    ap.add_argument("--mvm-precs", default="f16x3",
+                    help="mvm mode: comma-separated arithmetics (fp64,fp32,bf16x1,bf16x3,f16x3)")
     ap.add_argument("--hyper-steps", type=int, default=20)
     ap.add_argument("--n", type=int, default=None, help="override the workload's n")
     ap.add_argument("--rank", type=int, default=128)
@@ -450,6 +453,9 @@ def main():
     plain = None
     if a.plain != "none" and a.plain != a.prec:
         plain = run_variant(precs[a.plain], a.steps, a.warmup, a.plain)
+    alt = None
+    if a.alt != "none" and a.alt not in (a.prec, a.plain):
+        alt = run_variant(precs[a.alt], a.steps, a.warmup, a.alt)
     pk.pkm_destroy(ctx)
 
     info = mixed["info"]
@@ -504,6 +510,12 @@ def main():
                         "true_residual_products": int(plain["info"].true_residuals),
                         "mvm_ms": plain["mvm_ms"], "mvm_tflops": plain["tflops"]}
         out["speedup_vs_plain"] = out["plain"]["value"] / value
+    if alt is not None:
+        out["alt"] = {"product": a.alt, "value": statistics.median(alt["times"]),
+                      "iters": int(alt["info"].total_iters),
+                      "true_residual_products": int(alt["info"].true_residuals),
+                      "max_true_relres": float(alt["info"].relres_true.max()),
+                      "mvm_ms": alt["mvm_ms"], "mvm_tflops": alt["tflops"]}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, int(info.total_iters))
     print(json.dumps(out), flush=True)

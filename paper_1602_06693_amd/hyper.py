@@ -105,7 +105,7 @@ def run(ctx, X, y, Z, theta0, lam, arms, steps, eta=1.0, opts=None, replay=None,
     (or ``replay``, a recorded trajectory); every arm solves the same systems.
     Returns the theta trajectory and per-arm, per-step records."""
     import torch
-    opts = opts or pk.make_opts(tol=1e-6, prec=pk.PKM_BF16X3)
+    opts = opts or pk.make_opts(tol=1e-6, prec=pk.PKM_F16X3)
     d = X.shape[1]
     theta = np.array(theta0, dtype=np.float64)
     G = np.zeros_like(theta)
