@@ -14,7 +14,8 @@ refinement on A_hat reaches the true solution.
 
 Rounding points emulated here (what the GPU products round):
   * ``entries``: every K_ij rounded (to FP32, or to BF16, or carried as a
-    two-part BF16 split K_h + K_l), exact sums;
+    two-part BF16 split K_h + K_l, or as a two-part FP16 split of K_ij / sigma2
+    -- IEEE binary16 with its subnormals -- times sigma2), exact sums;
   * ``augmented_fp32``: the FP32 kernel's own exponent, the augmented dot
     product a_i . b_j accumulated in FP32 over FP32 operands, then exp2 in
     FP32 -- its per-row norm roundings make E proportional to K row by row,
@@ -22,7 +23,8 @@ Rounding points emulated here (what the GPU products round):
     sqrt(n).
 
 Functions:
-  round_fp32, round_bf16          elementwise rounding (RNE)
+  round_fp32, round_bf16,         elementwise rounding (RNE)
+  round_fp16
   perturbed_kernel(...)           K + E for one of the rounding models
   rho(Khat, K, lam)               ||Khat - K||_2 / lam
   refine(Khat, K, lam, b, ...)    FP64-residual refinement on A_hat, history
@@ -38,13 +40,30 @@ import numpy as np
 from .kernel import kernel_matrix
 from .mlp import round_bf16
 
-__all__ = ["round_fp32", "round_bf16", "perturbed_kernel", "rho", "refine",
+__all__ = ["round_fp32", "round_bf16", "round_fp16", "split_fp16", "perturbed_kernel",
+           "rho", "refine",
            "fp32_solution_residual", "augmented_fp32_kernel"]
 
 
 def round_fp32(a):
     """Round FP64 values to the nearest FP32 (ties to even), returned as FP64."""
     return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def round_fp16(a):
+    """Round FP64 values to the nearest IEEE binary16 (ties to even, gradual
+    underflow below 2^-14, overflow to inf above 65504), returned as FP64."""
+    with np.errstate(over="ignore"):
+        return np.asarray(a, dtype=np.float64).astype(np.float16).astype(np.float64)
+
+
+def split_fp16(a):
+    """Two-part FP16 split: h = fp16(a), l = fp16(a - h) (a - h is exact in
+    FP64).  For |a| <= 1 the carried value h + l is within
+    max(2^-23 |a|, 2^-25) of a."""
+    a = np.asarray(a, dtype=np.float64)
+    h = round_fp16(a)
+    return h, round_fp16(a - h)
 
 
 def augmented_fp32_kernel(X, sigma2, lengthscales):
@@ -71,8 +90,8 @@ def augmented_fp32_kernel(X, sigma2, lengthscales):
 
 
 def perturbed_kernel(X, sigma2, lengthscales, model):
-    """K + E under rounding ``model``: 'fp32', 'bf16', 'bf16x2' (entries),
-    or 'augmented_fp32' (the FP32 product's exponent arithmetic)."""
+    """K + E under rounding ``model``: 'fp32', 'bf16', 'bf16x2', 'f16x2'
+    (entries), or 'augmented_fp32' (the FP32 product's exponent arithmetic)."""
     if model == "augmented_fp32":
         return augmented_fp32_kernel(X, sigma2, lengthscales)
     K = kernel_matrix(X, sigma2, lengthscales)
@@ -83,6 +102,9 @@ def perturbed_kernel(X, sigma2, lengthscales, model):
     if model == "bf16x2":
         hi = round_bf16(K)
         return hi + round_bf16(K - hi)
+    if model == "f16x2":
+        hi, lo = split_fp16(K / sigma2)
+        return sigma2 * (hi + lo)
     raise ValueError(f"unknown rounding model {model!r}")
 
 

@@ -16,6 +16,52 @@ def test_round_fp32_ties_to_even():
     assert pr.round_fp32(np.array([0.5]))[0] == 0.5
 
 
+def test_fp16_split_of_one_third_by_hand():
+    """binary16 keeps 11 significant bits: 1/3 = 1.0101010101...b x 2^-2
+    rounds down to 1365/4096; the remainder 1/(3 * 4096) = (1/3) 2^-12 lies in
+    the normal range (>= 2^-14) and rounds the same way to 1365 / 2^24; the
+    pair then misses 1/3 by exactly 1 / (3 * 2^24)."""
+    h, l = pr.split_fp16(np.array([1.0 / 3.0]))
+    assert h[0] == 1365 / 4096
+    assert l[0] == 1365 / 2.0 ** 24
+    assert 1.0 / 3.0 - (h[0] + l[0]) == pytest.approx(1.0 / (3 * 2.0 ** 24), rel=1e-9)
+
+
+def test_round_fp16_format_limits():
+    assert pr.round_fp16(np.array([65504.0]))[0] == 65504.0            # largest finite
+    assert np.isinf(pr.round_fp16(np.array([65520.0]))[0])             # rounds past it
+    assert pr.round_fp16(np.array([2.0 ** -24]))[0] == 2.0 ** -24      # smallest subnormal
+    assert pr.round_fp16(np.array([2.0 ** -26]))[0] == 0.0             # below half of it
+    assert pr.round_fp16(np.array([1.0 + 2.0 ** -11]))[0] == 1.0       # tie -> even
+    assert pr.round_fp16(np.array([1.0 + 3 * 2.0 ** -11]))[0] == 1.0 + 2.0 ** -9
+
+
+def test_fp16_split_error_bound_on_kernel_entries():
+    """Entry-wise bound of the two-part FP16 split of K / sigma2 in (0, 1]:
+    max(2^-23 K, 2^-25) (relative 2^-11 per part where normal, half the
+    2^-24 subnormal spacing below).  Dropping the low part would leave
+    2^-12 relative; a BF16 split leaves ~2^-17."""
+    rng = np.random.default_rng(3)
+    X = rng.random((300, 4))
+    K = kernel_matrix(X, 1.0, np.full(4, 0.3))
+    assert K.min() < 2.0 ** -14 < K.max()          # spans the subnormal range
+    h, l = pr.split_fp16(K)
+    err = np.abs(h + l - K)
+    assert np.all(err <= np.maximum(2.0 ** -23 * K, 2.0 ** -25))
+    assert np.max(np.abs(h - K) / K) > 2.0 ** -13  # the low part is needed
+    bf = pr.perturbed_kernel(X, 1.0, np.full(4, 0.3), "bf16x2")
+    assert np.max(np.abs(bf - K)) > 8 * np.max(err)
+
+
+def test_fp16_split_scales_with_sigma2():
+    rng = np.random.default_rng(4)
+    X = rng.random((120, 3))
+    ls = np.full(3, 0.4)
+    K1 = pr.perturbed_kernel(X, 1.0, ls, "f16x2")
+    K2 = pr.perturbed_kernel(X, 3.0e5, ls, "f16x2")
+    np.testing.assert_allclose(K2, 3.0e5 * K1, rtol=1e-15, atol=0)
+
+
 def test_rho_closed_form():
     K = np.diag([1.0, 2.0, 3.0])
     eps, lam = 1e-3, 1e-2
@@ -65,7 +111,7 @@ def test_bf16_entries_make_the_operator_indefinite(c1_like):
     assert pr.refine(Kh, K, 1e-4, b, steps=4)[-1] > 1.0
 
 
-@pytest.mark.parametrize("model", ["fp32", "bf16x2", "augmented_fp32"])
+@pytest.mark.parametrize("model", ["fp32", "bf16x2", "f16x2", "augmented_fp32"])
 def test_fp32_class_products_refine_to_fp64_accuracy(c1_like, model):
     X, ls, K, b = c1_like
     Kh = pr.perturbed_kernel(X, 1.0, ls, model)
@@ -97,3 +143,16 @@ def test_augmented_fp32_error_grows_with_n_not_sqrt_n():
     assert 1.6 < rhos[1] / rhos[0] < 2.6
     assert rhos_entry[1] / rhos_entry[0] < 1.6
     assert rhos[1] > 3 * rhos_entry[1]
+
+
+def test_fp16_split_perturbs_less_than_bf16_split(c1_like):
+    """At the 1024-point size of the FP64 workload's recipe the FP16x2
+    entries' rho is an order of magnitude below the BF16x2 entries' and below
+    the FP32 exponent's: the K V part no longer dominates the product's error."""
+    X, ls, K, b = c1_like
+    r16 = pr.rho(pr.perturbed_kernel(X, 1.0, ls, "f16x2"), K, 1e-4)
+    rb = pr.rho(pr.perturbed_kernel(X, 1.0, ls, "bf16x2"), K, 1e-4)
+    ra = pr.rho(pr.perturbed_kernel(X, 1.0, ls, "augmented_fp32"), K, 1e-4)
+    print("rho f16x2 %.3e bf16x2 %.3e augmented_fp32 %.3e" % (r16, rb, ra))
+    assert r16 < rb / 10
+    assert r16 < ra
