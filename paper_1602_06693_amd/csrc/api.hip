@@ -115,6 +115,7 @@ int pkm_create(pkm_ctx** out, int device, void* stream) {
         PKM_HIP(hipEventCreate(&ctx->ev1));
         for (auto& e : ctx->poll_ev) PKM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         PKM_HIP(hipHostMalloc(&ctx->pinned, PKM_PINNED_BYTES, hipHostMallocDefault));
+        PKM_HIP(hipHostGetDevicePointer(&ctx->pinned_dev, ctx->pinned, 0));
         return PKM_OK;
     });
     if (rc != PKM_OK) {

@@ -249,14 +249,15 @@ __device__ inline void split_k_f16(const float (&kf)[8], f16x8& kh, f16x8& kl) {
 // Work-group: 4 waves x U i-tiles of 16 rows; loops over 32-row j-chunks of
 // its j-split.  All k columns (padded to 16 KT) run on the matrix cores.
 // NP: 1 = BF16X1, 3 = BF16X3, 4 = F16X3 (three FP16 products; colmax holds
-// the column scales).  The epilogue multiplies by sigma2 (and 2^-col_shift).
+// the column scales).  The epilogue multiplies by sigma2 (and 2^-col_shift)
+// and stores the k real columns of each row (row stride k; the padding
+// columns are never written).
 template <int S6, int KT, int U, int NP>
 __global__ __launch_bounds__(256) void k_mvm_bf16(
     const bf16x8* __restrict__ jsb, const bf16x8* __restrict__ isb,
     const bf16x8* __restrict__ vb, float* __restrict__ yout, int nchunk, int nrb, int jsplit,
     int chunks_per_split, int64_t split_stride, const unsigned long long* __restrict__ colmax,
-    float s2) {
-    constexpr int KP = 16 * KT;
+    float s2, int kout) {
     constexpr int NPV = NP == 1 ? 1 : 2;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -350,8 +351,9 @@ __global__ __launch_bounds__(256) void k_mvm_bf16(
         for (int qt = 0; qt < KT; ++qt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                const int col = 16 * qt + (lane & 15);
                 const float a = NP == 4 ? ldexpf(acc[u][qt][r], sh[qt]) : acc[u][qt][r];
-                yo[(row0 + 4 * g + r) * KP + 16 * qt + (lane & 15)] = a * s2;
+                if (col < kout) yo[(row0 + 4 * g + r) * kout + col] = a * s2;
             }
     }
 }
@@ -375,11 +377,11 @@ void prepare_bf16(pkm_ctx* ctx) {
 template <int S6, int NP>
 static void launch_bf16_s(int KT, dim3 grid, hipStream_t s, const bf16x8* js, const bf16x8* is,
                           const bf16x8* vb, float* y, int nchunk, int nrb, int jsplit, int cps,
-                          int64_t stride, const unsigned long long* colmax, float s2) {
+                          int64_t stride, const unsigned long long* colmax, float s2, int kout) {
 #define PKM_B_CASE(kt)                                                                         \
     if (KT == kt) {                                                                            \
         k_mvm_bf16<S6, kt, 4, NP><<<grid, 256, 0, s>>>(js, is, vb, y, nchunk, nrb, jsplit, cps, \
-                                                        stride, colmax, s2);                   \
+                                                        stride, colmax, s2, kout);             \
         return;                                                                                \
     }
     PKM_B_CASE(1) PKM_B_CASE(2) PKM_B_CASE(3) PKM_B_CASE(4) PKM_B_CASE(5)
@@ -391,11 +393,11 @@ template <int NP>
 static void launch_bf16(int S6, int KT, dim3 grid, hipStream_t s, const bf16x8* js,
                         const bf16x8* is, const bf16x8* vb, float* y, int nchunk, int nrb,
                         int jsplit, int cps, int64_t stride, const unsigned long long* colmax,
-                        float s2) {
+                        float s2, int kout) {
 #define PKM_S_CASE(s6)                                                                          \
     case s6:                                                                                    \
         launch_bf16_s<s6, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride,     \
-                              colmax, s2);                                                      \
+                              colmax, s2, kout);                                                \
         break;
     switch (S6) {
         PKM_S_CASE(1) PKM_S_CASE(2) PKM_S_CASE(3) PKM_S_CASE(4) PKM_S_CASE(5) PKM_S_CASE(6)
@@ -413,7 +415,6 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     const int NPV = NP == 1 ? 1 : 2;
     const int KT = int(cdiv(k, 16));   // every column on the matrix cores
     const int KR = 0;
-    const int KP = 16 * KT;
     const int nchunk = int(P.n_pad / 32);
     hipStream_t s = ctx->stream;
     const int64_t vb_elems = int64_t(nchunk) * KT * NPV * 512;
@@ -445,7 +446,7 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     const int group = 8 / jsplit;
     const int64_t nrb_pad = round_up(nrb, group);
     dim3 grid((unsigned)(nrb_pad * jsplit));
-    const int64_t stride = P.n_pad * KP;
+    const int64_t stride = P.n_pad * k;   // partial planes hold the k real columns
     ctx->y32.ensure(sizeof(float) * stride * jsplit);
     float* y = ctx->y32.as<float>();
 
@@ -455,11 +456,11 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     const bf16x8* vbv = reinterpret_cast<const bf16x8*>(vb);
     const float s2 = float(P.sigma2);
     if (NP == 1)
-        launch_bf16<1>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride, colmax, s2);
+        launch_bf16<1>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride, colmax, s2, k);
     else if (NP == 3)
-        launch_bf16<3>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride, colmax, s2);
+        launch_bf16<3>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride, colmax, s2, k);
     else
-        launch_bf16<4>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride, colmax, s2);
+        launch_bf16<4>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride, colmax, s2, k);
     PKM_CHECK_LAUNCH();
     if (ctx->timing) {
         PKM_HIP(hipEventRecord(ctx->ev1, s));
@@ -473,7 +474,7 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
         st.pairs += pairs;
         st.flops += pairs * (2.0 * P.d + 2.0 * k);
     }
-    return F32Out{y, jsplit, stride, KP};
+    return F32Out{y, jsplit, stride, k};
 }
 
 }  // namespace pkm

@@ -147,9 +147,10 @@ __global__ void k_update_xr(int64_t n, int k, const ColState* __restrict__ st,
     }
 }
 
-// recursive residual norms and flags
+// recursive residual norms and flags; with `mirror` (pinned host memory as
+// the device addresses it) the flags also go straight to the host
 __global__ void k_rr(const double* __restrict__ prr, int k, double tol, ColState* __restrict__ st,
-                     Flags* __restrict__ fl) {
+                     Flags* __restrict__ fl, Flags* __restrict__ mirror) {
     __shared__ int live, pending, broke;
     if (threadIdx.x == 0) live = pending = broke = 0;
     __syncthreads();
@@ -176,6 +177,13 @@ __global__ void k_rr(const double* __restrict__ prr, int k, double tol, ColState
         fl->live = live;
         fl->pending = pending;
         fl->broke = broke;
+        if (mirror) {
+            mirror->live = live;
+            mirror->pending = pending;
+            mirror->broke = broke;
+            mirror->max_tru = fl->max_tru;
+            mirror->max_gap = fl->max_gap;
+        }
     }
 }
 
@@ -383,17 +391,22 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     // the current step runs, so the stream never drains between steps.  The
     // conditions read that way only ever hold from then on (no live column,
     // no stepping column, a breakdown) until the host itself acts on them, so
-    // a stale copy costs at most one idle step.
+    // a stale copy costs at most one idle step.  In the loop k_rr writes the
+    // slot itself (host-mapped store, no copy launch).
     int lag_slot = -1;   // slot whose copy is still unread (-1: none)
+    Flags* hfl_dev = static_cast<Flags*>(ctx->pinned_dev);
     auto poll = [&]() {
         PKM_HIP(hipMemcpyAsync(hfl, fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
         PKM_HIP(hipStreamSynchronize(s));
         lag_slot = -1;   // in-flight copies completed and are superseded
         return *hfl;
     };
-    auto poll_lagged = [&](Flags& out) {
-        const int slot = lag_slot == 1 ? 2 : 1;
-        PKM_HIP(hipMemcpyAsync(hfl + slot, fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
+    auto next_slot = [&]() { return lag_slot == 1 ? 2 : 1; };
+    // `written`: the slot already holds this step's flags (k_rr's mirror)
+    auto poll_lagged = [&](Flags& out, bool written) {
+        const int slot = next_slot();
+        if (!written)
+            PKM_HIP(hipMemcpyAsync(hfl + slot, fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
         PKM_HIP(hipEventRecord(ctx->poll_ev[slot - 1], s));
         const int prev = lag_slot;
         lag_slot = slot;
@@ -431,7 +444,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     PKM_CHECK_LAUNCH();
     // x0 may already satisfy the tolerance
     dot_part(ctx, r, r, n, k, partA);
-    k_rr<<<1, 256, 0, s>>>(partA, k, o->tol, st, fl);
+    k_rr<<<1, 256, 0, s>>>(partA, k, o->tol, st, fl, nullptr);
     PKM_CHECK_LAUNCH();
     Flags f = poll();
     if (f.live > 0 && f.pending == 0) {
@@ -492,7 +505,12 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         k_update_xr<<<gb, 256, 0, s>>>(n, k, st, p, Ap, X, r);
         PKM_CHECK_LAUNCH();
         dot_part(ctx, r, r, n, k, partA);
-        k_rr<<<1, 256, 0, s>>>(partA, k, o->tol, st, fl);
+        // a lagged poll after this step takes its flags from k_rr's mirror
+        const int64_t it1 = it + 1;
+        const bool lag_poll = !(cur != PKM_FP64 && it1 - last_true >= period.cur) &&
+                              it1 % check == 0 && it1 != o->max_iter;
+        k_rr<<<1, 256, 0, s>>>(partA, k, o->tol, st, fl,
+                               lag_poll ? hfl_dev + next_slot() : nullptr);
         PKM_CHECK_LAUNCH();
         ++it;
         bool do_true = cur != PKM_FP64 && it - last_true >= period.cur;
@@ -500,7 +518,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
             Flags lagged;
             if (it == o->max_iter) {
                 f = poll();
-            } else if (poll_lagged(lagged)) {
+            } else if (poll_lagged(lagged, lag_poll)) {
                 f = lagged;
             } else {
                 f.broke = 0;   // first poll of the loop: nothing read yet

@@ -179,6 +179,7 @@ struct pkm_ctx {
     pkm::DevBuf lap[14];                // Laplace approximation vectors and blocks
     pkm::DevBuf batch[16];              // batched-solve workspace
     void* pinned = nullptr;   // pinned host staging area (PKM_PINNED_BYTES)
+    void* pinned_dev = nullptr;   // the same memory as kernels address it
 };
 
 struct pkm_precond {
@@ -223,7 +224,7 @@ void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy);
 // FP32 product pipeline: pack V (n x k FP64, row-major) into MFMA tiles,
 // run the fused kernel, return FP32 partials pointer and layout.
 struct F32Out {
-    const float* y;   // jsplit x n_pad x kp32 FP32 partial sums of K V
+    const float* y;   // jsplit x n_pad x kp FP32 partial sums of K V
     int jsplit;
     int64_t stride;   // elements between consecutive split planes
     int kp;           // row stride in floats
