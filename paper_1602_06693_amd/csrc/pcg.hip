@@ -86,6 +86,26 @@ __device__ inline double sum_parts(const double* part, int k, int c) {
     return s;
 }
 
+// Column sums of the NRED x k partials by a whole 256-thread work-group:
+// threads c, c + k, ... add every per-th partial of column c, then the per
+// slices are added in a fixed order into out[c] (deterministic).  Every
+// thread of the group must call it.
+__device__ inline void sum_parts_wg(const double* __restrict__ part, int k, double* out) {
+    __shared__ double sh[256];
+    const int per = 256 / k;
+    double acc = 0.0;
+    if (int(threadIdx.x) < per * k)
+        for (int b = threadIdx.x / k; b < NRED; b += per) acc += part[b * k + threadIdx.x % k];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (int(threadIdx.x) < k) {
+        double s = 0.0;
+        for (int q = 0; q < per; ++q) s += sh[threadIdx.x + q * k];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
 // initial state: bnorm, rz = r^T z
 __global__ void k_init_state(const double* __restrict__ pbb, const double* __restrict__ prz,
                              int k, ColState* __restrict__ st) {
@@ -113,12 +133,15 @@ __global__ void k_init_state(const double* __restrict__ pbb, const double* __res
     st[c] = s;
 }
 
-__global__ void k_alpha(const double* __restrict__ ppap, int k, ColState* __restrict__ st) {
+__global__ __launch_bounds__(256) void k_alpha(const double* __restrict__ ppap, int k,
+                                               ColState* __restrict__ st) {
+    __shared__ double sums[256];
+    sum_parts_wg(ppap, k, sums);
     int c = threadIdx.x;
     if (c >= k) return;
     ColState s = st[c];
     if (stepping(s)) {
-        double pap = sum_parts(ppap, k, c);
+        double pap = sums[c];
         if (!(pap > 0.0) || !isfinite(pap)) {
             s.active = 0;
             s.status = PKM_COL_BREAKDOWN;
@@ -149,15 +172,17 @@ __global__ void k_update_xr(int64_t n, int k, const ColState* __restrict__ st,
 
 // recursive residual norms and flags; with `mirror` (pinned host memory as
 // the device addresses it) the flags also go straight to the host
-__global__ void k_rr(const double* __restrict__ prr, int k, double tol, ColState* __restrict__ st,
-                     Flags* __restrict__ fl, Flags* __restrict__ mirror) {
+__global__ __launch_bounds__(256) void k_rr(const double* __restrict__ prr, int k, double tol,
+                                            ColState* __restrict__ st, Flags* __restrict__ fl,
+                                            Flags* __restrict__ mirror) {
     __shared__ int live, pending, broke;
+    __shared__ double sums[256];
     if (threadIdx.x == 0) live = pending = broke = 0;
-    __syncthreads();
+    sum_parts_wg(prr, k, sums);
     int c = threadIdx.x;
     if (c < k) {
         ColState s = st[c];
-        double rr = sum_parts(prr, k, c);
+        double rr = sums[c];
         s.rr = rr;
         s.rec = s.bnorm > 0.0 ? sqrt(rr) / s.bnorm : 0.0;
         if (s.active && !isfinite(rr)) {
@@ -274,12 +299,15 @@ __global__ void k_report_true(const double* __restrict__ prr, int k, ColState* _
     st[c].tru = st[c].bnorm > 0.0 ? sqrt(rr) / st[c].bnorm : 0.0;
 }
 
-__global__ void k_beta(const double* __restrict__ prz, int k, ColState* __restrict__ st) {
+__global__ __launch_bounds__(256) void k_beta(const double* __restrict__ prz, int k,
+                                              ColState* __restrict__ st) {
+    __shared__ double sums[256];
+    sum_parts_wg(prz, k, sums);
     int c = threadIdx.x;
     if (c >= k) return;
     ColState s = st[c];
     if (stepping(s)) {
-        double rz = sum_parts(prz, k, c);
+        double rz = sums[c];
         if (rz < 0.0 || !isfinite(rz)) {
             s.active = 0;
             s.status = PKM_COL_BREAKDOWN;
