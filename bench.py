@@ -60,11 +60,14 @@ def bf16_issue_model_ms(n, d, k, prec):
     per 512 kernel entries (16 rows x 32 columns) and lane, 8 exp2 and the
     split's other VALU ops (BF16 split 3: 24; FP16 split 3: 16; split 1: 4),
     and 2 ceil((6 d + 6) / 32) exponent plus (3 or 1) ceil(k / 16) K V MFMAs
-    at half their duration."""
+    (FP16 split 3: one fewer when the last 16-column tile holds at most 8
+    columns) at half their duration."""
     s6 = -(-(6 * d + 6) // 32)
     kt = -(-k // 16)
     split3 = prec in ("bf16x3", "f16x3")
     mfma = 2 * s6 + (3 if split3 else 1) * kt
+    if prec == "f16x3" and k - 16 * (kt - 1) <= 8:
+        mfma -= 1   # merged last tile: (K_h + K_l) [V_h | V_l], two MFMAs
     valu = {"bf16x3": 24, "f16x3": 16}.get(prec, 4)
     cycles = 8 * ISSUE_EXP + valu * ISSUE_VALU + mfma * ISSUE_MFMA_HALF
     return (n * n / 512.0) * cycles / (SIMDS * CLOCK_HZ) * 1e3

@@ -149,12 +149,14 @@ __device__ inline int col_shift(const unsigned long long* colmax, int c) {
 // Pack V (n x k FP64) for split NP: parts h (and l when NP == 3) in the
 // permuted 32-row chunk order, plus the FP32 remainder columns.  With colmax
 // (FP16 parts) each column is first scaled by 2^col_shift; otherwise the
-// parts are BF16.
+// parts are BF16.  merge_last (FP16, at most 8 real columns in the last
+// 16-column tile): that tile's part 0 carries the h parts of its columns in
+// tile columns 0-7 and their l parts in tile columns 8-15 (part 1 unused).
 //   vb[((T KT + qt) NPV + part) 64 + lane][q]
 //   yr[((T KR + e) 4 + g) 8 + q]
 __global__ void k_pack_v_bf16(const double* __restrict__ V, int64_t ldv, int64_t n, int k,
                               int nchunk, int KT, int KR, int NPV,
-                              const unsigned long long* __restrict__ colmax,
+                              const unsigned long long* __restrict__ colmax, int merge_last,
                               __bf16* __restrict__ vb, float* __restrict__ yr) {
     int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     const int64_t per_chunk_v = int64_t(KT) * 64 * 8;   // one part
@@ -171,7 +173,14 @@ __global__ void k_pack_v_bf16(const double* __restrict__ V, int64_t ldv, int64_t
         int64_t j = 32 * T + 16 * (q >> 2) + 4 * g + (q & 3);
         int col = 16 * qt + (lane & 15);
         int64_t base = ((T * KT + qt) * NPV) * 512 + lane * 8 + q;
-        if (colmax) {
+        if (colmax && merge_last && qt == KT - 1) {
+            const int c = 16 * qt + (lane & 7);
+            const float v = (j < n && c < k) ? float(ldexp(V[j * ldv + c], col_shift(colmax, c))) : 0.0f;
+            const _Float16 h = (_Float16)v;
+            const _Float16 l = (_Float16)(v - (float)h);
+            vb[base] = __builtin_bit_cast(__bf16, (lane & 8) ? l : h);
+            vb[base + 512] = __builtin_bit_cast(__bf16, (_Float16)0.0f);
+        } else if (colmax) {
             const float v = (j < n && col < k) ? float(ldexp(V[j * ldv + col], col_shift(colmax, col)))
                                                : 0.0f;
             const _Float16 h = (_Float16)v;
@@ -249,10 +258,13 @@ __device__ inline void split_k_f16(const float (&kf)[8], f16x8& kh, f16x8& kl) {
 // Work-group: 4 waves x U i-tiles of 16 rows; loops over 32-row j-chunks of
 // its j-split.  All k columns (padded to 16 KT) run on the matrix cores.
 // NP: 1 = BF16X1, 3 = BF16X3, 4 = F16X3 (three FP16 products; colmax holds
-// the column scales).  The epilogue multiplies by sigma2 (and 2^-col_shift)
-// and stores the k real columns of each row (row stride k; the padding
-// columns are never written).
-template <int S6, int KT, int U, int NP>
+// the column scales).  ML (F16X3 only): the last column tile is packed merged
+// (h parts in tile columns 0-7, l parts in 8-15) and takes two MFMAs,
+// (K_h + K_l) [V_h | V_l], instead of three; the epilogue adds column c + 8
+// to column c.  The epilogue multiplies by sigma2 (and 2^-col_shift) and
+// stores the k real columns of each row (row stride k; the padding columns
+// are never written).
+template <int S6, int KT, int U, int NP, bool ML>
 __global__ __launch_bounds__(256) void k_mvm_bf16(
     const bf16x8* __restrict__ jsb, const bf16x8* __restrict__ isb,
     const bf16x8* __restrict__ vb, float* __restrict__ yout, int nchunk, int nrb, int jsplit,
@@ -297,7 +309,8 @@ __global__ __launch_bounds__(256) void k_mvm_bf16(
 #pragma unroll
         for (int qt = 0; qt < KT; ++qt)
 #pragma unroll
-            for (int pp = 0; pp < NPV; ++pp) vv[qt][pp] = pv[(qt * NPV + pp) * 64];
+            for (int pp = 0; pp < NPV; ++pp)
+                if (!(ML && qt == KT - 1 && pp == 1)) vv[qt][pp] = pv[(qt * NPV + pp) * 64];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
@@ -318,9 +331,11 @@ __global__ __launch_bounds__(256) void k_mvm_bf16(
 #pragma unroll
                 for (int qt = 0; qt < KT; ++qt) {
                     const f16x8 vh = __builtin_bit_cast(f16x8, vv[qt][0]);
-                    const f16x8 vl = __builtin_bit_cast(f16x8, vv[qt][NPV - 1]);
                     acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh, vh, acc[u][qt], 0, 0, 0);
-                    acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh, vl, acc[u][qt], 0, 0, 0);
+                    if (!(ML && qt == KT - 1)) {
+                        const f16x8 vl = __builtin_bit_cast(f16x8, vv[qt][NPV - 1]);
+                        acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh, vl, acc[u][qt], 0, 0, 0);
+                    }
                     acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kl, vh, acc[u][qt], 0, 0, 0);
                 }
             } else {
@@ -342,7 +357,8 @@ __global__ __launch_bounds__(256) void k_mvm_bf16(
     // then one rounding for sigma2
     int sh[KT];
 #pragma unroll
-    for (int qt = 0; qt < KT; ++qt) sh[qt] = NP == 4 ? -col_shift(colmax, 16 * qt + (lane & 15)) : 0;
+    for (int qt = 0; qt < KT; ++qt)
+        sh[qt] = NP == 4 ? -col_shift(colmax, 16 * qt + (lane & ((ML && qt == KT - 1) ? 7 : 15))) : 0;
     float* yo = yout + int64_t(split) * split_stride;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -352,8 +368,14 @@ __global__ __launch_bounds__(256) void k_mvm_bf16(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int col = 16 * qt + (lane & 15);
-                const float a = NP == 4 ? ldexpf(acc[u][qt][r], sh[qt]) : acc[u][qt][r];
-                if (col < kout) yo[(row0 + 4 * g + r) * kout + col] = a * s2;
+                float v = acc[u][qt][r];
+                bool keep = col < kout;
+                if (ML && qt == KT - 1) {   // h half + l half (lanes l and l ^ 8)
+                    v += __shfl_xor(v, 8);
+                    keep = keep && (lane & 8) == 0;
+                }
+                const float a = NP == 4 ? ldexpf(v, sh[qt]) : v;
+                if (keep) yo[(row0 + 4 * g + r) * kout + col] = a * s2;
             }
     }
 }
@@ -374,13 +396,13 @@ void prepare_bf16(pkm_ctx* ctx) {
     P.validb = true;
 }
 
-template <int S6, int NP>
+template <int S6, int NP, bool ML>
 static void launch_bf16_s(int KT, dim3 grid, hipStream_t s, const bf16x8* js, const bf16x8* is,
                           const bf16x8* vb, float* y, int nchunk, int nrb, int jsplit, int cps,
                           int64_t stride, const unsigned long long* colmax, float s2, int kout) {
 #define PKM_B_CASE(kt)                                                                         \
     if (KT == kt) {                                                                            \
-        k_mvm_bf16<S6, kt, 4, NP><<<grid, 256, 0, s>>>(js, is, vb, y, nchunk, nrb, jsplit, cps, \
+        k_mvm_bf16<S6, kt, 4, NP, ML><<<grid, 256, 0, s>>>(js, is, vb, y, nchunk, nrb, jsplit, cps, \
                                                         stride, colmax, s2, kout);             \
         return;                                                                                \
     }
@@ -389,14 +411,14 @@ static void launch_bf16_s(int KT, dim3 grid, hipStream_t s, const bf16x8* js, co
     fail(PKM_ERR_UNSUPPORTED, "BF16 product: unsupported column count");
 }
 
-template <int NP>
+template <int NP, bool ML>
 static void launch_bf16(int S6, int KT, dim3 grid, hipStream_t s, const bf16x8* js,
                         const bf16x8* is, const bf16x8* vb, float* y, int nchunk, int nrb,
                         int jsplit, int cps, int64_t stride, const unsigned long long* colmax,
                         float s2, int kout) {
 #define PKM_S_CASE(s6)                                                                          \
     case s6:                                                                                    \
-        launch_bf16_s<s6, NP>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride,     \
+        launch_bf16_s<s6, NP, ML>(KT, grid, s, js, is, vb, y, nchunk, nrb, jsplit, cps, stride,     \
                               colmax, s2, kout);                                                \
         break;
     switch (S6) {
@@ -434,8 +456,10 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
         PKM_CHECK_LAUNCH();
     }
     const int64_t tot = int64_t(nchunk) * (int64_t(KT) * 512 + int64_t(KR) * 32);
-    k_pack_v_bf16<<<cdiv(tot, 256), 256, 0, s>>>(V, ldv, P.n, k, nchunk, KT, KR, NPV, colmax, vb,
-                                                  yrp);
+    // FP16 parts: a last tile with at most 8 real columns is packed merged
+    const bool ml = NP == 4 && k - 16 * (KT - 1) <= 8;
+    k_pack_v_bf16<<<cdiv(tot, 256), 256, 0, s>>>(V, ldv, P.n, k, nchunk, KT, KR, NPV, colmax,
+                                                  ml ? 1 : 0, vb, yrp);
     PKM_CHECK_LAUNCH();
 
     constexpr int U = 4;
@@ -456,11 +480,17 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     const bf16x8* vbv = reinterpret_cast<const bf16x8*>(vb);
     const float s2 = float(P.sigma2);
     if (NP == 1)
-        launch_bf16<1>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride, colmax, s2, k);
+        launch_bf16<1, false>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride,
+                              colmax, s2, k);
     else if (NP == 3)
-        launch_bf16<3>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride, colmax, s2, k);
+        launch_bf16<3, false>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride,
+                              colmax, s2, k);
+    else if (ml)
+        launch_bf16<4, true>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride,
+                             colmax, s2, k);
     else
-        launch_bf16<4>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride, colmax, s2, k);
+        launch_bf16<4, false>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride,
+                              colmax, s2, k);
     PKM_CHECK_LAUNCH();
     if (ctx->timing) {
         PKM_HIP(hipEventRecord(ctx->ev1, s));
