@@ -218,8 +218,8 @@ def batched_mode(pk, ctx, a):
     from pkm_inputs import batched_problems
     probs = batched_problems(seed=a.seed, count=a.count)
     dev = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).to("cuda:0")
-    prec = {"fp32": pk.PKM_FP32, "fp64": pk.PKM_FP64}[a.prec if a.prec in ("fp32", "fp64")
-                                                      else "fp32"]
+    prec = {"fp32": pk.PKM_FP32, "fp64": pk.PKM_FP64, "f16x3": pk.PKM_F16X3}[
+        a.prec if a.prec in ("fp32", "fp64", "f16x3") else "fp32"]
     gps = [pk.Problem(dev(p.X), p.lengthscales, p.sigma2, p.lam) for p in probs]
     Bs = [dev(p.B) for p in probs]
     idxs = [dev(p.idx) for p in probs]
@@ -270,7 +270,7 @@ def batched_mode(pk, ctx, a):
         return statistics.median(ts), res
 
     t_b, (infos_b, rc) = timed(batched_step, "batched")
-    st = pk.pkm_mvm_stats(ctx, pk.PKM_FP32)
+    st = pk.pkm_mvm_stats(ctx, prec)
     t_s, infos_s = timed(sequential_step, "sequential")
     ok_b = all(np.all(i.col_status == pk.PKM_COL_CONVERGED) and np.all(i.relres_true <= 1e-6)
                for i in infos_b)

@@ -271,8 +271,9 @@ int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
  * added in a fixed order) when its row blocks alone would leave the chip
  * idle.  Stalls are handled per problem as in pkm_solve (refinement mode,
  * then FP64 products for that problem only; infos[b].prec_final).
- * prec PKM_FP32 (with FP64 residual replacement) or PKM_FP64;
- * 1 <= k <= 33, every d <= 34 for PKM_FP32.                                */
+ * prec PKM_FP32 or PKM_F16X3 (with FP64 residual replacement; a problem
+ * that stalls or breaks down moves to FP64 products directly) or PKM_FP64;
+ * 1 <= k <= 33, every d <= 34 for PKM_FP32, d <= 36 for PKM_F16X3.        */
 int pkm_solve_batched(pkm_ctx* ctx, int32_t P, const pkm_problem* probs,
                       const pkm_precond* const* pcs, int32_t k, const double* const* B,
                       double* const* X, const pkm_solve_opts* opts, pkm_solve_info* infos);

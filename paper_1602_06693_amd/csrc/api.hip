@@ -501,8 +501,8 @@ int pkm_solve_batched(pkm_ctx* ctx, int32_t P, const pkm_problem* probs,
         PKM_REQUIRE(probs != nullptr && B != nullptr && X != nullptr, "NULL argument");
         pkm_solve_opts o;
         fill_opts(opts, &o);
-        PKM_REQUIRE(o.prec == PKM_FP32 || o.prec == PKM_FP64,
-                    "batched solve supports FP32 or FP64 products");
+        PKM_REQUIRE(o.prec == PKM_FP32 || o.prec == PKM_FP64 || o.prec == PKM_F16X3,
+                    "batched solve supports FP32, F16X3 or FP64 products");
         PKM_REQUIRE(k >= 1 && k <= 33, "batched solve supports 1 <= k <= 33");
         for (int b = 0; b < P; ++b) {
             validate_problem(&probs[b]);

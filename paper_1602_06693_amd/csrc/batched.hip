@@ -57,6 +57,9 @@ struct BDesc {
     int64_t rpc;           // phase-1 rows per chunk
     int nchunk;
     int mpad;
+    const void* jsb;       // FP16x3 products: BF16 operand slots (prep.hip / mvm_bf16.hip)
+    const void* isb;
+    double sigma2;
 };
 
 struct BCol {
@@ -183,6 +186,220 @@ __global__ __launch_bounds__(256) void k_bmvm_f32(const BDesc* __restrict__ desc
                 if (g == 0) yout[(row0 + (lane & 15)) * KP + 16 * KT + e] = v;
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// work-queue FP16x3 kernel product (inner loop as k_mvm_bf16 with NP = 4):
+// BF16-split exponent on BF16 MFMA, K / sigma2 and the power-of-two-scaled
+// V columns (per problem) as FP16 parts on FP16 MFMA, FP32 accumulation.
+// Items as k_bmvm_f32: (problem, row block of 64 U rows, split, splits); a
+// split covers a contiguous range of the problem's 32-row j-chunks.  ML: the
+// last column tile is packed merged ([V_h | V_l], at most 8 columns).
+// Partial planes hold the k real columns of each row (row stride k).
+// ---------------------------------------------------------------------------
+typedef __bf16 bbf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 bf16h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 bf16h2 __attribute__((ext_vector_type(2)));
+typedef float bf32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t bu32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline uint32_t bpack_f16x2(float a, float b) {
+    bf32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16h2));
+}
+
+// K -> K_h = f16(K), K_l = f16(K - K_h); the remainder by one mixed FMA
+// reading the FP16 half of the packed dword (v_fma_mix_f32)
+__device__ inline void bsplit_k_f16(const float (&kf)[8], bf16h8& kh, bf16h8& kl) {
+    bu32x4 h, l;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const uint32_t w = bpack_f16x2(kf[2 * p], kf[2 * p + 1]);
+        h[p] = w;
+        float a, b;
+        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(a) : "v"(w), "v"(kf[2 * p]));
+        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+            : "=v"(b) : "v"(w), "v"(kf[2 * p + 1]));
+        l[p] = bpack_f16x2(a, b);
+    }
+    kh = __builtin_bit_cast(bf16h8, h);
+    kl = __builtin_bit_cast(bf16h8, l);
+}
+
+// power-of-two exponent taking a column's largest magnitude into [2^14, 2^15)
+__device__ inline int bcol_shift(const unsigned long long* colmax, int c) {
+    const double m = __longlong_as_double((long long)colmax[c]);
+    if (!(m > 0.0) || !(m <= 1.7976931348623157e308)) return 0;
+    return 14 - ilogb(m);
+}
+
+template <int S6, int KT, int U, bool ML>
+__global__ __launch_bounds__(256) void k_bmvm_f16(const BDesc* __restrict__ desc,
+                                                  const int4* __restrict__ items, int nitems,
+                                                  int* __restrict__ counter,
+                                                  const int* __restrict__ live,
+                                                  const int* __restrict__ use64,
+                                                  const bbf16x8* __restrict__ vb,
+                                                  const unsigned long long* __restrict__ colmax,
+                                                  int k, float* __restrict__ ybase,
+                                                  int64_t split_stride) {
+    constexpr int NPV = 2;
+    __shared__ int sh_item;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) sh_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = sh_item;
+        if (it >= nitems) return;
+        const int4 item = items[it];   // problem, row block, split, splits
+        if (!live[item.x] || use64[item.x]) continue;
+        const BDesc D = desc[item.x];
+        const bbf16x8* __restrict__ jsb = static_cast<const bbf16x8*>(D.jsb);
+        const bbf16x8* __restrict__ isb = static_cast<const bbf16x8*>(D.isb);
+        const int64_t nch = D.ntiles / 2;   // 32-row j-chunks of this problem
+        const int64_t cps = (nch + item.w - 1) / item.w;
+        const int64_t c_beg = item.z * cps;
+        const int64_t c_end = min(nch, c_beg + cps);
+        float* __restrict__ yout = ybase + item.z * split_stride;
+        const int64_t itile0 = (int64_t(item.y) * 4 + wave) * U;   // local i-tile
+        bbf16x8 bi[U][S6];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int s = 0; s < S6; ++s) bi[u][s] = isb[((itile0 + u) * S6 + s) * 64 + lane];
+        f32x4 acc[U][KT];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < KT; ++q) acc[u][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const bbf16x8* pa = jsb + 2 * c_beg * S6 * 64 + lane;
+        const bbf16x8* pv = vb + (D.tile0 / 2 + c_beg) * KT * NPV * 64 + lane;
+        for (int64_t T = c_beg; T < c_end; ++T, pa += 2 * S6 * 64, pv += KT * NPV * 64) {
+            bbf16x8 a0[S6], a1[S6];
+#pragma unroll
+            for (int s = 0; s < S6; ++s) {
+                a0[s] = pa[s * 64];
+                a1[s] = pa[(S6 + s) * 64];
+            }
+            bbf16x8 vv[KT][NPV];
+#pragma unroll
+            for (int qt = 0; qt < KT; ++qt)
+#pragma unroll
+                for (int pp = 0; pp < NPV; ++pp)
+                    if (!(ML && qt == KT - 1 && pp == 1)) vv[qt][pp] = pv[(qt * NPV + pp) * 64];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < S6; ++s) {
+                    s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[s], bi[u][s], s0, 0, 0, 0);
+                    s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[s], bi[u][s], s1, 0, 0, 0);
+                }
+                float kf[8];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    kf[r] = __builtin_amdgcn_exp2f(s0[r]);
+                    kf[4 + r] = __builtin_amdgcn_exp2f(s1[r]);
+                }
+                bf16h8 kh, kl;
+                bsplit_k_f16(kf, kh, kl);
+#pragma unroll
+                for (int qt = 0; qt < KT; ++qt) {
+                    const bf16h8 vh = __builtin_bit_cast(bf16h8, vv[qt][0]);
+                    acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh, vh, acc[u][qt], 0, 0, 0);
+                    if (!(ML && qt == KT - 1)) {
+                        const bf16h8 vl = __builtin_bit_cast(bf16h8, vv[qt][1]);
+                        acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kh, vl, acc[u][qt], 0, 0, 0);
+                    }
+                    acc[u][qt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kl, vh, acc[u][qt], 0, 0, 0);
+                }
+            }
+        }
+        const unsigned long long* cm = colmax + int64_t(item.x) * k;
+        int sh[KT];
+#pragma unroll
+        for (int qt = 0; qt < KT; ++qt) {
+            const int c = 16 * qt + (lane & ((ML && qt == KT - 1) ? 7 : 15));
+            sh[qt] = c < k ? -bcol_shift(cm, c) : 0;
+        }
+        const float s2 = float(D.sigma2);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t row0 = D.row0 + (itile0 + u) * 16;
+#pragma unroll
+            for (int qt = 0; qt < KT; ++qt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int col = 16 * qt + (lane & 15);
+                    float v = acc[u][qt][r];
+                    bool keep = col < k;
+                    if (ML && qt == KT - 1) {   // h half + l half (lanes l and l ^ 8)
+                        v += __shfl_xor(v, 8);
+                        keep = keep && (lane & 8) == 0;
+                    }
+                    if (keep) yout[(row0 + 4 * g + r) * k + col] = ldexpf(v, sh[qt]) * s2;
+                }
+        }
+    }
+}
+
+// colmax[b k + c] = largest |V[row, c]| over problem b's rows (bit pattern of a
+// non-negative double), one work-group per 256-row block; colmax zeroed first
+__global__ __launch_bounds__(256) void k_bcolmax(const double* __restrict__ V, int k,
+                                                 const int* __restrict__ rbprob,
+                                                 unsigned long long* __restrict__ colmax) {
+    __shared__ unsigned long long sm[64];
+    const int t = threadIdx.x;
+    if (t < k) sm[t] = 0ull;
+    __syncthreads();
+    const int L = 256 / k;
+    const int64_t r0 = int64_t(blockIdx.x) * 256;
+    if (t < L * k) {
+        const int col = t % k;
+        double m = 0.0;
+        for (int rr = t / k; rr < 256; rr += L) m = fmax(m, fabs(V[(r0 + rr) * k + col]));
+        atomicMax(&sm[col], (unsigned long long)__double_as_longlong(m));
+    }
+    __syncthreads();
+    if (t < k) atomicMax(&colmax[int64_t(rbprob[blockIdx.x]) * k + t], sm[t]);
+}
+
+// packed p (n_total x k FP64) -> FP16 parts in the permuted 32-row chunk
+// order of k_bmvm_f16 (global chunk index), each problem's columns scaled by
+// its own powers of two; rows past a problem's n pack as zero
+__global__ void k_bpack_v16(const double* __restrict__ V, int64_t nchunk, int k, int KT, int ml,
+                            const int* __restrict__ rbprob, const BDesc* __restrict__ desc,
+                            const unsigned long long* __restrict__ colmax,
+                            __bf16* __restrict__ vb) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int64_t per_chunk = int64_t(KT) * 512;
+    if (e >= nchunk * per_chunk) return;
+    const int64_t T = e / per_chunk;
+    const int w = int(e - T * per_chunk);
+    const int qt = w / 512, rem = w % 512;
+    const int lane = rem >> 3, q = rem & 7;
+    const int64_t j = 32 * T + 16 * (q >> 2) + 4 * (lane >> 4) + (q & 3);
+    const int b = rbprob[j >> 8];
+    const bool valid = j - desc[b].row0 < desc[b].n;
+    const unsigned long long* cm = colmax + int64_t(b) * k;
+    const int64_t base = ((T * KT + qt) * 2) * 512 + lane * 8 + q;
+    if (ml && qt == KT - 1) {
+        const int c = 16 * qt + (lane & 7);
+        const float v = (valid && c < k) ? float(ldexp(V[j * k + c], bcol_shift(cm, c))) : 0.0f;
+        const _Float16 h = (_Float16)v;
+        const _Float16 l = (_Float16)(v - (float)h);
+        vb[base] = __builtin_bit_cast(__bf16, (lane & 8) ? l : h);
+        vb[base + 512] = __builtin_bit_cast(__bf16, (_Float16)0.0f);
+    } else {
+        const int c = 16 * qt + (lane & 15);
+        const float v = (valid && c < k) ? float(ldexp(V[j * k + c], bcol_shift(cm, c))) : 0.0f;
+        const _Float16 h = (_Float16)v;
+        vb[base] = __builtin_bit_cast(__bf16, h);
+        vb[base + 512] = __builtin_bit_cast(__bf16, (_Float16)(v - (float)h));
     }
 }
 
@@ -734,6 +951,52 @@ static void launch_bmvm(int S4, int KT, int KR, int U, int grid, hipStream_t s, 
     }
 }
 
+template <int S6, int KT, bool ML>
+static void launch_bmvm16_u(int U, int grid, hipStream_t s, const BDesc* desc, const int4* items,
+                            int nitems, int* counter, const int* live, const int* use64,
+                            const bbf16x8* vb, const unsigned long long* colmax, int k, float* y,
+                            int64_t ss) {
+    if (U == 4)
+        k_bmvm_f16<S6, KT, 4, ML><<<grid, 256, 0, s>>>(desc, items, nitems, counter, live, use64, vb,
+                                                        colmax, k, y, ss);
+    else
+        k_bmvm_f16<S6, KT, 2, ML><<<grid, 256, 0, s>>>(desc, items, nitems, counter, live, use64, vb,
+                                                        colmax, k, y, ss);
+}
+
+// KT16 = ceil(k / 16) column tiles, the last merged (ML) when it holds <= 8
+template <int S6>
+static void launch_bmvm16_s(int KT, bool ml, int U, int grid, hipStream_t s, const BDesc* desc,
+                            const int4* items, int nitems, int* counter, const int* live,
+                            const int* use64, const bbf16x8* vb,
+                            const unsigned long long* colmax, int k, float* y, int64_t ss) {
+#define PKM_BH(kt, m)                                                                              \
+    if (KT == kt && ml == m) {                                                                     \
+        launch_bmvm16_u<S6, kt, m>(U, grid, s, desc, items, nitems, counter, live, use64, vb,      \
+                                   colmax, k, y, ss);                                              \
+        return;                                                                                    \
+    }
+    PKM_BH(1, true) PKM_BH(1, false) PKM_BH(2, true) PKM_BH(2, false) PKM_BH(3, true)
+#undef PKM_BH
+    fail(PKM_ERR_UNSUPPORTED, "batched FP16x3 product: k must be <= 33");
+}
+
+static void launch_bmvm16(int S6, int KT, bool ml, int U, int grid, hipStream_t s,
+                          const BDesc* desc, const int4* items, int nitems, int* counter,
+                          const int* live, const int* use64, const bbf16x8* vb,
+                          const unsigned long long* colmax, int k, float* y, int64_t ss) {
+#define PKM_BS(s6)                                                                                 \
+    case s6:                                                                                       \
+        launch_bmvm16_s<s6>(KT, ml, U, grid, s, desc, items, nitems, counter, live, use64, vb,     \
+                            colmax, k, y, ss);                                                     \
+        break;
+    switch (S6) {
+        PKM_BS(1) PKM_BS(2) PKM_BS(3) PKM_BS(4) PKM_BS(5) PKM_BS(6) PKM_BS(7)
+        default: fail(PKM_ERR_UNSUPPORTED, "batched FP16x3 product: d must be <= 36");
+    }
+#undef PKM_BS
+}
+
 struct ClassPlan {
     int s4;
     std::vector<int> probs;
@@ -749,7 +1012,8 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     hipStream_t s = ctx->stream;
     auto t_start = std::chrono::steady_clock::now();
     const int prec = o->prec;
-    PKM_REQUIRE(prec == PKM_FP32 || prec == PKM_FP64, "batched solve supports FP32 or FP64 products");
+    PKM_REQUIRE(prec == PKM_FP32 || prec == PKM_FP64 || prec == PKM_F16X3,
+                "batched solve supports FP32, F16X3 or FP64 products");
     PKM_REQUIRE(k >= 1 && k <= 33, "batched solve supports 1 <= k <= 33");
     tune_load();
 
@@ -775,7 +1039,8 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     std::vector<int64_t> row0(P + 1, 0);
     for (int b = 0; b < P; ++b) {
         ctx->active = &preps[b];
-        prepare(ctx, &probs[b], true, prec == PKM_FP32);
+        prepare(ctx, &probs[b], true, prec != PKM_FP64);
+        if (prec == PKM_F16X3) prepare_bf16(ctx);
         ctx->active = &ctx->prep;
         row0[b + 1] = row0[b] + round_up(probs[b].n, 256);
     }
@@ -806,6 +1071,9 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         D.ntiles = preps[b].n_pad / 16;
         D.jside = preps[b].jside.as<float>();
         D.iside = preps[b].iside.as<float>();
+        D.jsb = preps[b].jsb.p;
+        D.isb = preps[b].isb.p;
+        D.sigma2 = probs[b].sigma2;
         D.lambda = probs[b].lambda;
         const pkm_precond* pc = pcs ? pcs[b] : nullptr;
         D.psi = pc ? pc->psi.as<double>() : nullptr;
@@ -828,12 +1096,17 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         }
         for (int y = 0; y < int(cdiv(D.n, 64)); ++y) it2.push_back({b, y, 0, 0});
     }
-    // product work lists per dimension class, longest items first
+    // product work lists per dimension class (FP32: augmented 4-slices,
+    // FP16x3: BF16 32-slot slices), longest items first
+    const bool f16 = prec == PKM_F16X3;
+    const int KT16 = int(cdiv(k, 16));
+    const bool ml16 = k - 16 * (KT16 - 1) <= 8;   // FP16x3: merged last column tile
     std::map<int, ClassPlan> classes;
-    if (prec == PKM_FP32)
+    if (prec != PKM_FP64)
         for (int b = 0; b < P; ++b) {
-            ClassPlan& cp = classes[preps[b].d4 / 4];
-            cp.s4 = preps[b].d4 / 4;
+            const int sl = f16 ? preps[b].s6 : preps[b].d4 / 4;
+            ClassPlan& cp = classes[sl];
+            cp.s4 = sl;
             cp.probs.push_back(b);
             cp.work += preps[b].n_pad * preps[b].n_pad / 256;
         }
@@ -854,6 +1127,14 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     constexpr int kMaxSplit = 8;
     const int64_t split_stride = ntot * KP;
     W[15].ensure(sizeof(float) * split_stride * kMaxSplit + 64);
+    if (f16) {   // FP16 parts of p (ntot / 32 chunks x KT16 x 2 x 512) and column maxima
+        W[16].ensure(sizeof(__bf16) * (ntot / 32) * KT16 * 2 * 512);
+        W[17].ensure(sizeof(unsigned long long) * P * k + 64);
+        PKM_HIP(hipMemsetAsync(W[16].p, 0, sizeof(__bf16) * (ntot / 32) * KT16 * 2 * 512, s));
+        PKM_HIP(hipMemsetAsync(W[17].p, 0, sizeof(unsigned long long) * P * k, s));
+    }
+    const bbf16x8* vb16 = f16 ? W[16].as<bbf16x8>() : nullptr;
+    unsigned long long* colmax16 = f16 ? W[17].as<unsigned long long>() : nullptr;
     BDesc* d_desc = W[0].as<BDesc>();
     int* d_rbprob = W[1].as<int>();
     int* d_rbrange = d_rbprob + nrb;
@@ -999,7 +1280,8 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         ClassPlan& cp = kv.second;
         int64_t wb = 1;
         while (wb < cp.work) wb <<= 1;
-        TuneKey key{cp.s4, KT, KR, wb};
+        // FP16x3 classes are keyed 100 + slices, (KT16, merged last tile)
+        TuneKey key = f16 ? TuneKey{100 + cp.s4, KT16, ml16 ? 1 : 0, wb} : TuneKey{cp.s4, KT, KR, wb};
         // items for U i-tiles per wave; a problem whose row blocks alone give
         // fewer than kFill work-groups is split over up to kMaxSplit column
         // ranges of at least 16 tiles each
@@ -1025,8 +1307,13 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             cp.items.ensure(sizeof(int4) * items.size());
             PKM_HIP(hipMemcpyAsync(cp.items.p, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, s));
             PKM_HIP(hipMemsetAsync(counter, 0, sizeof(int), s));
-            launch_bmvm(cp.s4, KT, KR, U, grid_q, s, d_desc, cp.items.as<int4>(), int(items.size()),
-                        counter, live, use64d, vs, y32, split_stride);
+            if (f16)
+                launch_bmvm16(cp.s4, KT16, ml16, U, grid_q, s, d_desc, cp.items.as<int4>(),
+                              int(items.size()), counter, live, use64d, vb16, colmax16, k, y32,
+                              split_stride);
+            else
+                launch_bmvm(cp.s4, KT, KR, U, grid_q, s, d_desc, cp.items.as<int4>(), int(items.size()),
+                            counter, live, use64d, vs, y32, split_stride);
             PKM_CHECK_LAUNCH();
             PKM_HIP(hipStreamSynchronize(s));   // items is pageable host memory
         };
@@ -1038,6 +1325,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             float best_ms = 1e30f;
             int best_u = 4;
             for (int U : {1, 2, 4}) {
+                if (f16 && U == 1) continue;   // FP16x3 kernels: 2 or 4 i-tiles per wave
                 auto items = build(U);
                 run(U, items);   // warm
                 PKM_HIP(hipEventRecord(ctx->ev0, s));
@@ -1067,14 +1355,28 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             product64(V, Y, stepping);
             return;
         }
-        k_bpack_v32<<<cdiv((ntot / 16) * 16 * KP, 256), 256, 0, s>>>(V, ntot, k, KT, KR, vs);
-        PKM_CHECK_LAUNCH();
+        if (f16) {
+            PKM_HIP(hipMemsetAsync(colmax16, 0, sizeof(unsigned long long) * P * k, s));
+            k_bcolmax<<<nrb, 256, 0, s>>>(V, k, d_rbprob, colmax16);
+            PKM_CHECK_LAUNCH();
+            const int64_t nch = ntot / 32;
+            k_bpack_v16<<<cdiv(nch * KT16 * 512, 256), 256, 0, s>>>(
+                V, nch, k, KT16, ml16 ? 1 : 0, d_rbprob, d_desc, colmax16, W[16].as<__bf16>());
+            PKM_CHECK_LAUNCH();
+        } else {
+            k_bpack_v32<<<cdiv((ntot / 16) * 16 * KP, 256), 256, 0, s>>>(V, ntot, k, KT, KR, vs);
+            PKM_CHECK_LAUNCH();
+        }
         if (ctx->timing) PKM_HIP(hipEventRecord(ctx->ev0, s));
         for (auto& kv : classes) {
             ClassPlan& cp = kv.second;
             PKM_HIP(hipMemsetAsync(counter, 0, sizeof(int), s));
-            launch_bmvm(cp.s4, KT, KR, cp.U, grid_q, s, d_desc, cp.items.as<int4>(), cp.nitems,
-                        counter, live, use64d, vs, y32, split_stride);
+            if (f16)
+                launch_bmvm16(cp.s4, KT16, ml16, cp.U, grid_q, s, d_desc, cp.items.as<int4>(),
+                              cp.nitems, counter, live, use64d, vb16, colmax16, k, y32, split_stride);
+            else
+                launch_bmvm(cp.s4, KT, KR, cp.U, grid_q, s, d_desc, cp.items.as<int4>(), cp.nitems,
+                            counter, live, use64d, vs, y32, split_stride);
             PKM_CHECK_LAUNCH();
         }
         if (ctx->timing) {
@@ -1082,7 +1384,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             PKM_HIP(hipEventSynchronize(ctx->ev1));
             float ms = 0.f;
             PKM_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-            MvmStats& stt = ctx->stats[PKM_FP32];
+            MvmStats& stt = ctx->stats[prec];
             stt.launches += 1;
             stt.ms += ms;
             // count the work of the problems the launch actually processed
@@ -1096,8 +1398,8 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
                 stt.flops += pr * (2.0 * probs[b].d + 2.0 * k);
             }
         }
-        k_bfinish32<<<gb, 256, 0, s>>>(y32, split_stride, KP, ntot, k, d_rbprob, d_desc, d_nsplit,
-                                       V, Y);
+        k_bfinish32<<<gb, 256, 0, s>>>(y32, split_stride, f16 ? k : KP, ntot, k, d_rbprob, d_desc,
+                                       d_nsplit, V, Y);
         PKM_CHECK_LAUNCH();
         for (int b = 0; b < P; ++b)   // escalated problems: FP64 products
             if (use64[b] && stepping[b]) {

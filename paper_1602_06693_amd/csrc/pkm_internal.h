@@ -177,7 +177,7 @@ struct pkm_ctx {
     pkm::DevBuf cross[4];               // cross-product operands and prediction scratch
     pkm::DevBuf pred[3];                // predictive variance: I, K(X, X_*), solutions
     pkm::DevBuf lap[14];                // Laplace approximation vectors and blocks
-    pkm::DevBuf batch[16];              // batched-solve workspace
+    pkm::DevBuf batch[18];              // batched-solve workspace
     void* pinned = nullptr;   // pinned host staging area (PKM_PINNED_BYTES)
     void* pinned_dev = nullptr;   // the same memory as kernels address it
 };
