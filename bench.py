@@ -348,8 +348,10 @@ def main():
     ap.add_argument("--workload", default="block_fp32")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--prec", default="f16x3", choices=("fp32", "bf16x3", "bf16x1", "f16x3", "fp64"),
-                    help="arithmetic of the kernel product inside the loop (the mixed path)")
+    ap.add_argument("--prec", default=None, choices=("fp32", "bf16x3", "bf16x1", "f16x3", "fp64"),
+                    help="arithmetic of the kernel product inside the loop (the mixed path); "
+                         "default f16x3, fp64 for --mode laplace (its 1e-8 solves sit below "
+                         "what 16-bit products refine to quickly)")
     ap.add_argument("--alt", default="bf16x3", choices=("fp32", "bf16x3", "bf16x1", "f16x3", "fp64",
                                                         "none"),
                     help="also time this mixed arithmetic (reported beside the headline)")
@@ -369,9 +371,12 @@ def main():
                     help="mvm: only --steps FP32 kernel products of the workload's size, "
                          "then one 1 GiB device copy (counter calibration for profiles)")
     a = ap.parse_args()
+    if a.prec is None:
+        a.prec = "fp64" if a.mode == "laplace" else "f16x3"
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how it would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the rows of the product would shard over GPUs with an all-gather of V).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -50,7 +50,7 @@ extern "C" {
 #define PKM_ERR_BREAKDOWN   -2   /* p^T K_y p <= 0, r^T z <= 0, or NaN/Inf  */
 #define PKM_ERR_HIP         -3   /* a HIP runtime call failed               */
 #define PKM_ERR_OOM         -4   /* device allocation failed                */
-#define PKM_ERR_UNSUPPORTED -5   /* valid request this build cannot serve   */
+#define PKM_ERR_UNSUPPORTED -5   /* valid request the library cannot serve  */
 
 /* ---- arithmetic of the kernel product ---------------------------------- */
 #define PKM_FP64   0   /* FP64 distances, exp and accumulation             */
