@@ -139,7 +139,8 @@ int pkm_destroy(pkm_ctx* ctx) {
     ctx->prep.jsb.release();
     ctx->prep.isb.release();
     for (DevBuf* b : {&ctx->vbf, &ctx->v32, &ctx->y32, &ctx->v64pad, &ctx->y64pad, &ctx->red, &ctx->red2,
-                      &ctx->scal, &ctx->state, &ctx->grad, &ctx->ws_split, &ctx->ws_tmp})
+                      &ctx->scal, &ctx->state, &ctx->grad, &ctx->ws_split, &ctx->ws_tmp,
+                      &ctx->colmax})
         b->release();
     for (auto& b : ctx->pcg) b.release();
     for (auto& b : ctx->ws_setup) b.release();

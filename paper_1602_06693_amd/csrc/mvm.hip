@@ -607,10 +607,13 @@ void cross_k64(pkm_ctx* ctx, const pkm_problem* prob, const double* Xa, int64_t 
 }
 
 // Y = sum_splits(part32) + lambda V, FP64 out.
+// (zero_after: 128 slots cleared for the next product, by the first work-group)
 __global__ void k_finish32(const float* __restrict__ part, int nsplit, int64_t sstride, int kp,
                            int64_t n, int k, const double* __restrict__ V, int64_t ldv,
-                           double lambda, double* __restrict__ Y, int64_t ldy) {
+                           double lambda, double* __restrict__ Y, int64_t ldy,
+                           unsigned long long* __restrict__ zero_after) {
     int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (zero_after && e < 128) zero_after[e] = 0ull;
     if (e >= n * k) return;
     int64_t i = e / k;
     int c = int(e - i * k);
@@ -647,8 +650,9 @@ void mvm_shift(pkm_ctx* ctx, int prec, int k, const double* V, double* Y, double
         F32Out o = prec == PKM_FP32 ? mvm_k32(ctx, kc, V + c0, k)
                                     : mvm_kbf16(ctx, prec, kc, V + c0, k);
         k_finish32<<<cdiv(n * kc, 256), 256, 0, s>>>(o.y, o.jsplit, o.stride, o.kp, n, kc, V + c0, k,
-                                                      shift, Y + c0, k);
+                                                      shift, Y + c0, k, o.zero_after);
         PKM_CHECK_LAUNCH();
+        if (o.zero_after) ctx->colmax_clean = true;
     }
 }
 

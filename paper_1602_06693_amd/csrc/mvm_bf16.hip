@@ -130,6 +130,7 @@ __global__ void k_colmax(const double* __restrict__ V, int64_t ldv, int64_t n, i
     if (t < L * k) {
         const int col = t % k;
         double m = 0.0;
+#pragma unroll 4
         for (int64_t row = int64_t(blockIdx.x) * L + t / k; row < n; row += int64_t(gridDim.x) * L)
             m = fmax(m, fabs(V[row * ldv + col]));
         atomicMax(&sm[col], (unsigned long long)__double_as_longlong(m));
@@ -443,13 +444,18 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     const int64_t yr_elems = int64_t(nchunk) * KR * 32;
     const size_t vb_bytes = round_up(sizeof(__bf16) * std::max<int64_t>(vb_elems, 8), 256);
     const size_t yr_bytes = round_up(sizeof(float) * std::max<int64_t>(yr_elems, 4), 256);
-    ctx->vbf.ensure(vb_bytes + yr_bytes + 128 * sizeof(unsigned long long));
+    ctx->vbf.ensure(vb_bytes + yr_bytes);
     __bf16* vb = ctx->vbf.as<__bf16>();
     float* yrp = reinterpret_cast<float*>(reinterpret_cast<char*>(vb) + vb_bytes);
     unsigned long long* colmax = nullptr;
     if (NP == 4) {   // column scales for the FP16 parts (128 slots; padded columns stay 0)
-        colmax = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(vb) + vb_bytes + yr_bytes);
-        PKM_HIP(hipMemsetAsync(colmax, 0, 128 * sizeof(unsigned long long), s));
+        // the slots start at zero: the previous product's k_finish32 cleared
+        // them (cleared here after a fresh allocation or an interrupted call)
+        if (ctx->colmax.bytes < 128 * sizeof(unsigned long long)) ctx->colmax_clean = false;
+        ctx->colmax.ensure(128 * sizeof(unsigned long long));
+        colmax = ctx->colmax.as<unsigned long long>();
+        if (!ctx->colmax_clean) PKM_HIP(hipMemsetAsync(colmax, 0, 128 * sizeof(unsigned long long), s));
+        ctx->colmax_clean = false;
         const int rows_per_pass = 256 / k;
         const int64_t blocks = std::min<int64_t>(512, cdiv(P.n, rows_per_pass));
         k_colmax<<<(unsigned)blocks, 256, 0, s>>>(V, ldv, P.n, k, colmax);
@@ -504,7 +510,7 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
         st.pairs += pairs;
         st.flops += pairs * (2.0 * P.d + 2.0 * k);
     }
-    return F32Out{y, jsplit, stride, k};
+    return F32Out{y, jsplit, stride, k, colmax};
 }
 
 }  // namespace pkm

@@ -180,6 +180,8 @@ struct pkm_ctx {
     pkm::DevBuf batch[18];              // batched-solve workspace
     void* pinned = nullptr;   // pinned host staging area (PKM_PINNED_BYTES)
     void* pinned_dev = nullptr;   // the same memory as kernels address it
+    pkm::DevBuf colmax;       // FP16x3 products: column maxima (128 slots)
+    bool colmax_clean = false;   // colmax holds zeros (reset by k_finish32)
 };
 
 struct pkm_precond {
@@ -228,6 +230,7 @@ struct F32Out {
     int jsplit;
     int64_t stride;   // elements between consecutive split planes
     int kp;           // row stride in floats
+    unsigned long long* zero_after = nullptr;   // 128 slots the finishing kernel clears
 };
 F32Out mvm_k32(pkm_ctx* ctx, int k, const double* V, int ldv);
 // BF16 products (prec PKM_BF16X1 / PKM_BF16X3), same partial-sum layout.
