@@ -83,3 +83,24 @@ def test_batched_max_iter_and_zero_rhs(ctx):
     assert infos[1].col_status[1] == pk.PKM_COL_CONVERGED
     assert np.all(host(Xs[1])[:, 1] == 0.0)
     assert np.all(infos[0].iters == 2)
+
+
+@pytest.mark.parametrize("n_probes", [0, 15, 16, 32])
+def test_batched_f16x3_column_counts(ctx, n_probes):
+    """FP16x3 batched products for k = 1 (one merged tile), 16 (one full
+    tile), 17 and 33 (merged last tile after full ones): every problem meets
+    the FP64 tolerance against the oracle."""
+    probs = batched_problems(seed=7, count=4, n_lo=300, n_hi=1500, n_probes=n_probes)
+    gps = [pk.Problem(dev(p.X), p.lengthscales, p.sigma2, p.lam) for p in probs]
+    pcs = [pk.pkm_precond_setup(ctx, g, pk.PKM_PC_NYSTROM, len(p.idx), idx=dev(p.idx), jitter=1e-8)
+           for p, g in zip(probs, gps)]
+    try:
+        Xs, infos, rc = pk.pkm_solve_batched(ctx, gps, [dev(p.B) for p in probs], pcs=pcs,
+                                             opts=pk.make_opts(tol=1e-6, prec=pk.PKM_F16X3))
+    finally:
+        for pc in pcs:
+            pk.pkm_precond_destroy(pc)
+    assert rc == pk.PKM_OK
+    for p, X, inf in zip(probs, Xs, infos):
+        assert np.all(inf.col_status == pk.PKM_COL_CONVERGED)
+        assert np.all(_true_relres(p, host(X)) <= 1e-6 * 1.001), p.name

@@ -69,11 +69,12 @@ def test_fp32_product_full_size_sampled_rows(ctx):
     assert rel_err(got[rows], want, axis=None) < TOL32
 
 
-def test_product_is_deterministic(ctx):
+@pytest.mark.parametrize("prec", [pk.PKM_FP32, pk.PKM_F16X3])
+def test_product_is_deterministic(ctx, prec):
     p = make("block_fp32", seed=13, n=5000, n_probes=16)
     g = GpuProblem(p)
-    a = host(pk.pkm_kernel_mvm(ctx, g.prob, g.B, pk.PKM_FP32))
-    b = host(pk.pkm_kernel_mvm(ctx, g.prob, g.B, pk.PKM_FP32))
+    a = host(pk.pkm_kernel_mvm(ctx, g.prob, g.B, prec))
+    b = host(pk.pkm_kernel_mvm(ctx, g.prob, g.B, prec))
     assert np.array_equal(a, b)
 
 
