@@ -149,6 +149,11 @@ int pkm_destroy(pkm_ctx* ctx) {
     for (auto& b : ctx->pred) b.release();
     for (auto& b : ctx->lap) b.release();
     for (auto& b : ctx->batch) b.release();
+    for (auto& q : ctx->pending) {
+        (void)hipEventDestroy(q.e0);
+        (void)hipEventDestroy(q.e1);
+    }
+    for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     for (auto& e : ctx->poll_ev)
@@ -686,13 +691,21 @@ int pkm_adagrad_step(int32_t p, double* theta, const double* g, double* G, doubl
 
 int pkm_timing_enable(pkm_ctx* ctx, int32_t on) {
     if (!ctx) return PKM_ERR_INVALID;
-    ctx->timing = on != 0;
-    return PKM_OK;
+    return guarded(ctx, [&] {
+        if (!on) timing_flush(ctx);
+        ctx->timing = on != 0;
+        return PKM_OK;
+    });
 }
 
 int pkm_mvm_stats(pkm_ctx* ctx, int32_t prec, int64_t* launches, double* ms, double* pairs,
                   double* flops) {
     if (!ctx || prec < PKM_FP64 || prec > PKM_F16X3) return PKM_ERR_INVALID;
+    const int rc = guarded(ctx, [&] {
+        timing_flush(ctx);
+        return PKM_OK;
+    });
+    if (rc != PKM_OK) return rc;
     const MvmStats& s = ctx->stats[prec];
     if (launches) *launches = s.launches;
     if (ms) *ms = s.ms;
@@ -703,8 +716,58 @@ int pkm_mvm_stats(pkm_ctx* ctx, int32_t prec, int64_t* launches, double* ms, dou
 
 int pkm_mvm_stats_reset(pkm_ctx* ctx) {
     if (!ctx) return PKM_ERR_INVALID;
+    const int rc = guarded(ctx, [&] {
+        timing_flush(ctx);
+        return PKM_OK;
+    });
     for (auto& s : ctx->stats) s = MvmStats{};
-    return PKM_OK;
+    return rc;
 }
 
 }  // extern "C"
+
+namespace pkm {
+
+hipEvent_t timing_start(pkm_ctx* ctx) {
+    hipEvent_t e;
+    if (!ctx->ev_pool.empty()) {
+        e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+    } else {
+        PKM_HIP(hipEventCreate(&e));
+    }
+    PKM_HIP(hipEventRecord(e, ctx->stream));
+    return e;
+}
+
+void timing_stop(pkm_ctx* ctx, hipEvent_t e0, int prec, double pairs, double flops) {
+    hipEvent_t e1;
+    if (!ctx->ev_pool.empty()) {
+        e1 = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+    } else {
+        PKM_HIP(hipEventCreate(&e1));
+    }
+    PKM_HIP(hipEventRecord(e1, ctx->stream));
+    ctx->pending.push_back(PendingTime{e0, e1, prec, pairs, flops});
+    if (ctx->pending.size() >= 256) timing_flush(ctx);
+}
+
+void timing_flush(pkm_ctx* ctx) {
+    if (ctx->pending.empty()) return;
+    PKM_HIP(hipEventSynchronize(ctx->pending.back().e1));
+    for (const PendingTime& q : ctx->pending) {
+        float ms = 0.f;
+        PKM_HIP(hipEventElapsedTime(&ms, q.e0, q.e1));
+        MvmStats& st = ctx->stats[q.prec];
+        st.launches += 1;
+        st.ms += ms;
+        st.pairs += q.pairs;
+        st.flops += q.flops;
+        ctx->ev_pool.push_back(q.e0);
+        ctx->ev_pool.push_back(q.e1);
+    }
+    ctx->pending.clear();
+}
+
+}  // namespace pkm

@@ -1367,7 +1367,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             k_bpack_v32<<<cdiv((ntot / 16) * 16 * KP, 256), 256, 0, s>>>(V, ntot, k, KT, KR, vs);
             PKM_CHECK_LAUNCH();
         }
-        if (ctx->timing) PKM_HIP(hipEventRecord(ctx->ev0, s));
+        const hipEvent_t t0 = ctx->timing ? timing_start(ctx) : nullptr;
         for (auto& kv : classes) {
             ClassPlan& cp = kv.second;
             PKM_HIP(hipMemsetAsync(counter, 0, sizeof(int), s));
@@ -1379,24 +1379,17 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
                             counter, live, use64d, vs, y32, split_stride);
             PKM_CHECK_LAUNCH();
         }
-        if (ctx->timing) {
-            PKM_HIP(hipEventRecord(ctx->ev1, s));
-            PKM_HIP(hipEventSynchronize(ctx->ev1));
-            float ms = 0.f;
-            PKM_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-            MvmStats& stt = ctx->stats[prec];
-            stt.launches += 1;
-            stt.ms += ms;
-            // count the work of the problems the launch actually processed
-            std::vector<int> hlive(P);
-            PKM_HIP(hipMemcpyAsync(hlive.data(), live, sizeof(int) * P, hipMemcpyDeviceToHost, s));
-            PKM_HIP(hipStreamSynchronize(s));
+        if (t0) {
+            // work of the problems the launch processed, as of the host's last
+            // status read (which lags the device by at most one step)
+            double pairs = 0.0, flops = 0.0;
             for (int b = 0; b < P; ++b) {
-                if (!hlive[b] || use64[b]) continue;
+                if (!stepping[b] || use64[b]) continue;
                 const double pr = double(probs[b].n) * double(probs[b].n);
-                stt.pairs += pr;
-                stt.flops += pr * (2.0 * probs[b].d + 2.0 * k);
+                pairs += pr;
+                flops += pr * (2.0 * probs[b].d + 2.0 * k);
             }
+            timing_stop(ctx, t0, prec, pairs, flops);
         }
         k_bfinish32<<<gb, 256, 0, s>>>(y32, split_stride, f16 ? k : KP, ntot, k, d_rbprob, d_desc,
                                        d_nsplit, V, Y);

@@ -209,8 +209,7 @@ F32Out mvm_k32(pkm_ctx* ctx, int k, const double* V, int ldv) {
     int64_t stride = P.n_pad * KP;
     ctx->y32.ensure(sizeof(float) * stride * jsplit);
 
-    hipEvent_t e0 = ctx->ev0, e1 = ctx->ev1;
-    if (ctx->timing) PKM_HIP(hipEventRecord(e0, s));
+    const hipEvent_t t0 = ctx->timing ? timing_start(ctx) : nullptr;
     const float* js = P.jside.as<float>();
     const float* is = P.iside.as<float>();
     float* y = ctx->y32.as<float>();
@@ -227,17 +226,9 @@ F32Out mvm_k32(pkm_ctx* ctx, int k, const double* V, int ldv) {
         default: fail(PKM_ERR_UNSUPPORTED, "FP32 product: d must be <= 34");
     }
     PKM_CHECK_LAUNCH();
-    if (ctx->timing) {
-        PKM_HIP(hipEventRecord(e1, s));
-        PKM_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        PKM_HIP(hipEventElapsedTime(&ms, e0, e1));
-        MvmStats& st = ctx->stats[PKM_FP32];
-        st.launches += 1;
-        st.ms += ms;
-        double pairs = double(P.n) * double(P.n);
-        st.pairs += pairs;
-        st.flops += pairs * (2.0 * P.d + 2.0 * k);
+    if (t0) {
+        const double pairs = double(P.n) * double(P.n);
+        timing_stop(ctx, t0, PKM_FP32, pairs, pairs * (2.0 * P.d + 2.0 * k));
     }
     return F32Out{y, jsplit, stride, KP};
 }
@@ -502,8 +493,7 @@ void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy) 
     double* part = ctx->y64pad.as<double>();
     dim3 grid((unsigned)(nrb), (unsigned)(jsplit));
 
-    hipEvent_t e0 = ctx->ev0, e1 = ctx->ev1;
-    if (ctx->timing) PKM_HIP(hipEventRecord(e0, s));
+    const hipEvent_t t0 = ctx->timing ? timing_start(ctx) : nullptr;
     const double* xs = P.xs64.as<double>();
     if (use_mfma) {
         // j tiles of 16 rows over the padded length; jps is a multiple of 64
@@ -547,17 +537,9 @@ void mvm_k64(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy) 
             col0 += kc;
         }
     }
-    if (ctx->timing) {
-        PKM_HIP(hipEventRecord(e1, s));
-        PKM_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        PKM_HIP(hipEventElapsedTime(&ms, e0, e1));
-        MvmStats& st = ctx->stats[PKM_FP64];
-        st.launches += 1;
-        st.ms += ms;
-        double pairs = double(n) * double(n);
-        st.pairs += pairs;
-        st.flops += pairs * (2.0 * d + 2.0 * k);
+    if (t0) {
+        const double pairs = double(n) * double(n);
+        timing_stop(ctx, t0, PKM_FP64, pairs, pairs * (2.0 * d + 2.0 * k));
     }
     int64_t tot = n * k;
     k_sum_splits64<<<cdiv(tot, 256), 256, 0, s>>>(part, jsplit, sstride, n, k, k, Y, ldy);

@@ -480,7 +480,7 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     ctx->y32.ensure(sizeof(float) * stride * jsplit);
     float* y = ctx->y32.as<float>();
 
-    if (ctx->timing) PKM_HIP(hipEventRecord(ctx->ev0, s));
+    const hipEvent_t t0 = ctx->timing ? timing_start(ctx) : nullptr;
     const bf16x8* js = P.jsb.as<bf16x8>();
     const bf16x8* is = P.isb.as<bf16x8>();
     const bf16x8* vbv = reinterpret_cast<const bf16x8*>(vb);
@@ -498,17 +498,9 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
         launch_bf16<4, false>(P.s6, KT, grid, s, js, is, vbv, y, nchunk, int(nrb), jsplit, cps, stride,
                               colmax, s2, k);
     PKM_CHECK_LAUNCH();
-    if (ctx->timing) {
-        PKM_HIP(hipEventRecord(ctx->ev1, s));
-        PKM_HIP(hipEventSynchronize(ctx->ev1));
-        float ms = 0.f;
-        PKM_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-        MvmStats& st = ctx->stats[prec];
-        st.launches += 1;
-        st.ms += ms;
+    if (t0) {
         const double pairs = double(P.n) * double(P.n);
-        st.pairs += pairs;
-        st.flops += pairs * (2.0 * P.d + 2.0 * k);
+        timing_stop(ctx, t0, prec, pairs, pairs * (2.0 * P.d + 2.0 * k));
     }
     return F32Out{y, jsplit, stride, k, colmax};
 }

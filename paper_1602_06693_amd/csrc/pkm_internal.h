@@ -134,6 +134,14 @@ struct MvmStats {
     double ms = 0.0, pairs = 0.0, flops = 0.0;
 };
 
+// A timed launch whose events are not read yet (timing never blocks the
+// host per launch: the elapsed times are collected in batches).
+struct PendingTime {
+    hipEvent_t e0, e1;
+    int prec;
+    double pairs, flops;
+};
+
 // Prepared inputs of one problem (input preparation, done once per theta).
 struct Prepared {
     int64_t n = 0, n_pad = 0;
@@ -166,6 +174,8 @@ struct pkm_ctx {
     bool timing = false;
     pkm::MvmStats stats[5];
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> ev_pool;            // reusable timing events
+    std::vector<pkm::PendingTime> pending;      // timed launches not yet read
     hipEvent_t poll_ev[2] = {nullptr, nullptr};   // lag-one status polls of the solvers
     pkm::Prepared prep;                 // the context's own prepared inputs
     pkm::Prepared* active = &prep;      // inputs the kernels use (batched solves switch it)
@@ -232,6 +242,13 @@ struct F32Out {
     int kp;           // row stride in floats
     unsigned long long* zero_after = nullptr;   // 128 slots the finishing kernel clears
 };
+// Product timing (pkm_timing_enable): timing_start records a start event on
+// the context stream and returns it; timing_stop records the end event and
+// queues the launch; timing_flush waits for the last queued event and adds
+// every queued launch to ctx->stats (also done when 256 are queued).
+hipEvent_t timing_start(pkm_ctx* ctx);
+void timing_stop(pkm_ctx* ctx, hipEvent_t e0, int prec, double pairs, double flops);
+void timing_flush(pkm_ctx* ctx);
 F32Out mvm_k32(pkm_ctx* ctx, int k, const double* V, int ldv);
 // BF16 products (prec PKM_BF16X1 / PKM_BF16X3), same partial-sum layout.
 F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv);
