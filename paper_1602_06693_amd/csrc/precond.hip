@@ -513,19 +513,20 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // are never stored -- and the next block's loads are issued before this
 // block's MFMAs, so a wave keeps a block of HBM reads in flight behind its
 // matrix-core work; the ragged last block of a chunk loads under guards.
-template <int KT>
+template <int KT, int JT>
 __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, int m,
                                                 const double* __restrict__ R, int k, int c0,
                                                 int kc, int64_t n, int64_t rows_per_chunk,
                                                 double* __restrict__ part) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane >> 4, cc = lane & 15;
-    const int j0 = (blockIdx.x * 4 + w) * 16;
+    const int j0 = (blockIdx.x * 4 + w) * 16 * JT;   // JT 16-column tiles of Psi per wave
     if (j0 >= m) return;
     const int64_t i0 = int64_t(blockIdx.y) * rows_per_chunk;
     const int64_t i1 = min(n, i0 + rows_per_chunk);
-    const int jj = j0 + cc;
-    const int jc = min(jj, m - 1);
+    int jc[JT];
+#pragma unroll
+    for (int t = 0; t < JT; ++t) jc[t] = min(j0 + 16 * t + cc, m - 1);
     int col[KT];
     bool cv[KT];
 #pragma unroll
@@ -533,32 +534,38 @@ __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, 
         cv[kt] = 16 * kt + cc < kc;
         col[kt] = c0 + min(16 * kt + cc, kc - 1);
     }
-    f64x4 acc[KT];
+    f64x4 acc[JT][KT];
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt) acc[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < JT; ++t)
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) acc[t][kt] = f64x4{0.0, 0.0, 0.0, 0.0};
     const int64_t ifull = i0 + ((i1 - i0) & ~int64_t(15));
-    double a[4], b[4][KT];
-    auto load = [&](int64_t ib, double (&la)[4], double (&lb)[4][KT]) {
+    double a[JT][4], b[4][KT];
+    auto load = [&](int64_t ib, double (&la)[JT][4], double (&lb)[4][KT]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t i = ib + 4 * g + q;
-            la[q] = psi[i * m + jc];
+#pragma unroll
+            for (int t = 0; t < JT; ++t) la[t][q] = psi[i * m + jc[t]];
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt) lb[q][kt] = R[i * k + col[kt]];
         }
     };
-    auto step = [&](const double (&la)[4], const double (&lb)[4][KT]) {
+    auto step = [&](const double (&la)[JT][4], const double (&lb)[4][KT]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt)
-                acc[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[q], lb[q][kt], acc[kt], 0, 0, 0);
+#pragma unroll
+                for (int t = 0; t < JT; ++t)
+                    acc[t][kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[t][q], lb[q][kt], acc[t][kt],
+                                                                      0, 0, 0);
     };
     // two register buffers in turn: a block's loads are issued one block
     // ahead of its MFMAs and never copied (a copy would wait for them)
     // (unconditional loads -- past the end they re-read the last block -- so
     // that every wait counts exactly the loads it needs)
-    double a2[4], b2[4][KT];
+    double a2[JT][4], b2[4][KT];
     if (i0 < ifull) {
         const int64_t last = ifull - 16;
         load(i0, a, b);
@@ -575,7 +582,8 @@ __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, 
         for (int q = 0; q < 4; ++q) {
             const int64_t i = ifull + 4 * g + q;
             const bool iv = i < i1;
-            a[q] = iv ? psi[i * m + jc] : 0.0;
+#pragma unroll
+            for (int t = 0; t < JT; ++t) a[t][q] = iv ? psi[i * m + jc[t]] : 0.0;
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt) b[q][kt] = iv ? R[i * k + col[kt]] : 0.0;
         }
@@ -583,13 +591,15 @@ __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, 
     }
     // FP64 16x16x4 results: lane l holds rows l / 16 + 4 r (here: Psi columns)
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt)
+    for (int t = 0; t < JT; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int j = j0 + g + 4 * r;
-            if (j < m && cv[kt])
-                part[(int64_t(blockIdx.y) * m + j) * k + c0 + 16 * kt + cc] = acc[kt][r];
-        }
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = j0 + 16 * t + g + 4 * r;
+                if (j < m && cv[kt])
+                    part[(int64_t(blockIdx.y) * m + j) * k + c0 + 16 * kt + cc] = acc[t][kt][r];
+            }
 }
 
 // T[j][c] = sum over chunks of part, written zero-padded as an m_pad x ldt
@@ -706,6 +716,8 @@ __global__ __launch_bounds__(256) void k_apply_z(const double* __restrict__ psi,
             }
 }
 
+constexpr int kPsitJT = 2;   // Psi column tiles per wave in phase 1
+
 template <int KC>
 static void apply_chunk(pkm_ctx* ctx, const pkm_precond* pc, int k, int c0, const double* R,
                         double* Z) {
@@ -724,7 +736,9 @@ static void apply_chunk(pkm_ctx* ctx, const pkm_precond* pc, int k, int c0, cons
     ctx->red2.ensure(sizeof(double) * (nchunk * int64_t(m) * k + int64_t(m_pad) * ldt));
     double* part = ctx->red2.as<double>();
     double* T = part + nchunk * int64_t(m) * k;
-    k_psit_r<KT><<<dim3((unsigned)mt, (unsigned)nchunk), 256, 0, s>>>(
+    // phase 1: each wave takes kPsitJT 16-column tiles of Psi, so the R rows
+    // it loads serve kPsitJT MFMA tiles
+    k_psit_r<KT, kPsitJT><<<dim3((unsigned)cdiv(m, AT * kPsitJT), (unsigned)nchunk), 256, 0, s>>>(
         pc->psi.as<double>(), m, R, k, c0, kc, n, rpc, part);
     PKM_CHECK_LAUNCH();
     k_sum_chunks<<<cdiv(int64_t(m_pad) * ldt, 64), 256, 0, s>>>(part, int(nchunk), m, k, c0, kc,
