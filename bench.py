@@ -357,6 +357,8 @@ def main():
                     help="also time this mixed arithmetic (reported beside the headline)")
     ap.add_argument("--plain", default="fp32", choices=("fp32", "fp64", "none"),
                     help="also time this product arithmetic for the mixed-vs-plain comparison")
+    ap.add_argument("--fitc", action=argparse.BooleanOptionalAction, default=True,
+                    help="step mode: also time the mixed step with FITC (same m and points)")
     ap.add_argument("--reliable", type=int, default=-50,
                     help="FP64 replacement period; negative: adaptive from its magnitude")
     ap.add_argument("--ks", default="", help="mvm mode: comma-separated column counts")
@@ -415,11 +417,12 @@ def main():
     precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x1": pk.PKM_BF16X1,
              "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3}
 
-    def run_variant(prec, steps, warmup, label):
+    def run_variant(prec, steps, warmup, label, kind=None):
         opts = pk.make_opts(tol=p.tol, prec=prec, reliable_every=a.reliable)
+        kind = pk.PKM_PC_NYSTROM if kind is None else kind
 
         def step():
-            pc = pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_NYSTROM, m, idx=idx, jitter=1e-8)
+            pc = pk.pkm_precond_setup(ctx, prob, kind, m, idx=idx, jitter=1e-8)
             try:
                 return pk.pkm_lml_grad(ctx, prob, y, Z, pc=pc, opts=opts, sol=sol)
             finally:
@@ -464,6 +467,9 @@ def main():
     alt = None
     if a.alt != "none" and a.alt not in (a.prec, a.plain):
         alt = run_variant(precs[a.alt], a.steps, a.warmup, a.alt)
+    fitc = None
+    if a.fitc:   # the same step with the FITC preconditioner (same inducing points)
+        fitc = run_variant(precs[a.prec], a.steps, a.warmup, a.prec + "+fitc", pk.PKM_PC_FITC)
     pk.pkm_destroy(ctx)
 
     info = mixed["info"]
@@ -518,6 +524,12 @@ def main():
                         "true_residual_products": int(plain["info"].true_residuals),
                         "mvm_ms": plain["mvm_ms"], "mvm_tflops": plain["tflops"]}
         out["speedup_vs_plain"] = out["plain"]["value"] / value
+    if fitc is not None:
+        out["fitc"] = {"product": a.prec, "preconditioner": "fitc",
+                       "value": statistics.median(fitc["times"]),
+                       "iters": int(fitc["info"].total_iters),
+                       "true_residual_products": int(fitc["info"].true_residuals),
+                       "max_true_relres": float(fitc["info"].relres_true.max())}
     if alt is not None:
         out["alt"] = {"product": a.alt, "value": statistics.median(alt["times"]),
                       "iters": int(alt["info"].total_iters),
