@@ -52,12 +52,19 @@ class LearnedArm(Arm):
     inducing points as a NystromArm with the same seed, forms probe pairs
     (Z, (K - Q) Z) -- the part of K that step's Nystrom approximation Q
     misses -- fine-tunes the factor network on them, and preconditions with
-    Nystrom on the sketch [E_U, U(X)] (pkm_precond_setup_hybrid)."""
+    Nystrom on the sketch [E_U, U(X)] (pkm_precond_setup_hybrid).
+
+    Fallback: the training loss is the share of the probes' residual energy
+    ||(K - Q) Z||^2 that the learned columns leave unexplained (1 for a
+    network that adds nothing).  When the fine-tuned network still leaves at
+    least ``fallback_loss`` of it, that step uses plain Nystrom on the same
+    inducing points instead (counted in ``fallbacks``)."""
 
     name = "learned"
 
     def __init__(self, ctx, params, d, rank, n, m, n_train_probes=64, first_steps=300,
-                 steps_per_theta=50, lr=2e-3, seed=0, jitter=1e-8, log=None):
+                 steps_per_theta=50, lr=2e-3, seed=0, jitter=1e-8, log=None,
+                 fallback_loss=0.95):
         self.net = pk.pkm_mlp_create(ctx, params, d, 128, rank)
         self.rank, self.nz, self.n, self.m = rank, n_train_probes, n, m
         self.first, self.later, self.lr, self.jitter = first_steps, steps_per_theta, lr, jitter
@@ -66,6 +73,8 @@ class LearnedArm(Arm):
         self.train_s = 0.0
         self.losses = []
         self.log = log
+        self.fallback_loss = fallback_loss
+        self.fallbacks = 0
 
     def setup(self, ctx, prob, step):
         import torch
@@ -86,6 +95,16 @@ class LearnedArm(Arm):
             self.losses.append(pk.pkm_mlp_train_step(ctx, self.net, prob, Z, R, self.lr))
             if self.log and (it + 1) % 50 == 0:
                 self.log(f"[learned] step {step}: Adam {it + 1}/{iters}, loss {self.losses[-1]:.4e}")
+        # the loss after the last update (train_step reports the loss before it)
+        final = pk.pkm_mlp_loss_grad(ctx, self.net, prob, Z, R, prob.d, 128, self.rank)[0]
+        if final >= self.fallback_loss:
+            self.fallbacks += 1
+            if self.log:
+                self.log(f"[learned] step {step}: loss {final:.3f}, plain Nystrom this step")
+            torch.cuda.synchronize()
+            self.train_s += time.perf_counter() - t0
+            return pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_NYSTROM, self.m, idx=idx_d,
+                                        jitter=self.jitter)
         U = pk.pkm_mlp_forward(ctx, self.net, prob, self.rank)
         torch.cuda.synchronize()
         self.train_s += time.perf_counter() - t0

@@ -58,3 +58,24 @@ def test_learned_and_nystrom_arms_share_a_replayed_trajectory(ctx):
     for name in ("nystrom", "learned"):
         assert all(r["converged"] and r["max_relres"] <= 1e-6 for r in rec[name]), rec[name]
     assert len(traj) == 3
+
+
+def test_learned_arm_falls_back_to_nystrom(ctx):
+    """A network that explains none of the residual (zero output layer, Adam
+    steps of 1e-30: loss 1) makes every step use plain Nystrom on the same inducing
+    points, so the PCG step counts equal the Nystrom arm's exactly."""
+    p = make("learned", seed=5, n=2500, n_probes=4)
+    d = p.d
+    theta0 = hyper.theta_of(1.0, p.lengthscales)
+    learned = hyper.LearnedArm(ctx, mlp_params(3, d_in=d, rank=32, out_scale=0.0), d, 32, p.n,
+                               128, n_train_probes=16, first_steps=2, steps_per_theta=2, lr=1e-30,
+                               seed=4)
+    try:
+        arms = [hyper.NystromArm(p.n, 128, seed=4), learned]
+        _, rec = hyper.run(ctx, dev(p.X), dev(p.y), dev(p.Z), theta0, p.lam, arms, 2,
+                           eta=0.1, opts=pk.make_opts(tol=1e-8, prec=pk.PKM_FP64))
+        assert learned.fallbacks == 2
+    finally:
+        learned.close()
+    assert [r["iters"] for r in rec["learned"]] == [r["iters"] for r in rec["nystrom"]]
+    assert all(r["converged"] for r in rec["learned"])
