@@ -56,15 +56,19 @@ class LearnedArm(Arm):
 
     Fallback: the training loss is the share of the probes' residual energy
     ||(K - Q) Z||^2 that the learned columns leave unexplained (1 for a
-    network that adds nothing).  When the fine-tuned network still leaves at
-    least ``fallback_loss`` of it, that step uses plain Nystrom on the same
-    inducing points instead (counted in ``fallbacks``)."""
+    network that adds nothing, above 1 for one that adds the wrong
+    directions).  When the fine-tuned network leaves at least
+    ``fallback_loss`` of it, that step uses plain Nystrom on the same
+    inducing points instead (counted in ``fallbacks``).  The threshold sits
+    just below 1: a network that explains only a few per cent of the
+    residual energy can still take the largest residual directions and cut
+    the CG steps by a fifth."""
 
     name = "learned"
 
     def __init__(self, ctx, params, d, rank, n, m, n_train_probes=64, first_steps=300,
                  steps_per_theta=50, lr=2e-3, seed=0, jitter=1e-8, log=None,
-                 fallback_loss=0.95):
+                 fallback_loss=0.999):
         self.net = pk.pkm_mlp_create(ctx, params, d, 128, rank)
         self.rank, self.nz, self.n, self.m = rank, n_train_probes, n, m
         self.first, self.later, self.lr, self.jitter = first_steps, steps_per_theta, lr, jitter
