@@ -246,7 +246,7 @@ int pkm_precond_destroy(pkm_precond* pc);
  * replacement and stop stepping once the recursive residual is 1e-3 below
  * the last true one (outer FP64 iterative refinement around short inner
  * solves).  On a second stall, divergence or breakdown the solve raises the
- * product arithmetic (BF16 -> FP32 -> FP64), resumes broken columns and
+ * product arithmetic (16-bit -> FP32 -> FP64), resumes broken columns and
  * restarts every column from its FP64 true residual (reported in
  * prec_final).  A column converges when its FP64 true
  * relative residual is <= tol.  Returns PKM_NOT_CONVERGED if a column reached max_iter and

@@ -483,7 +483,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     // Reduced-precision products carry a perturbation of K.  When the true
     // residual stalls, the columns first switch to refinement mode (restart
     // at every replacement, short inner solves); if it stalls again, or a
-    // column breaks down, the product arithmetic is raised (BF16 -> FP32 ->
+    // column breaks down, the product arithmetic is raised (16-bit -> FP32 ->
     // FP64), broken columns resume, and every column restarts from its FP64
     // true residual in plain replacement mode.
     int cur = prec;
