@@ -213,3 +213,27 @@ def test_adaptive_replacement_period(ctx):
     assert adaptive.true_residuals < fixed.true_residuals
     assert abs(adaptive.total_iters - fixed.total_iters) <= 0.1 * fixed.total_iters + 5
 
+
+
+@pytest.mark.parametrize("prec", [pk.PKM_F16X3, pk.PKM_FP32])
+def test_bench_workload_full_size_sampled_rows(ctx, prec):
+    """The 65,536-point workload exactly as the bench step solves it (Nystrom
+    m = 512, 1 + 16 right-hand sides, tol 1e-6, adaptive replacement from
+    50): every column certified by its FP64 true residual, and on 16 sampled
+    rows the oracle's residual b_i - (K_y x)_i stays within 1e-6 ||b||_2 of
+    its column (implied for every row by a 1e-6 relative residual)."""
+    p = make("block_fp32", seed=0)
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, len(p.idx), idx=g.idx, jitter=JIT)
+    try:
+        X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc,
+                               opts=pk.make_opts(tol=1e-6, prec=prec, reliable_every=-50),
+                               allow_warning=False)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    assert np.all(info.col_status == pk.PKM_COL_CONVERGED)
+    assert np.all(info.relres_true <= 1e-6)
+    assert info.prec_final == prec and not info.refined
+    rows = np.random.default_rng(12).choice(p.n, size=16, replace=False)
+    r = p.B[rows] - ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, host(X), rows=rows)
+    assert np.all(np.abs(r) <= 1.01e-6 * np.linalg.norm(p.B, axis=0))
