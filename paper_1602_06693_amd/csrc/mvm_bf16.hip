@@ -449,17 +449,26 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     float* yrp = reinterpret_cast<float*>(reinterpret_cast<char*>(vb) + vb_bytes);
     unsigned long long* colmax = nullptr;
     if (NP == 4) {   // column scales for the FP16 parts (128 slots; padded columns stay 0)
-        // the slots start at zero: the previous product's k_finish32 cleared
-        // them (cleared here after a fresh allocation or an interrupted call)
-        if (ctx->colmax.bytes < 128 * sizeof(unsigned long long)) ctx->colmax_clean = false;
-        ctx->colmax.ensure(128 * sizeof(unsigned long long));
-        colmax = ctx->colmax.as<unsigned long long>();
-        if (!ctx->colmax_clean) PKM_HIP(hipMemsetAsync(colmax, 0, 128 * sizeof(unsigned long long), s));
-        ctx->colmax_clean = false;
-        const int rows_per_pass = 256 / k;
-        const int64_t blocks = std::min<int64_t>(512, cdiv(P.n, rows_per_pass));
-        k_colmax<<<(unsigned)blocks, 256, 0, s>>>(V, ldv, P.n, k, colmax);
-        PKM_CHECK_LAUNCH();
+        // the PCG direction update may have filled the slots for this V already
+        const bool ready = ctx->colmax_src == V && ctx->colmax_k == k && ldv == k &&
+                           ctx->colmax.bytes >= 128 * sizeof(unsigned long long);
+        ctx->colmax_src = nullptr;
+        if (ready) {
+            colmax = ctx->colmax.as<unsigned long long>();
+        } else {
+            // the slots start at zero: the previous product's k_finish32 cleared
+            // them (cleared here after a fresh allocation or an interrupted call)
+            if (ctx->colmax.bytes < 128 * sizeof(unsigned long long)) ctx->colmax_clean = false;
+            ctx->colmax.ensure(128 * sizeof(unsigned long long));
+            colmax = ctx->colmax.as<unsigned long long>();
+            if (!ctx->colmax_clean)
+                PKM_HIP(hipMemsetAsync(colmax, 0, 128 * sizeof(unsigned long long), s));
+            ctx->colmax_clean = false;
+            const int rows_per_pass = 256 / k;
+            const int64_t blocks = std::min<int64_t>(512, cdiv(P.n, rows_per_pass));
+            k_colmax<<<(unsigned)blocks, 256, 0, s>>>(V, ldv, P.n, k, colmax);
+            PKM_CHECK_LAUNCH();
+        }
     }
     const int64_t tot = int64_t(nchunk) * (int64_t(KT) * 512 + int64_t(KR) * 32);
     // FP16 parts: a last tile with at most 8 real columns is packed merged

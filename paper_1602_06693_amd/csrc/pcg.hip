@@ -332,6 +332,40 @@ __global__ void k_update_p(int64_t n, int k, const ColState* __restrict__ st,
     if (stepping(st[c])) p[e] = fma(st[c].beta, p[e], z[e]);
 }
 
+// p = z + beta p (live columns) and, for FP16x3 products, the largest |p|
+// of every column (updated or not) max-reduced into colmax (zeroed slots).
+// Thread t takes column t % k of rows t / k, t / k + L, ... (L = 256 / k),
+// so a pass reads consecutive addresses.
+__global__ __launch_bounds__(256) void k_update_p_cm(int64_t n, int k,
+                                                     const ColState* __restrict__ st,
+                                                     const double* __restrict__ z,
+                                                     double* __restrict__ p,
+                                                     unsigned long long* __restrict__ colmax) {
+    __shared__ unsigned long long sm[128];
+    const int t = threadIdx.x;
+    if (t < k) sm[t] = 0ull;
+    __syncthreads();
+    const int L = 256 / k;
+    if (t < L * k) {
+        const int col = t % k;
+        const bool stp = stepping(st[col]);
+        const double beta = st[col].beta;
+        double m = 0.0;
+        for (int64_t row = int64_t(blockIdx.x) * L + t / k; row < n; row += int64_t(gridDim.x) * L) {
+            const int64_t e = row * k + col;
+            double v = p[e];
+            if (stp) {
+                v = fma(beta, v, z[e]);
+                p[e] = v;
+            }
+            m = fmax(m, fabs(v));
+        }
+        atomicMax(&sm[col], (unsigned long long)__double_as_longlong(m));
+    }
+    __syncthreads();
+    if (t < k) atomicMax(&colmax[t], sm[t]);
+}
+
 __global__ void k_mark_maxiter(int k, ColState* __restrict__ st) {
     int c = threadIdx.x;
     if (c < k && st[c].active) {
@@ -579,18 +613,35 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         dot_part(ctx, r, z, n, k, partB);
         k_beta<<<1, 256, 0, s>>>(partB, k, st);
         PKM_CHECK_LAUNCH();
-        k_update_p<<<gb, 256, 0, s>>>(n, k, st, z, p);
+        if (cur == PKM_F16X3 && !wscale && k <= 80 && ctx->colmax_clean &&
+            ctx->colmax.bytes >= 128 * sizeof(unsigned long long)) {
+            // the next product's column maxima come with the update (the
+            // slots are clean: the last product's k_finish32 cleared them)
+            const int64_t blocks = std::min<int64_t>(512, cdiv(n, 256 / k));
+            k_update_p_cm<<<(unsigned)blocks, 256, 0, s>>>(n, k, st, z, p,
+                                                           ctx->colmax.as<unsigned long long>());
+            ctx->colmax_clean = false;
+            ctx->colmax_src = p;
+            ctx->colmax_k = k;
+        } else {
+            k_update_p<<<gb, 256, 0, s>>>(n, k, st, z, p);
+        }
         PKM_CHECK_LAUNCH();
     }
     k_mark_maxiter<<<1, 256, 0, s>>>(k, st);
     PKM_CHECK_LAUNCH();
-    // final FP64 true residual of every column for the report
-    apply_A(PKM_FP64, X, tmp);
-    k_sub<<<gb, 256, 0, s>>>(tot, B, tmp, tmp);
-    PKM_CHECK_LAUNCH();
-    dot_part(ctx, tmp, tmp, n, k, partA);
-    k_report_true<<<1, 256, 0, s>>>(partA, k, st);
-    PKM_CHECK_LAUNCH();
+    ctx->colmax_src = nullptr;
+    // final FP64 true residual of every column for the report -- unless every
+    // column was accepted by an FP64 true residual of its final x already
+    // (no live and no broken column: x has not moved since acceptance)
+    if (f.live > 0 || f.broke > 0) {
+        apply_A(PKM_FP64, X, tmp);
+        k_sub<<<gb, 256, 0, s>>>(tot, B, tmp, tmp);
+        PKM_CHECK_LAUNCH();
+        dot_part(ctx, tmp, tmp, n, k, partA);
+        k_report_true<<<1, 256, 0, s>>>(partA, k, st);
+        PKM_CHECK_LAUNCH();
+    }
     std::vector<ColState> hs(k);
     PKM_HIP(hipMemcpyAsync(hs.data(), st, sizeof(ColState) * k, hipMemcpyDeviceToHost, s));
     PKM_HIP(hipStreamSynchronize(s));

@@ -192,6 +192,8 @@ struct pkm_ctx {
     void* pinned_dev = nullptr;   // the same memory as kernels address it
     pkm::DevBuf colmax;       // FP16x3 products: column maxima (128 slots)
     bool colmax_clean = false;   // colmax holds zeros (reset by k_finish32)
+    const double* colmax_src = nullptr;   // colmax already holds this V's maxima
+    int colmax_k = 0;                     // (the PCG direction update fills it)
 };
 
 struct pkm_precond {
