@@ -537,7 +537,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         mon.reset();
         return poll();
     };
-    auto judge = [&](Flags fl_now) {   // after an FP64 true residual
+    auto assess = [&](Flags fl_now) {   // after an FP64 true residual
         if (cur == PKM_FP64) return fl_now;
         if (fl_now.broke > 0) return escalate();
         // a true residual above the right-hand side itself while the
@@ -596,7 +596,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         if (do_true) {
             true_residual();
             last_true = it;
-            f = judge(poll());
+            f = assess(poll());
             period.update(f.max_gap, f.max_tru);
             if (verbose)
                 std::fprintf(stderr, "pkm_solve: step %lld, product %d%s, live columns %d, "
