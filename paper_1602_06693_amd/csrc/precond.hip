@@ -631,7 +631,7 @@ __global__ __launch_bounds__(256) void k_sum_chunks(const double* __restrict__ p
 // index q pairs with the matching rows of T.  Whole 16-column blocks load
 // without guards (a row past n reads row 0 and is never stored) and one
 // block ahead of their MFMAs; a ragged last block loads under guards.
-template <int KT, int U>
+template <int KT, int U, bool VEC>
 __global__ __launch_bounds__(256) void k_apply_z(const double* __restrict__ psi, int m,
                                                  const double* __restrict__ T, int ldt,
                                                  const double* __restrict__ dinv,
@@ -663,9 +663,19 @@ __global__ __launch_bounds__(256) void k_apply_z(const double* __restrict__ psi,
     };
     auto load = [&](int m0, double (&la)[U][4], double (&lt)[4][KT]) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+            if (VEC) {   // the lane's four consecutive entries as two 16-byte loads
+                const double2* p2 = reinterpret_cast<const double2*>(prow[u] + m0 + 4 * g);
+                const double2 x0 = p2[0], x1 = p2[1];
+                la[u][0] = x0.x;
+                la[u][1] = x0.y;
+                la[u][2] = x1.x;
+                la[u][3] = x1.y;
+            } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) la[u][q] = prow[u][m0 + 4 * g + q];
+                for (int q = 0; q < 4; ++q) la[u][q] = prow[u][m0 + 4 * g + q];
+            }
+        }
         load_t(m0, lt);
     };
     auto step = [&](const double (&la)[U][4], const double (&lt)[4][KT]) {
@@ -747,8 +757,13 @@ static void apply_chunk(pkm_ctx* ctx, const pkm_precond* pc, int k, int c0, cons
     // PITC: Z already holds blockdiag(D^-1) R; the kernel subtracts Psi T
     const double* dv = pc->kind == PKM_PC_PITC ? nullptr : pc->dinv.as<double>();
     constexpr int U = KT >= 2 ? 2 : 1;
-    k_apply_z<KT, U><<<(unsigned)cdiv(n, 64 * U), 256, 0, s>>>(pc->psi.as<double>(), m, T, ldt,
-                                                              dv, R, k, c0, n, Z);
+    // Psi rows are 16-byte aligned when m is even: vector loads in phase 2
+    if (m % 2 == 0)
+        k_apply_z<KT, U, true><<<(unsigned)cdiv(n, 64 * U), 256, 0, s>>>(pc->psi.as<double>(), m, T,
+                                                                        ldt, dv, R, k, c0, n, Z);
+    else
+        k_apply_z<KT, U, false><<<(unsigned)cdiv(n, 64 * U), 256, 0, s>>>(pc->psi.as<double>(), m, T,
+                                                                         ldt, dv, R, k, c0, n, Z);
     PKM_CHECK_LAUNCH();
 }
 
