@@ -513,7 +513,10 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // are never stored -- and the next block's loads are issued before this
 // block's MFMAs, so a wave keeps a block of HBM reads in flight behind its
 // matrix-core work; the ragged last block of a chunk loads under guards.
-template <int KT, int JT>
+// PAIR (JT = 2, m even): lane cc of the wave's two tiles takes the adjacent
+// Psi columns j0 + 2 cc and j0 + 2 cc + 1, one 16-byte load for both tiles;
+// output row rho of tile t is then column j0 + 2 rho + t.
+template <int KT, int JT, bool PAIR>
 __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, int m,
                                                 const double* __restrict__ R, int k, int c0,
                                                 int kc, int64_t n, int64_t rows_per_chunk,
@@ -526,7 +529,8 @@ __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, 
     const int64_t i1 = min(n, i0 + rows_per_chunk);
     int jc[JT];
 #pragma unroll
-    for (int t = 0; t < JT; ++t) jc[t] = min(j0 + 16 * t + cc, m - 1);
+    for (int t = 0; t < JT; ++t)
+        jc[t] = PAIR ? min(j0 + 2 * cc, m - 2) + t : min(j0 + 16 * t + cc, m - 1);
     int col[KT];
     bool cv[KT];
 #pragma unroll
@@ -545,8 +549,14 @@ __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, 
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t i = ib + 4 * g + q;
+            if (PAIR) {
+                const double2 x = *reinterpret_cast<const double2*>(psi + i * m + jc[0]);
+                la[0][q] = x.x;
+                la[1][q] = x.y;
+            } else {
 #pragma unroll
-            for (int t = 0; t < JT; ++t) la[t][q] = psi[i * m + jc[t]];
+                for (int t = 0; t < JT; ++t) la[t][q] = psi[i * m + jc[t]];
+            }
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt) lb[q][kt] = R[i * k + col[kt]];
         }
@@ -596,7 +606,7 @@ __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, 
         for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int j = j0 + 16 * t + g + 4 * r;
+                const int j = PAIR ? j0 + 2 * (g + 4 * r) + t : j0 + 16 * t + g + 4 * r;
                 if (j < m && cv[kt])
                     part[(int64_t(blockIdx.y) * m + j) * k + c0 + 16 * kt + cc] = acc[t][kt][r];
             }
@@ -748,8 +758,13 @@ static void apply_chunk(pkm_ctx* ctx, const pkm_precond* pc, int k, int c0, cons
     double* T = part + nchunk * int64_t(m) * k;
     // phase 1: each wave takes kPsitJT 16-column tiles of Psi, so the R rows
     // it loads serve kPsitJT MFMA tiles
-    k_psit_r<KT, kPsitJT><<<dim3((unsigned)cdiv(m, AT * kPsitJT), (unsigned)nchunk), 256, 0, s>>>(
-        pc->psi.as<double>(), m, R, k, c0, kc, n, rpc, part);
+    const dim3 grid1((unsigned)cdiv(m, AT * kPsitJT), (unsigned)nchunk);
+    if (kPsitJT == 2 && m % 2 == 0)   // rows 16-byte aligned: paired column loads
+        k_psit_r<KT, kPsitJT, true><<<grid1, 256, 0, s>>>(pc->psi.as<double>(), m, R, k, c0, kc, n,
+                                                           rpc, part);
+    else
+        k_psit_r<KT, kPsitJT, false><<<grid1, 256, 0, s>>>(pc->psi.as<double>(), m, R, k, c0, kc, n,
+                                                            rpc, part);
     PKM_CHECK_LAUNCH();
     k_sum_chunks<<<cdiv(int64_t(m_pad) * ldt, 64), 256, 0, s>>>(part, int(nchunk), m, k, c0, kc,
                                                                 m_pad, ldt, T);
