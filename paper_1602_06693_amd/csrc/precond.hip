@@ -629,7 +629,11 @@ __global__ __launch_bounds__(256) void k_sum_chunks(const double* __restrict__ p
         for (int q = w; q < nchunk; q += 4) s += part[(int64_t(q) * m + j) * k + c0 + c];
     sh[w][lane] = s;
     __syncthreads();
-    if (w == 0 && ev) T[e] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+    // stored column-tile-interleaved: (j, 16 kt + rr) at (16 j + rr) ldt/16 + kt,
+    // so a phase-2 lane finds its KT values of one row next to each other
+    if (w == 0 && ev)
+        T[(int64_t(j) * 16 + c % 16) * (ldt / 16) + c / 16] =
+            (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
 }
 
 // Phase 2: Z = D^-1 R - Psi T for columns [c0, c0 + 16 KT).  Each wave owns
@@ -664,12 +668,19 @@ __global__ __launch_bounds__(256) void k_apply_z(const double* __restrict__ psi,
         for (int kt = 0; kt < KT; ++kt) acc[u][kt] = f64x4{0.0, 0.0, 0.0, 0.0};
     const int mfull = m & ~15;
     double a[U][4], t[4][KT];
-    auto load_t = [&](int m0, double (&lt)[4][KT]) {
+    auto load_t = [&](int m0, double (&lt)[4][KT]) {   // T column-tile-interleaved
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 4; ++q) {
+            const double* tp = T + (int64_t(m0 + 4 * g + q) * 16 + rr) * KT;
+            if (KT == 2) {   // T starts 16-byte aligned
+                const double2 x = *reinterpret_cast<const double2*>(tp);
+                lt[q][0] = x.x;
+                lt[q][KT - 1] = x.y;
+            } else {
 #pragma unroll
-            for (int kt = 0; kt < KT; ++kt)
-                lt[q][kt] = T[int64_t(m0 + 4 * g + q) * ldt + rr + 16 * kt];
+                for (int kt = 0; kt < KT; ++kt) lt[q][kt] = tp[kt];
+            }
+        }
     };
     auto load = [&](int m0, double (&la)[U][4], double (&lt)[4][KT]) {
 #pragma unroll
@@ -753,9 +764,9 @@ static void apply_chunk(pkm_ctx* ctx, const pkm_precond* pc, int k, int c0, cons
     int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 1024 / mt));
     int64_t rpc = round_up(cdiv(n, nchunk), 16);
     nchunk = cdiv(n, rpc);
-    ctx->red2.ensure(sizeof(double) * (nchunk * int64_t(m) * k + int64_t(m_pad) * ldt));
+    ctx->red2.ensure(sizeof(double) * (round_up(nchunk * int64_t(m) * k, 2) + int64_t(m_pad) * ldt));
     double* part = ctx->red2.as<double>();
-    double* T = part + nchunk * int64_t(m) * k;
+    double* T = part + round_up(nchunk * int64_t(m) * k, 2);   // 16-byte aligned
     // phase 1: each wave takes kPsitJT 16-column tiles of Psi, so the R rows
     // it loads serve kPsitJT MFMA tiles
     const dim3 grid1((unsigned)cdiv(m, AT * kPsitJT), (unsigned)nchunk);
