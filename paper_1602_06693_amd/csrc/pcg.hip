@@ -69,8 +69,12 @@ __global__ __launch_bounds__(256) void k_dot_part(const double* __restrict__ u,
     const int64_t chunk = round_up(cdiv(tot, NRED), k);
     const int64_t beg = blockIdx.x * chunk, end = min(tot, beg + chunk);
     double acc = 0.0;
-    if (threadIdx.x < T)
+    if (threadIdx.x < T) {
+        // unrolled so that several iterations' loads are in flight at once;
+        // the additions keep their order
+#pragma unroll 4
         for (int64_t e = beg + threadIdx.x; e < end; e += T) acc = fma(u[e], v[e], acc);
+    }
     sh[threadIdx.x] = acc;
     __syncthreads();
     if (threadIdx.x < k) {
