@@ -355,6 +355,7 @@ __global__ __launch_bounds__(256) void k_update_p_cm(int64_t n, int k,
         const bool stp = stepping(st[col]);
         const double beta = st[col].beta;
         double m = 0.0;
+#pragma unroll 4
         for (int64_t row = int64_t(blockIdx.x) * L + t / k; row < n; row += int64_t(gridDim.x) * L) {
             const int64_t e = row * k + col;
             double v = p[e];
