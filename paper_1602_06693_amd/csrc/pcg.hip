@@ -160,17 +160,45 @@ __global__ __launch_bounds__(256) void k_alpha(const double* __restrict__ ppap, 
     st[c] = s;
 }
 
-// x += alpha p; r -= alpha Ap
-__global__ void k_update_xr(int64_t n, int k, const ColState* __restrict__ st,
-                            const double* __restrict__ p, const double* __restrict__ Ap,
-                            double* __restrict__ x, double* __restrict__ r) {
-    int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (e >= n * k) return;
-    int c = int(e % k);
-    double a = st[c].alpha;
-    if (a != 0.0) {
-        x[e] = fma(a, p[e], x[e]);
-        r[e] = fma(-a, Ap[e], r[e]);
+// x += alpha p; r -= alpha Ap, and the partial sums of r o r over the updated
+// r in the same pass: the grid, the element order and the additions are
+// those of k_dot_part, so the partials equal k_dot_part(r, r) bit for bit
+// (thread t keeps column t % k, whose alpha it reads once)
+__global__ __launch_bounds__(256) void k_update_xr_rr(int64_t n, int k,
+                                                      const ColState* __restrict__ st,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ Ap,
+                                                      double* __restrict__ x,
+                                                      double* __restrict__ r,
+                                                      double* __restrict__ part) {
+    __shared__ double sh[256];
+    const int per = 256 / k;
+    const int T = per * k;
+    const int64_t tot = n * k;
+    const int64_t chunk = round_up(cdiv(tot, NRED), k);
+    const int64_t beg = blockIdx.x * chunk, end = min(tot, beg + chunk);
+    double acc = 0.0;
+    if (threadIdx.x < T) {
+        const double a = st[threadIdx.x % k].alpha;
+        if (a != 0.0) {
+#pragma unroll 4
+            for (int64_t e = beg + threadIdx.x; e < end; e += T) {
+                x[e] = fma(a, p[e], x[e]);
+                const double re = fma(-a, Ap[e], r[e]);
+                r[e] = re;
+                acc = fma(re, re, acc);
+            }
+        } else {
+#pragma unroll 4
+            for (int64_t e = beg + threadIdx.x; e < end; e += T) acc = fma(r[e], r[e], acc);
+        }
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double s = 0.0;
+        for (int q = 0; q < per; ++q) s += sh[threadIdx.x + q * k];
+        part[blockIdx.x * k + threadIdx.x] = s;
     }
 }
 
@@ -569,9 +597,8 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         dot_part(ctx, p, Ap, n, k, partA);
         k_alpha<<<1, 256, 0, s>>>(partA, k, st);
         PKM_CHECK_LAUNCH();
-        k_update_xr<<<gb, 256, 0, s>>>(n, k, st, p, Ap, X, r);
+        k_update_xr_rr<<<NRED, 256, 0, s>>>(n, k, st, p, Ap, X, r, partA);
         PKM_CHECK_LAUNCH();
-        dot_part(ctx, r, r, n, k, partA);
         // a lagged poll after this step takes its flags from k_rr's mirror
         const int64_t it1 = it + 1;
         const bool lag_poll = !(cur != PKM_FP64 && it1 - last_true >= period.cur) &&
