@@ -428,8 +428,9 @@ def main():
             finally:
                 pk.pkm_precond_destroy(pc)
 
+        all_infos = []   # every step, warmup included, must certify
         for _ in range(warmup):
-            step()
+            all_infos.append(step()[1])
         torch.cuda.synchronize()
         pk.pkm_mvm_stats_reset(ctx)
         pk.pkm_timing_enable(ctx, True)
@@ -449,12 +450,14 @@ def main():
         t_all = time.perf_counter() - t_all
         pk.pkm_timing_enable(ctx, False)
         info = infos[-1]
-        assert np.all(info.col_status == pk.PKM_COL_CONVERGED), info.col_status
-        assert np.all(info.relres_true <= p.tol)
+        for i_ in all_infos + infos:
+            assert np.all(i_.col_status == pk.PKM_COL_CONVERGED), i_.col_status
+            assert np.all(i_.relres_true <= p.tol), i_.relres_true.max()
+        max_rel = float(max(i_.relres_true.max() for i_ in all_infos + infos))
         st = pk.pkm_mvm_stats(ctx, prec)
         st64 = pk.pkm_mvm_stats(ctx, pk.PKM_FP64)
         avg_ms = st["ms"] / max(st["launches"], 1)
-        return {"times": times, "t_all": t_all, "info": info, "mvm_ms": avg_ms,
+        return {"times": times, "t_all": t_all, "info": info, "max_rel": max_rel, "mvm_ms": avg_ms,
                 "flops_per_launch": st["flops"] / max(st["launches"], 1),
                 "tflops": st["flops"] / max(st["launches"], 1) / (avg_ms * 1e-3) / 1e12,
                 "fp64_ms": st64["ms"] / max(st64["launches"], 1),
@@ -501,7 +504,7 @@ def main():
                    "parallelism": "single GPU"},
         "iters": int(info.total_iters),
         "true_residual_products": int(info.true_residuals),
-        "max_true_relres": float(info.relres_true.max()),
+        "max_true_relres": mixed["max_rel"],
         "mvm_tflops": mixed["tflops"],
         "mvm_ms": mixed["mvm_ms"],
         "fp64_true_residual_ms": mixed["fp64_ms"],
@@ -529,12 +532,12 @@ def main():
                        "value": statistics.median(fitc["times"]),
                        "iters": int(fitc["info"].total_iters),
                        "true_residual_products": int(fitc["info"].true_residuals),
-                       "max_true_relres": float(fitc["info"].relres_true.max())}
+                       "max_true_relres": fitc["max_rel"]}
     if alt is not None:
         out["alt"] = {"product": a.alt, "value": statistics.median(alt["times"]),
                       "iters": int(alt["info"].total_iters),
                       "true_residual_products": int(alt["info"].true_residuals),
-                      "max_true_relres": float(alt["info"].relres_true.max()),
+                      "max_true_relres": alt["max_rel"],
                       "mvm_ms": alt["mvm_ms"], "mvm_tflops": alt["tflops"]}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, int(info.total_iters))

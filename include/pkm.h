@@ -263,8 +263,12 @@ int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
  * and per-column reports as pkm_solve (infos: host array of P reports, or
  * NULL).  Every PCG phase runs as one launch over all problems; the kernel
  * product is a work-queue launch per input-dimension class whose tile
- * shape is autotuned on first use (cached in memory and, if the
- * environment variable PKM_TUNE_CACHE names a file, there as JSON lines).
+ * shape is autotuned on first use: i-tiles per wave (1, 2 or 4; 2 or 4
+ * for F16X3) times the work-group count below which a problem is split over
+ * column ranges (512, 1024 or 2048), per arithmetic, augmented length,
+ * column tiling and power-of-two bucket of the class's work (cached in
+ * memory and, if the environment variable PKM_TUNE_CACHE names a file, there
+ * as JSON lines; see pkm_tune_cache_load).
  * A problem whose columns all stopped stepping is certified by its own FP64
  * true residual at once; FP64 products run only for problems that need
  * them.  A large problem is split over column ranges of K (partial sums
@@ -277,6 +281,15 @@ int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
 int pkm_solve_batched(pkm_ctx* ctx, int32_t P, const pkm_problem* probs,
                       const pkm_precond* const* pcs, int32_t k, const double* const* B,
                       double* const* X, const pkm_solve_opts* opts, pkm_solve_info* infos);
+
+/* Loads batched-product launch shapes from a tuning cache file (the format
+ * pkm_solve_batched writes to PKM_TUNE_CACHE: one JSON object per line with
+ * the key s4, kt, kr, work and the shape u, fill).  An entry is kept only if
+ * its shape is one the library instantiates for its key; other lines are
+ * counted in *rejected and ignored.  Host-only, no context; safe to call from
+ * any thread (the cache is shared by all contexts and guarded by a lock).
+ * accepted and rejected may be NULL.  PKM_ERR_INVALID for a NULL path.     */
+int pkm_tune_cache_load(const char* path, int32_t* accepted, int32_t* rejected);
 
 /* ---- gradient pass (Eq. (2) with the trace estimate of Section 2.1) -------
  * Given alpha = K_y^-1 y and S = K_y^-1 Z for N Rademacher probes Z, writes
@@ -294,8 +307,11 @@ int pkm_grad_pass(pkm_ctx* ctx, const pkm_problem* prob, int32_t N,
 /* ---- solve + gradient --------------------------------------------------
  * Solves K_y [alpha, S] = [y, Z] with pc and opts, then runs the gradient
  * pass.  y is device n, Z device n x N (N >= 1).  Solutions are written to
- * sol (device n x (1 + N), may be NULL).  info arrays, if given, hold
- * 1 + N entries.                                                           */
+ * sol (device n x (1 + N), may be NULL).  With opts->use_x0, sol must hold
+ * the starting block [alpha_0, S_0] on entry (PKM_ERR_INVALID if sol is
+ * NULL).  pc must have been set up for this problem's n on this context's
+ * device and opts->prec must suit d, as for pkm_solve.  info arrays, if
+ * given, hold 1 + N entries.                                               */
 int pkm_lml_grad(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,
                  const double* y, int32_t N, const double* Z,
                  const pkm_solve_opts* opts, double* grad_host, double* sol,

@@ -53,6 +53,7 @@ EXPORTS = (
     "pkm_laplace_mode", "pkm_laplace_grad", "pkm_laplace_predict", "pkm_grad_pass", "pkm_lml_grad", "pkm_timing_enable", "pkm_mvm_stats",
     "pkm_mvm_stats_reset", "pkm_mlp_create", "pkm_mlp_destroy", "pkm_mlp_params",
     "pkm_mlp_forward", "pkm_mlp_loss_grad", "pkm_mlp_train_step", "pkm_adagrad_step",
+    "pkm_tune_cache_load",
 )
 
 
@@ -143,6 +144,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                         P(C.c_float)]),
         "pkm_mlp_train_step": (C.c_int, [vp, vp, P(pkm_problem), i32, vp, vp, dbl, P(dbl)]),
         "pkm_adagrad_step": (C.c_int, [i32, P(dbl), P(dbl), P(dbl), dbl, dbl]),
+        "pkm_tune_cache_load": (C.c_int, [C.c_char_p, P(i32), P(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -525,6 +527,14 @@ def pkm_adagrad_step(theta, g, G, eta=1.0, eps=1e-8):
                                    g.ctypes.data_as(P), G.ctypes.data_as(P), float(eta),
                                    float(eps)))
     return theta
+
+
+def pkm_tune_cache_load(path):
+    """Merge a batched-product tuning cache file; returns (accepted, rejected)."""
+    a, r = C.c_int32(), C.c_int32()
+    _check(load().pkm_tune_cache_load(None if path is None else str(path).encode(), C.byref(a),
+                                      C.byref(r)))
+    return a.value, r.value
 
 
 def pkm_solve_batched(ctx, probs, Bs, pcs=None, Xs=None, opts=None):

@@ -29,6 +29,7 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
                   pkm_solve_info* infos);
 void grad_pass(pkm_ctx* ctx, const pkm_problem* prob, int N, const double* AS,
                const double* YZ, double* grad);
+void tune_cache_load(const char* path, int* accepted, int* rejected);
 void mlp_create(pkm_ctx* ctx, int d_in, int hidden, int rank, const float* params_host,
                 pkm_mlp* net);
 void mlp_forward(pkm_ctx* ctx, pkm_mlp* net, int64_t n, const double* xs, double* U);
@@ -527,6 +528,17 @@ int pkm_solve_batched(pkm_ctx* ctx, int32_t P, const pkm_problem* probs,
     });
 }
 
+int pkm_tune_cache_load(const char* path, int32_t* accepted, int32_t* rejected) {
+    return guarded(nullptr, [&] {
+        PKM_REQUIRE(path != nullptr, "path is NULL");
+        int a = 0, r = 0;
+        tune_cache_load(path, &a, &r);
+        if (accepted) *accepted = a;
+        if (rejected) *rejected = r;
+        return PKM_OK;
+    });
+}
+
 int pkm_grad_pass(pkm_ctx* ctx, const pkm_problem* prob, int32_t N, const double* AS,
                   const double* YZ, double* grad_host) {
     if (!ctx) return PKM_ERR_INVALID;
@@ -555,6 +567,14 @@ int pkm_lml_grad(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, c
         PKM_REQUIRE(grad_host != nullptr, "grad is NULL");
         pkm_solve_opts o;
         fill_opts(opts, &o);
+        check_prec(o.prec, prob->d);
+        if (pc) {
+            PKM_REQUIRE(pc->n == prob->n, "preconditioner was built for another n");
+            PKM_REQUIRE(pc->device == ctx->device, "preconditioner belongs to another device");
+        }
+        // a warm start comes from the caller's sol (x0 of all 1 + N columns)
+        PKM_REQUIRE(!o.use_x0 || sol != nullptr, "use_x0 needs sol to hold x0");
+        if (sol) require_dev(sol, "sol");
         const int64_t n = prob->n;
         const int k = 1 + N;
         // [y, Z] and [alpha, Z] blocks (row-major n x k), solutions in S
@@ -565,6 +585,8 @@ int pkm_lml_grad(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, c
         double* S = ctx->pcg[6].as<double>();
         double* AZ = ctx->pcg[7].as<double>();
         hipStream_t s = ctx->stream;
+        if (o.use_x0)
+            PKM_HIP(hipMemcpyAsync(S, sol, sizeof(double) * n * k, hipMemcpyDeviceToDevice, s));
         PKM_HIP(hipMemcpy2DAsync(Bk, sizeof(double) * k, y, sizeof(double), sizeof(double), n,
                                  hipMemcpyDeviceToDevice, s));
         PKM_HIP(hipMemcpy2DAsync(Bk + 1, sizeof(double) * k, Z, sizeof(double) * N,

@@ -33,6 +33,7 @@
 #include <cstdlib>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <cstring>
 #include <sstream>
 #include <string>
@@ -877,35 +878,81 @@ struct TuneKey {
     }
 };
 
-static std::map<TuneKey, int> g_tune;   // key -> i-tiles per wave (U)
+// Tuned launch shape of one product class: i-tiles of 16 rows per wave (U;
+// a work-group of 4 waves covers 64 U rows) and the work-group count below
+// which a problem's row blocks are split over column ranges of K (fill).
+struct TuneVal {
+    int u, fill;
+};
+
+static std::mutex g_tune_mu;            // guards g_tune and g_tune_loaded
+static std::map<TuneKey, TuneVal> g_tune;
 static bool g_tune_loaded = false;
 
-static void tune_load() {
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
-    const char* path = std::getenv("PKM_TUNE_CACHE");
-    if (!path) return;
+// A cached entry is used only if its shape is one the launchers instantiate
+// for its key: FP16x3 keys (s4 = 100 + BF16 slices 1..7, kt 1..3, kr = merged
+// last tile 0/1) take U in {2, 4}; FP32 keys (s4 = augmented slices 1..9,
+// kt 0..2, kr 0/1) take U in {1, 2, 4}; fill in {256, ..., 4096}.
+static bool tune_valid(const TuneKey& k, const TuneVal& v) {
+    const bool f16 = k.s4 >= 100;
+    const bool key_ok = f16 ? (k.s4 <= 107 && k.kt >= 1 && k.kt <= 3 && (k.kr == 0 || k.kr == 1))
+                            : (k.s4 >= 1 && k.s4 <= 9 && k.kt >= 0 && k.kt <= 2 &&
+                               (k.kr == 0 || k.kr == 1) && k.kt + k.kr >= 1);
+    const bool u_ok = f16 ? (v.u == 2 || v.u == 4) : (v.u == 1 || v.u == 2 || v.u == 4);
+    const bool fill_ok = v.fill == 256 || v.fill == 512 || v.fill == 1024 || v.fill == 2048 ||
+                         v.fill == 4096;
+    return key_ok && u_ok && fill_ok && k.work_bucket >= 1 &&
+           (k.work_bucket & (k.work_bucket - 1)) == 0;
+}
+
+// One JSON line of the cache file; entries written before the fill field
+// existed take fill 1024 (the earlier fixed value).
+static bool tune_parse(const char* line, TuneKey* k, TuneVal* v) {
+    long long wb = 0;
+    int u = 0, fill = 1024;
+    const int got = std::sscanf(line, " {\"s4\": %d, \"kt\": %d, \"kr\": %d, \"work\": %lld, \"u\": %d, \"fill\": %d",
+                                &k->s4, &k->kt, &k->kr, &wb, &u, &fill);
+    if (got < 5) return false;
+    k->work_bucket = wb;
+    *v = TuneVal{u, fill};
+    return tune_valid(*k, *v);
+}
+
+// Merges the valid entries of a cache file into the in-memory cache (caller
+// holds g_tune_mu); counts accepted and rejected non-empty lines.
+static void tune_merge_file(const char* path, int* accepted, int* rejected) {
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
         TuneKey k{};
-        int u = 0;
-        long long wb = 0;
-        if (std::sscanf(line.c_str(), " {\"s4\": %d, \"kt\": %d, \"kr\": %d, \"work\": %lld, \"u\": %d",
-                        &k.s4, &k.kt, &k.kr, &wb, &u) == 5) {
-            k.work_bucket = wb;
-            g_tune[k] = u;
+        TuneVal v{};
+        if (tune_parse(line.c_str(), &k, &v)) {
+            g_tune[k] = v;
+            ++*accepted;
+        } else {
+            ++*rejected;
         }
     }
 }
 
-static void tune_save() {
+static void tune_load() {   // caller holds g_tune_mu
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("PKM_TUNE_CACHE");
+    if (!path) return;
+    int a = 0, r = 0;
+    tune_merge_file(path, &a, &r);
+}
+
+static void tune_save() {   // caller holds g_tune_mu
     const char* path = std::getenv("PKM_TUNE_CACHE");
     if (!path) return;
     std::ofstream f(path);
     for (auto& kv : g_tune)
         f << "{\"s4\": " << kv.first.s4 << ", \"kt\": " << kv.first.kt << ", \"kr\": " << kv.first.kr
-          << ", \"work\": " << kv.first.work_bucket << ", \"u\": " << kv.second << "}\n";
+          << ", \"work\": " << kv.first.work_bucket << ", \"u\": " << kv.second.u
+          << ", \"fill\": " << kv.second.fill << "}\n";
 }
 
 template <int S4, int KT, int KR>
@@ -1015,7 +1062,10 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     PKM_REQUIRE(prec == PKM_FP32 || prec == PKM_FP64 || prec == PKM_F16X3,
                 "batched solve supports FP32, F16X3 or FP64 products");
     PKM_REQUIRE(k >= 1 && k <= 33, "batched solve supports 1 <= k <= 33");
-    tune_load();
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load();
+    }
 
     // per-problem prepared operands and packed layout (released on every exit)
     struct Preps {
@@ -1283,17 +1333,16 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
         // FP16x3 classes are keyed 100 + slices, (KT16, merged last tile)
         TuneKey key = f16 ? TuneKey{100 + cp.s4, KT16, ml16 ? 1 : 0, wb} : TuneKey{cp.s4, KT, KR, wb};
         // items for U i-tiles per wave; a problem whose row blocks alone give
-        // fewer than kFill work-groups is split over up to kMaxSplit column
+        // fewer than `fill` work-groups is split over up to kMaxSplit column
         // ranges of at least 16 tiles each
-        auto build = [&](int U) {
-            constexpr int kFill = 1024;
+        auto build = [&](int U, int fill) {
             std::vector<std::pair<int64_t, int4>> v;
             for (int b : cp.probs) {
                 const int64_t rows_wg = 64 * U;
                 const int nblk = int(cdiv(preps[b].n_pad, rows_wg));
                 const int64_t ntiles = preps[b].n_pad / 16;
                 int ns = 1;
-                while (ns < kMaxSplit && int64_t(nblk) * ns < kFill && ntiles / (2 * ns) >= 16) ns *= 2;
+                while (ns < kMaxSplit && int64_t(nblk) * ns < fill && ntiles / (2 * ns) >= 16) ns *= 2;
                 hsplit[b] = ns;
                 for (int y = 0; y < nblk; ++y)
                     for (int q = 0; q < ns; ++q) v.push_back({preps[b].n_pad, int4{b, y, q, ns}});
@@ -1317,33 +1366,44 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
             PKM_CHECK_LAUNCH();
             PKM_HIP(hipStreamSynchronize(s));   // items is pageable host memory
         };
-        auto found = g_tune.find(key);
-        if (found == g_tune.end()) {
-            // time U = 1, 2, 4 once on this batch (all problems live, p = 0)
+        TuneVal tv{};
+        bool cached;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto found = g_tune.find(key);
+            cached = found != g_tune.end();
+            if (cached) tv = found->second;
+        }
+        if (!cached) {
+            // time every (U, fill) once on this batch (all problems live, p = 0)
             std::vector<int> ones(P, 1);
             PKM_HIP(hipMemcpyAsync(live, ones.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
             float best_ms = 1e30f;
-            int best_u = 4;
+            tv = TuneVal{4, 1024};
             for (int U : {1, 2, 4}) {
                 if (f16 && U == 1) continue;   // FP16x3 kernels: 2 or 4 i-tiles per wave
-                auto items = build(U);
-                run(U, items);   // warm
-                PKM_HIP(hipEventRecord(ctx->ev0, s));
-                run(U, items);
-                PKM_HIP(hipEventRecord(ctx->ev1, s));
-                PKM_HIP(hipEventSynchronize(ctx->ev1));
-                float ms = 0.f;
-                PKM_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best_u = U;
+                for (int fill : {512, 1024, 2048}) {
+                    auto items = build(U, fill);
+                    run(U, items);   // warm
+                    PKM_HIP(hipEventRecord(ctx->ev0, s));
+                    run(U, items);
+                    PKM_HIP(hipEventRecord(ctx->ev1, s));
+                    PKM_HIP(hipEventSynchronize(ctx->ev1));
+                    float ms = 0.f;
+                    PKM_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        tv = TuneVal{U, fill};
+                    }
                 }
             }
-            g_tune[key] = best_u;
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[key] = tv;
             tune_save();
         }
-        cp.U = g_tune[key];
-        auto items = build(cp.U);
+        PKM_REQUIRE(tune_valid(key, tv), "internal: tuned launch shape not instantiated");
+        cp.U = tv.u;
+        auto items = build(cp.U, tv.fill);
         cp.nitems = int(items.size());
         cp.items.ensure(sizeof(int4) * items.size());
         PKM_HIP(hipMemcpyAsync(cp.items.p, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, s));
@@ -1619,6 +1679,12 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     if (code == PKM_ERR_BREAKDOWN) ctx->err = "batched solve: a column broke down";
     else if (code == PKM_NOT_CONVERGED) ctx->err = "batched solve: a column reached max_iter";
     return code;
+}
+
+void tune_cache_load(const char* path, int* accepted, int* rejected) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load();   // the PKM_TUNE_CACHE file first, so that this file's entries win
+    tune_merge_file(path, accepted, rejected);
 }
 
 }  // namespace pkm

@@ -78,3 +78,27 @@ def test_adagrad_step_host_logic_matches_oracle():
     bad = np.array([1.0, np.nan])
     with pytest.raises(binding.PkmError):
         binding.pkm_adagrad_step(np.zeros(2), bad, np.zeros(2))
+
+
+def test_tune_cache_rejects_shapes_the_library_does_not_instantiate(tmp_path):
+    """A cached launch shape is used only if the launchers instantiate it for
+    its key: FP16x3 keys (s4 >= 100) take 2 or 4 i-tiles per wave, FP32 keys
+    1, 2 or 4; malformed lines are ignored.  Host-only, no GPU."""
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libpkm.so not built")
+    f = tmp_path / "tune.jsonl"
+    f.write_text("\n".join([
+        '{"s4": 104, "kt": 2, "kr": 1, "work": 1024, "u": 4, "fill": 1024}',   # ok
+        '{"s4": 3, "kt": 1, "kr": 1, "work": 64, "u": 1, "fill": 512}',        # ok
+        '{"s4": 3, "kt": 1, "kr": 1, "work": 128, "u": 2}',                    # ok (old format)
+        '{"s4": 104, "kt": 2, "kr": 1, "work": 2048, "u": 1, "fill": 1024}',   # U=1 on FP16x3
+        '{"s4": 3, "kt": 1, "kr": 1, "work": 64, "u": 3, "fill": 512}',        # U=3
+        '{"s4": 3, "kt": 1, "kr": 1, "work": 64, "u": 2, "fill": 1000}',       # fill
+        '{"s4": 12, "kt": 1, "kr": 0, "work": 64, "u": 2, "fill": 512}',       # s4 > 9
+        '{"s4": 3, "kt": 1, "kr": 1, "work": 96, "u": 2, "fill": 512}',        # bucket not 2^p
+        'garbage',
+        '',
+    ]))
+    assert binding.pkm_tune_cache_load(f) == (3, 6)
+    with pytest.raises(binding.PkmError):
+        binding.pkm_tune_cache_load(None)
