@@ -22,6 +22,16 @@ Rounding points emulated here (what the GPU products round):
     so ||E|| grows with ||K|| (about n for smooth kernels) rather than with
     sqrt(n).
 
+  * ``int8 digits``: an FP64-class product on integer matrix cores.  K / sigma2
+    in (0, 1] is carried as the fixed-point integer kint = rint(2^30 K / sigma2)
+    (absolute error <= 2^-31), each V column as vint = rint(2^e V) with the
+    power of two e that puts its largest magnitude in [2^29, 2^30); both
+    integers are written in signed base-256 digits (four digits in
+    [-128, 127] each), digit products are summed exactly (integers), and only
+    the digit pairs whose weight 256^(p + q) has p + q >= 3 are kept.  There is
+    no structured (row- or column-wise) error: the exponent and exp2 are FP64
+    and every rounding is of a single entry, at 2^-30 of its scale.
+
 Functions:
   round_fp32, round_bf16,         elementwise rounding (RNE)
   round_fp16
@@ -30,6 +40,11 @@ Functions:
   refine(Khat, K, lam, b, ...)    FP64-residual refinement on A_hat, history
   fp32_solution_residual(...)     true residual of the exact solution rounded
                                   to FP32 (why x must stay FP64)
+  signed_digits(x, ndig)          base-256 digits in [-128, 127] of integers
+  int8_digit_product(...)         (K + shift I) V under the int8-digit model
+  int8_truncation_bound(...)      largest per-term error of the dropped pairs
+  refinement_factor(apply, ...)   |E(d)| / |r| for d = A^-1 r: the contraction
+                                  one refinement step achieves on residual r
 """
 from __future__ import annotations
 
@@ -42,7 +57,8 @@ from .mlp import round_bf16
 
 __all__ = ["round_fp32", "round_bf16", "round_fp16", "split_fp16", "perturbed_kernel",
            "rho", "refine",
-           "fp32_solution_residual", "augmented_fp32_kernel"]
+           "fp32_solution_residual", "augmented_fp32_kernel", "signed_digits",
+           "int8_digit_product", "int8_truncation_bound", "refinement_factor"]
 
 
 def round_fp32(a):
@@ -139,3 +155,90 @@ def fp32_solution_residual(K, lam, B):
     X = np.linalg.solve(A, B)
     R = B - A @ round_fp32(X)
     return np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0)
+
+
+def signed_digits(x, ndig=4):
+    """Digits s_0 .. s_{ndig-1} in [-128, 127] with x = sum_p s_p 256^p, for
+    integer-valued x (array, |x| well below 2^(8 ndig - 1)).  Textbook
+    signed-digit recursion: s = ((x + 128) mod 256) - 128, x <- (x - s) / 256.
+    Returns an array of shape (ndig,) + x.shape (float64, exact integers)."""
+    x = np.asarray(x, dtype=np.float64).copy()
+    out = np.empty((ndig,) + x.shape)
+    for p in range(ndig):
+        s = np.mod(x + 128.0, 256.0) - 128.0
+        out[p] = s
+        x = (x - s) / 256.0
+    if np.any(x != 0):
+        raise ValueError("value needs more digits")
+    return out
+
+
+def _column_exponents(V):
+    """Power of two e_c per column with max |V_c| 2^e_c in [2^29, 2^30);
+    0 for an all-zero column."""
+    m = np.max(np.abs(V), axis=0)
+    e = np.zeros(V.shape[1], dtype=np.int64)
+    nz = m > 0
+    e[nz] = 29 - np.floor(np.log2(m[nz])).astype(np.int64)
+    # log2 of a value just below a power of two can round up: fix the bracket
+    scaled = np.ldexp(m, e)
+    e[nz & (scaled >= 2.0 ** 30)] -= 1
+    e[nz & (np.ldexp(m, e) < 2.0 ** 29)] += 1
+    return e
+
+
+def int8_digit_product(X, sigma2, lengthscales, V, shift=0.0, min_class=3, K=None):
+    """(K + shift I) V under the int8-digit model (see the module header).
+
+    kint = rint(2^30 K / sigma2) and vint = rint(2^e_c V) in four signed
+    base-256 digits each; G_c = sum over digit pairs with p + q = c of the
+    exact integer products ks_p @ vs_q; the result is
+        sigma2 2^(-30 - e_c) sum_{c >= min_class} 256^c G_c  +  shift V
+    (min_class = 0 keeps every pair: then the K V part is exactly
+    sigma2 kint vint 2^(-30 - e) up to the final FP64 rounding)."""
+    V = np.asarray(V, dtype=np.float64)
+    squeeze = V.ndim == 1
+    if squeeze:
+        V = V[:, None]
+    if K is None:
+        K = kernel_matrix(X, sigma2, lengthscales)
+    kint = np.rint(np.ldexp(K / sigma2, 30))
+    e = _column_exponents(V)
+    vint = np.rint(np.ldexp(V, e[None, :]))
+    ks = signed_digits(kint)
+    vs = signed_digits(vint)
+    n, k = V.shape
+    acc = np.zeros((n, k))
+    for c in range(6, min_class - 1, -1):   # largest weight first
+        G = np.zeros((n, k))
+        for p in range(4):
+            q = c - p
+            if 0 <= q < 4:
+                G += ks[p] @ vs[q]          # integers below 2^53: exact
+        acc += G * 256.0 ** c
+    Y = sigma2 * np.ldexp(acc, -30 - e[None, :]) + shift * V
+    return Y[:, 0] if squeeze else Y
+
+
+def int8_truncation_bound(min_class=3):
+    """Largest |sum over dropped digit pairs| per (i, j) term, in units of
+    2^(-30 - e) sigma2: pairs with p + q < min_class, every digit magnitude at
+    most 128.  Relative to a column's largest scaled value (2^30) this is
+    about 2^-28.4 for min_class = 3."""
+    tot = 0.0
+    for c in range(min_class):
+        npairs = sum(1 for p in range(4) if 0 <= c - p < 4)
+        tot += npairs * 128.0 * 128.0 * 256.0 ** c
+    return tot
+
+
+def refinement_factor(apply, K, lam, R):
+    """Per column |E(d)| / |r| with d = A^-1 r, A = K + lam I and
+    E(d) = apply(d) - A d: one step of FP64-residual refinement around the
+    approximate product turns residual r into about E(A_hat^-1 r) ~ E(d), so
+    this is the contraction it achieves on r (below 1: refinement converges;
+    above 1: it cannot)."""
+    A = K + lam * np.eye(K.shape[0])
+    D = np.linalg.solve(A, R)
+    E = apply(D) - A @ D
+    return np.linalg.norm(E, axis=0) / np.linalg.norm(R, axis=0)

@@ -156,3 +156,100 @@ def test_fp16_split_perturbs_less_than_bf16_split(c1_like):
     print("rho f16x2 %.3e bf16x2 %.3e augmented_fp32 %.3e" % (r16, rb, ra))
     assert r16 < rb / 10
     assert r16 < ra
+
+
+# ---- int8-digit product model ---------------------------------------------
+
+def test_signed_digits_reconstruct_and_stay_in_range():
+    rng = np.random.default_rng(11)
+    x = np.concatenate([rng.integers(-2 ** 30, 2 ** 30, 2000).astype(float),
+                        [0, 1, -1, 127, 128, -128, -129, 255, 256, 2 ** 30, -2 ** 30 + 1]])
+    d = pr.signed_digits(x)
+    assert d.min() >= -128 and d.max() <= 127
+    assert np.all((d * 256.0 ** np.arange(4)[:, None]).sum(axis=0) == x)
+
+
+def test_signed_digits_unique_by_brute_force():
+    """Every two-digit value v in [-128 - 127*256, 127 + 127*256] has exactly
+    one pair (s0, s1) in [-128, 127]^2 with s0 + 256 s1 = v, and the
+    recursion returns it."""
+    s = np.arange(-128, 128)
+    vals = (s[:, None] + 256 * s[None, :]).ravel()
+    assert len(np.unique(vals)) == vals.size              # unique representation
+    pick = np.random.default_rng(12).choice(vals.size, 3000, replace=False)
+    d = pr.signed_digits(vals[pick].astype(float), ndig=2)
+    s0, s1 = np.divmod(pick, 256)                          # pick = i0 * 256 + i1
+    assert np.all(d[0] == s[s0]) and np.all(d[1] == s[s1])
+
+
+def test_column_exponents_bracket():
+    V = np.array([[1.0, -2.0 ** 40, 0.0, np.nextafter(4.0, 0.0), 3.0e-300],
+                  [0.5, 3.0, 0.0, -1.0, 0.0]])
+    e = pr._column_exponents(V)
+    m = np.max(np.abs(V), axis=0)
+    sc = np.ldexp(m, e)
+    nz = m > 0
+    assert np.all((sc[nz] >= 2.0 ** 29) & (sc[nz] < 2.0 ** 30))
+    assert e[2] == 0
+
+
+def test_int8_all_pairs_equal_exact_integer_product():
+    """With every digit pair kept (min_class 0), the model is the exact
+    product of the fixed-point integers kint = rint(2^30 K / sigma2) and
+    vint = rint(2^e V), here recomputed with Python integers."""
+    rng = np.random.default_rng(13)
+    X = rng.random((9, 3))
+    ls = np.array([0.3, 0.5, 0.8])
+    s2 = 2.5
+    V = rng.standard_normal((9, 2)) * np.array([1e-3, 40.0])
+    got = pr.int8_digit_product(X, s2, ls, V, min_class=0)
+    K = kernel_matrix(X, s2, ls)
+    e = pr._column_exponents(V)
+    for c in range(2):
+        vint = [int(np.rint(np.ldexp(v, int(e[c])))) for v in V[:, c]]
+        for i in range(9):
+            kint = [int(np.rint(np.ldexp(K[i, j] / s2, 30))) for j in range(9)]
+            exact = sum(a * b for a, b in zip(kint, vint))
+            assert got[i, c] == pytest.approx(s2 * exact * 2.0 ** (-30 - int(e[c])), rel=1e-15)
+
+
+@pytest.mark.parametrize("min_class", [2, 3])
+def test_int8_truncation_within_bound(min_class):
+    """Dropping the digit pairs with p + q < min_class moves each output by
+    at most n x the per-term bound (in units of sigma2 2^(-30 - e))."""
+    rng = np.random.default_rng(14)
+    n = 200
+    X = rng.standard_normal((n, 4))
+    ls = np.full(4, 1.5)
+    V = rng.standard_normal((n, 3))
+    full = pr.int8_digit_product(X, 1.0, ls, V, min_class=0)
+    part = pr.int8_digit_product(X, 1.0, ls, V, min_class=min_class)
+    e = pr._column_exponents(V)
+    bound = n * pr.int8_truncation_bound(min_class) * 2.0 ** (-30.0 - e)
+    assert np.all(np.abs(part - full) <= bound[None, :])
+    assert np.max(np.abs(part - full) / bound[None, :]) > 1e-4   # the bound is not vacuous
+
+
+def test_int8_model_error_against_exact_product():
+    """Norm-wise error of the model against the FP64 product: K in steps of
+    2^-30 and V in steps of 2^-30 of its column maximum leave about 2^-30
+    relative (the pairs with p + q < 2 add ~2^-36 per term), over an order
+    below FP32-rounded entries and V on the same product (whose K V sums
+    cancel: V is random).  Dropping the pairs with p + q = 2 as well would
+    cost a factor ~4."""
+    rng = np.random.default_rng(15)
+    n = 512
+    X = rng.standard_normal((n, 8))
+    ls = np.exp(rng.uniform(np.log(2), np.log(8), 8))
+    V = rng.standard_normal((n, 5))
+    K = kernel_matrix(X, 1.7, ls)
+    exact = K @ V + 1e-4 * V
+    got = pr.int8_digit_product(X, 1.7, ls, V, shift=1e-4, min_class=2, K=K)
+    err = np.linalg.norm(got - exact, axis=0) / np.linalg.norm(exact, axis=0)
+    f32 = pr.round_fp32(K) @ pr.round_fp32(V) + 1e-4 * V
+    err32 = np.linalg.norm(f32 - exact, axis=0) / np.linalg.norm(exact, axis=0)
+    assert np.all(err < 2.0 ** -29), err
+    assert np.all(err < err32 / 10), (err, err32)
+    got3 = pr.int8_digit_product(X, 1.7, ls, V, shift=1e-4, min_class=3, K=K)
+    err3 = np.linalg.norm(got3 - exact, axis=0) / np.linalg.norm(exact, axis=0)
+    assert np.all(err3 > 2 * err), (err3, err)
