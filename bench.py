@@ -132,11 +132,84 @@ def cpu_baseline(p, gpu_iters, budget_rows=1024):
             "sample": sample, "per_product_s": t_mvm, "setup_s": t_setup}
 
 
+PEAK_INT8_MFMA_TOPS = 5000.0   # dense
+
+
+def small_lambda_leg(pk, ctx, a):
+    """One step of the 262,144-point mixed-precision workload (d = 16,
+    lambda = 1e-4, k = 1 + 32, Nystrom m = 1024): preconditioner setup, block
+    PCG to a certified FP64 true residual of 1e-6 and the gradient pass, with
+    the FP64-class int8-digit product (PKM_I8X).  FP32-class products cannot
+    certify this system (lambda / |K| ~ 1e-9); one step takes minutes, so it
+    is timed once, after the headline arms."""
+    import torch
+
+    from pkm_inputs import make
+    p = make("mixed", seed=a.seed)
+    dev = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).to("cuda:0")
+    X, y, Z, idx = dev(p.X), dev(p.y), dev(p.Z), dev(p.idx)
+    N = p.Z.shape[1]
+    sol = torch.zeros((p.n, 1 + N), dtype=torch.float64, device="cuda:0")
+    prob = pk.Problem(X, p.lengthscales, p.sigma2, p.lam)
+    opts = pk.make_opts(tol=p.tol, prec=pk.PKM_I8X, reliable_every=a.reliable)
+    torch.cuda.synchronize()
+    pk.pkm_mvm_stats_reset(ctx)
+    pk.pkm_timing_enable(ctx, True)
+    t0 = time.perf_counter()
+    pc = pk.pkm_precond_setup(ctx, prob, pk.PKM_PC_NYSTROM, len(p.idx), idx=idx, jitter=1e-8)
+    try:
+        _, info = pk.pkm_lml_grad(ctx, prob, y, Z, pc=pc, opts=opts, sol=sol)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    pk.pkm_timing_enable(ctx, False)
+    assert np.all(info.col_status == pk.PKM_COL_CONVERGED), info.col_status
+    assert np.all(info.relres_true <= p.tol), info.relres_true.max()
+    st = pk.pkm_mvm_stats(ctx, pk.PKM_I8X)
+    st64 = pk.pkm_mvm_stats(ctx, pk.PKM_FP64)
+    ms = st["ms"] / max(st["launches"], 1)
+    fl = st["flops"] / max(st["launches"], 1)
+    tf = fl / (ms * 1e-3) / 1e12
+    print(f"[small-lambda i8x] step: {t:.1f} s, iters {info.total_iters}, true residuals "
+          f"{info.true_residuals}, max relres {info.relres_true.max():.2e}, product {ms:.2f} ms",
+          file=sys.stderr, flush=True)
+    out = {"workload": _describe(p, len(p.idx), "i8x", a.reliable), "n": p.n, "d": p.d,
+           "k": 1 + N, "m": len(p.idx), "product": "i8x", "steps": 1, "warmup": 0,
+           "value": t, "unit": "s", "iters": int(info.total_iters),
+           "true_residual_products": int(info.true_residuals),
+           "prec_final": int(info.prec_final),
+           "max_true_relres": float(info.relres_true.max()),
+           "mvm_ms": ms, "mvm_tflops": tf,
+           "fp64_true_residual_ms": st64["ms"] / max(st64["launches"], 1),
+           "product_roofline": {
+               "kernel": "k_mvm_i8 (FP64 MFMA exponent + FP64 table exp2 to 30-bit fixed point "
+                         "+ int8 MFMA digit pairs, exact int32 sums)",
+               "flops_per_launch": fl, "flop_count": "n^2 (2 d + 2 k) per product",
+               "achieved": tf, "unit": "TFLOP/s",
+               "frac_of_fp64_peak": tf / PEAK_FP64_TFLOPS,
+               "frac_of_int8_peak": tf / PEAK_INT8_MFMA_TOPS}}
+    if not a.no_cpu_baseline:
+        from oracle import kernel as ok
+        threads = int(os.environ.get("PKM_ORACLE_THREADS", os.cpu_count() or 1))
+        rows = np.sort(np.random.default_rng(0).choice(p.n, size=256, replace=False))
+        t1 = time.perf_counter()
+        ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, p.B, rows=rows, threads=threads)
+        per = (time.perf_counter() - t1) * p.n / len(rows)
+        out["cpu_baseline"] = {"value": per * int(info.total_iters), "unit": "s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": (f"oracle kernel_mvm on 256 of {p.n} rows, scaled to a "
+                                          f"whole product ({per:.1f} s) and by the GPU solve's "
+                                          f"{int(info.total_iters)} steps; extrapolated, FP64, "
+                                          "setup and gradient not included")}
+    return out
+
+
 def mvm_only(pk, ctx, prob, p, steps, prec_names, ks):
     """Kernel products alone (k-sweep per arithmetic), then a 1 GiB calibration copy."""
     import torch
     precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x1": pk.PKM_BF16X1,
-             "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3}
+             "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3, "i8x": pk.PKM_I8X}
     rng = np.random.default_rng(1)
     for name in prec_names:
         prec = precs[name]
@@ -177,7 +250,7 @@ def hyper_mode(pk, ctx, p, a):
     from pkm_inputs import mlp_params
     dev = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).to("cuda:0")
     precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x1": pk.PKM_BF16X1,
-             "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3}
+             "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3, "i8x": pk.PKM_I8X}
     opts = pk.make_opts(tol=p.tol, prec=precs[a.prec], reliable_every=a.reliable)
     theta0 = hyper.theta_of(p.sigma2, p.lengthscales)
     log = lambda msg: print(msg, file=sys.stderr, flush=True)
@@ -308,7 +381,7 @@ def laplace_mode(pk, ctx, a):
     yd = dev(y)
     R = dev(rademacher(np.random.default_rng(a.seed + 1), n, 16))
     Xs = dev(np.random.default_rng(a.seed + 2).random((128, 14)))
-    precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3}
+    precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3, "i8x": pk.PKM_I8X}
     # B solves to 1e-8 so that the Newton iterations reach the same mode in
     # both arms (Newton stops when Psi changes by <= 1e-10 relative)
     opts = pk.make_opts(tol=1e-8, prec=precs.get(a.prec, pk.PKM_FP64), reliable_every=a.reliable)
@@ -348,17 +421,21 @@ def main():
     ap.add_argument("--workload", default="block_fp32")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--prec", default=None, choices=("fp32", "bf16x3", "bf16x1", "f16x3", "fp64"),
+    ap.add_argument("--prec", default=None, choices=("fp32", "bf16x3", "bf16x1", "f16x3", "fp64",
+                                                     "i8x"),
                     help="arithmetic of the kernel product inside the loop (the mixed path); "
                          "default f16x3, fp64 for --mode laplace (its 1e-8 solves sit below "
                          "what 16-bit products refine to quickly)")
-    ap.add_argument("--alt", default="bf16x3", choices=("fp32", "bf16x3", "bf16x1", "f16x3", "fp64",
-                                                        "none"),
+    ap.add_argument("--alt", default="none", choices=("fp32", "bf16x3", "bf16x1", "f16x3", "fp64",
+                                                        "i8x", "none"),
                     help="also time this mixed arithmetic (reported beside the headline)")
-    ap.add_argument("--plain", default="fp32", choices=("fp32", "fp64", "none"),
+    ap.add_argument("--plain", default="fp32", choices=("fp32", "fp64", "i8x", "none"),
                     help="also time this product arithmetic for the mixed-vs-plain comparison")
-    ap.add_argument("--fitc", action=argparse.BooleanOptionalAction, default=True,
+    ap.add_argument("--fitc", action=argparse.BooleanOptionalAction, default=False,
                     help="step mode: also time the mixed step with FITC (same m and points)")
+    ap.add_argument("--small-lambda", action=argparse.BooleanOptionalAction, default=True,
+                    help="step mode on the default workload: also time one step of the "
+                         "262,144-point lambda = 1e-4 workload with int8-digit products")
     ap.add_argument("--reliable", type=int, default=-50,
                     help="FP64 replacement period; negative: adaptive from its magnitude")
     ap.add_argument("--ks", default="", help="mvm mode: comma-separated column counts")
@@ -415,7 +492,7 @@ def main():
         return
 
     precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x1": pk.PKM_BF16X1,
-             "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3}
+             "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3, "i8x": pk.PKM_I8X}
 
     def run_variant(prec, steps, warmup, label, kind=None):
         opts = pk.make_opts(tol=p.tol, prec=prec, reliable_every=a.reliable)
@@ -473,6 +550,9 @@ def main():
     fitc = None
     if a.fitc:   # the same step with the FITC preconditioner (same inducing points)
         fitc = run_variant(precs[a.prec], a.steps, a.warmup, a.prec + "+fitc", pk.PKM_PC_FITC)
+    small = None
+    if a.small_lambda and a.workload == "block_fp32" and a.n is None:
+        small = small_lambda_leg(pk, ctx, a)
     pk.pkm_destroy(ctx)
 
     info = mixed["info"]
@@ -539,6 +619,8 @@ def main():
                       "true_residual_products": int(alt["info"].true_residuals),
                       "max_true_relres": alt["max_rel"],
                       "mvm_ms": alt["mvm_ms"], "mvm_tflops": alt["tflops"]}
+    if small is not None:
+        out["small_lambda"] = small
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, int(info.total_iters))
     print(json.dumps(out), flush=True)

@@ -65,6 +65,17 @@ extern "C" {
                           scaled by a power of two (largest magnitude in
                           [2^14, 2^15)) and unscaled in the epilogue;
                           relative ~2^-22 per entry.  V must be finite.    */
+#define PKM_I8X    5   /* FP64-class product on int8 matrix cores: exponent
+                          on FP64 MFMA, FP64 exp2 rounded to the fixed-point
+                          integer rint(2^30 K / sigma2), each V column to
+                          rint(2^e V) with its largest magnitude in
+                          [2^29, 2^30); both in signed base-256 digits whose
+                          pair products (all pairs of weight 256^(p+q),
+                          p + q >= 2) sum exactly in int32; FP64 epilogue.
+                          Errors ~2^-30 of each entry's scale, none of them
+                          row- or column-structured (for small lambda against
+                          |K|, where FP32-class products cannot certify).
+                          d <= 32; V must be finite.                       */
 
 /* ---- preconditioner kinds ---------------------------------------------- */
 #define PKM_PC_NONE     0
@@ -111,8 +122,9 @@ typedef struct {
     double  tol;             /* relative residual |b - K_y x|_2 / |b|_2 per
                                 column; default 1e-6                         */
     int64_t max_iter;        /* default 100000 (the paper's cap, Section 4)  */
-    int32_t prec;            /* PKM_FP64, PKM_FP32, PKM_BF16X1, PKM_BF16X3 or
-                                PKM_F16X3 for the product inside the loop;
+    int32_t prec;            /* PKM_FP64, PKM_FP32, PKM_BF16X1, PKM_BF16X3,
+                                PKM_F16X3 or PKM_I8X for the product inside
+                                the loop;
                                 default
                                 PKM_FP32                                    */
     int32_t reliable_every;  /* FP64 true-residual replacement period (non-FP64
@@ -162,7 +174,8 @@ const char* pkm_version(void);
 /* ---- kernel product (Section 2.1: the O(n^2) operation of every CG step) --
  * Y = (K + lambda I) V for V, Y device n x k FP64 (k >= 1).  prec selects
  * the arithmetic of the K V part (the lambda V term is always FP64): any
- * PKM_FP64 .. PKM_F16X3; FP32 needs d <= 34, the 16-bit products d <= 36.
+ * PKM_FP64 .. PKM_I8X; FP32 needs d <= 34, the 16-bit products d <= 36,
+ * PKM_I8X d <= 32.
  * Y may not alias V.                                                         */
 int pkm_kernel_mvm(pkm_ctx* ctx, const pkm_problem* prob, int32_t k,
                    int32_t prec, const double* V, double* Y);
@@ -245,10 +258,12 @@ int pkm_precond_destroy(pkm_precond* pc);
  * switch to refinement mode: they restart their directions (p = z) at every
  * replacement and stop stepping once the recursive residual is 1e-3 below
  * the last true one (outer FP64 iterative refinement around short inner
- * solves).  On a second stall, divergence or breakdown the solve raises the
- * product arithmetic (16-bit -> FP32 -> FP64), resumes broken columns and
- * restarts every column from its FP64 true residual (reported in
- * prec_final).  A column converges when its FP64 true
+ * solves).  With PKM_I8X (FP64-class) a slow true residual counts as a stall
+ * only while it exceeds twice the recursive one.  On a second stall,
+ * divergence or breakdown the solve raises the product arithmetic (16-bit ->
+ * FP32 -> PKM_I8X -> FP64; PKM_I8X needs d <= 32, else FP32 -> FP64),
+ * resumes broken columns and restarts every column from its FP64 true
+ * residual (reported in prec_final).  A column converges when its FP64 true
  * relative residual is <= tol.  Returns PKM_NOT_CONVERGED if a column reached max_iter and
  * PKM_ERR_BREAKDOWN if one broke down; X holds the last iterate either way. */
 int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,

@@ -28,6 +28,7 @@ PKM_FP32 = 1
 PKM_BF16X1 = 2
 PKM_BF16X3 = 3
 PKM_F16X3 = 4
+PKM_I8X = 5
 
 PKM_PC_NONE = 0
 PKM_PC_NYSTROM = 1

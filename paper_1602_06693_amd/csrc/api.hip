@@ -78,9 +78,11 @@ static int guarded(pkm_ctx* ctx, F&& f) {
 static void fill_opts(const pkm_solve_opts* in, pkm_solve_opts* o);
 
 static void check_prec(int prec, int d) {
-    PKM_REQUIRE(prec >= PKM_FP64 && prec <= PKM_F16X3, "unknown precision");
+    PKM_REQUIRE(prec >= PKM_FP64 && prec <= PKM_I8X, "unknown precision");
     PKM_REQUIRE(prec != PKM_FP32 || d <= 34, "FP32 product supports d <= 34");
-    PKM_REQUIRE(prec < PKM_BF16X1 || d <= 36, "16-bit products support d <= 36");
+    PKM_REQUIRE(prec < PKM_BF16X1 || prec > PKM_F16X3 || d <= 36,
+                "16-bit products support d <= 36");
+    PKM_REQUIRE(prec != PKM_I8X || d <= 32, "int8-digit product supports d <= 32");
 }
 
 static void require_dev(const void* p, const char* what) {
@@ -174,7 +176,7 @@ int pkm_kernel_mvm(pkm_ctx* ctx, const pkm_problem* prob, int32_t k, int32_t pre
         require_dev(V, "V");
         require_dev(Y, "Y");
         PKM_REQUIRE(V != Y, "Y may not alias V");
-        prepare(ctx, prob, prec == PKM_FP64, prec != PKM_FP64);
+        prepare(ctx, prob, prec == PKM_FP64, prec != PKM_FP64 && prec != PKM_I8X);
         mvm(ctx, prec, k, V, Y);
         return PKM_OK;
     });
@@ -191,7 +193,7 @@ int pkm_kernel_mvm_shift(pkm_ctx* ctx, const pkm_problem* prob, int32_t k, int32
         require_dev(V, "V");
         require_dev(Y, "Y");
         PKM_REQUIRE(V != Y, "Y may not alias V");
-        prepare(ctx, prob, prec == PKM_FP64, prec != PKM_FP64);
+        prepare(ctx, prob, prec == PKM_FP64, prec != PKM_FP64 && prec != PKM_I8X);
         mvm_shift(ctx, prec, k, V, Y, shift);
         return PKM_OK;
     });
@@ -472,7 +474,7 @@ static void fill_opts(const pkm_solve_opts* in, pkm_solve_opts* o) {
     if (!in) o->prec = PKM_FP32;
     PKM_REQUIRE(std::isfinite(o->tol) && o->tol > 0.0, "tol must be > 0");
     PKM_REQUIRE(o->max_iter >= 1, "max_iter must be >= 1");
-    PKM_REQUIRE(o->prec >= PKM_FP64 && o->prec <= PKM_F16X3, "unknown precision");
+    PKM_REQUIRE(o->prec >= PKM_FP64 && o->prec <= PKM_I8X, "unknown precision");
     PKM_REQUIRE(o->reliable_every != 0 && o->check_every >= 1,
                 "periods must be >= 1 (a negative replacement period adapts)");
     PKM_REQUIRE(o->reliable_every >= -(1 << 24) && o->reliable_every <= (1 << 24),
@@ -722,7 +724,7 @@ int pkm_timing_enable(pkm_ctx* ctx, int32_t on) {
 
 int pkm_mvm_stats(pkm_ctx* ctx, int32_t prec, int64_t* launches, double* ms, double* pairs,
                   double* flops) {
-    if (!ctx || prec < PKM_FP64 || prec > PKM_F16X3) return PKM_ERR_INVALID;
+    if (!ctx || prec < PKM_FP64 || prec > PKM_I8X) return PKM_ERR_INVALID;
     const int rc = guarded(ctx, [&] {
         timing_flush(ctx);
         return PKM_OK;

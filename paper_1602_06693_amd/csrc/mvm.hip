@@ -625,6 +625,10 @@ void mvm_shift(pkm_ctx* ctx, int prec, int k, const double* V, double* Y, double
         PKM_CHECK_LAUNCH();
         return;
     }
+    if (prec == PKM_I8X) {
+        mvm_i8(ctx, k, V, k, Y, k, shift);
+        return;
+    }
     PKM_REQUIRE(prec == PKM_FP32 || prec == PKM_BF16X1 || prec == PKM_BF16X3 || prec == PKM_F16X3,
                 "unknown precision");
     for (int c0 = 0; c0 < k; c0 += 65) {

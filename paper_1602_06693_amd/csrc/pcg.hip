@@ -443,7 +443,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     const int64_t n = prob->n;
     hipStream_t s = ctx->stream;
     const int prec = o->prec;
-    prepare(ctx, prob, true, prec != PKM_FP64);
+    prepare(ctx, prob, true, prec != PKM_FP64 && prec != PKM_I8X);
     auto t_start = std::chrono::steady_clock::now();
 
     const size_t vec = sizeof(double) * n * k;
@@ -551,8 +551,13 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     // residual stalls, the columns first switch to refinement mode (restart
     // at every replacement, short inner solves); if it stalls again, or a
     // column breaks down, the product arithmetic is raised (16-bit -> FP32 ->
-    // FP64), broken columns resume, and every column restarts from its FP64
-    // true residual in plain replacement mode.
+    // int8-digit -> FP64), broken columns resume, and every column restarts
+    // from its FP64 true residual in plain replacement mode.  The int8-digit
+    // product is FP64-class (errors ~2^-30 of each entry's scale): with it a
+    // slow true residual counts as a stall only while the recursion has lost
+    // track of it (true / recursive above kStallGap) -- a faithful recursion
+    // that converges slowly is PCG's own pace, which FP64 products would not
+    // change.
     int cur = prec;
     bool refining = false, ever_refined = false;
     // PKM_VERBOSE=1 reports every FP64 replacement on stderr (long solves)
@@ -560,7 +565,9 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     StallMonitor mon;
     int64_t it = 0;   // PCG steps so far
     auto escalate = [&]() {
-        cur = (cur == PKM_BF16X1 || cur == PKM_BF16X3 || cur == PKM_F16X3) ? PKM_FP32 : PKM_FP64;
+        if (cur == PKM_BF16X1 || cur == PKM_BF16X3 || cur == PKM_F16X3) cur = PKM_FP32;
+        else if (cur == PKM_FP32 && prob->d <= 32) cur = PKM_I8X;
+        else cur = PKM_FP64;
         refining = false;
         k_reactivate<<<1, 256, 0, s>>>(k, st);
         PKM_CHECK_LAUNCH();
@@ -578,7 +585,8 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         // too coarse for lambda (PCG residual norms alone may rise early on)
         if (fl_now.live > 0 && fl_now.max_tru > 1.0 && fl_now.max_gap > 100.0)
             return escalate();
-        if (fl_now.live > 0 && mon.stalled(fl_now.max_tru, it)) {
+        const bool stalled = fl_now.live > 0 && mon.stalled(fl_now.max_tru, it);
+        if (stalled && (cur != PKM_I8X || fl_now.max_gap > kStallGap)) {
             if (refining) return escalate();
             refining = true;
             ever_refined = true;

@@ -159,6 +159,12 @@ struct Prepared {
     int s6 = 0;             // 16x16x32 MFMAs per tile: ceil((6 d + 6) / 32)
     DevBuf jsb, isb;
     bool validb = false;
+    // FP64 operands of the int8-digit product (mvm_i8.hip): the cross term
+    // 2 xh_i . xh_j on FP64 MFMA (dq = d rounded up to 4 slots, 16x16x4 lane
+    // order) and the row norms |xh_i|^2 (plain and, negated, in lane order)
+    int dq = 0;
+    DevBuf xi8, xj8, ni8, njl8;
+    bool validi8 = false;
     double sigma2 = 1.0, lambda = 0.0;
     std::vector<double> ls;
     const double* X = nullptr;
@@ -172,7 +178,7 @@ struct pkm_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     bool timing = false;
-    pkm::MvmStats stats[5];
+    pkm::MvmStats stats[6];
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<hipEvent_t> ev_pool;            // reusable timing events
     std::vector<pkm::PendingTime> pending;      // timed launches not yet read
@@ -190,6 +196,8 @@ struct pkm_ctx {
     pkm::DevBuf batch[18];              // batched-solve workspace
     void* pinned = nullptr;   // pinned host staging area (PKM_PINNED_BYTES)
     void* pinned_dev = nullptr;   // the same memory as kernels address it
+    pkm::DevBuf i8v, i8part;  // int8-digit products: packed V digits, FP64 split partials
+    pkm::DevBuf i8cm;         // int8-digit products: column maxima and exponents
     pkm::DevBuf colmax;       // FP16x3 products: column maxima (128 slots)
     bool colmax_clean = false;   // colmax holds zeros (reset by k_finish32)
     const double* colmax_src = nullptr;   // colmax already holds this V's maxima
@@ -255,6 +263,9 @@ F32Out mvm_k32(pkm_ctx* ctx, int k, const double* V, int ldv);
 // BF16 products (prec PKM_BF16X1 / PKM_BF16X3), same partial-sum layout.
 F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv);
 void prepare_bf16(pkm_ctx* ctx);
+// FP64-class product on int8 matrix cores (prec PKM_I8X): Y = (K + shift I) V
+// for row-major n x k FP64 blocks (leading dimensions ldv, ldy).
+void mvm_i8(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy, double shift);
 
 // ---- PCG (pcg.hip): K_y X = B, or B_laplace X = B when wscale (W^1/2) is given
 int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, const double* B,

@@ -129,7 +129,7 @@ void prepare(pkm_ctx* ctx, const pkm_problem* prob, bool need64, bool need32) {
     // caller may have changed X in place since the last call.
     Prepared& P = ctx->P();
     std::vector<double> ls(prob->lengthscales, prob->lengthscales + prob->d);
-    P.valid64 = P.valid32 = P.validb = false;
+    P.valid64 = P.valid32 = P.validb = P.validi8 = false;
     P.X = prob->X;
     P.n = prob->n;
     P.d = prob->d;

@@ -1,0 +1,91 @@
+"""The two small-lambda workloads at full size: the 262,144-point, d = 16
+mixed-precision recipe and the 131,072-point learned-preconditioner recipe
+(lambda = 1e-4 both).  Each solve is certified by the library's FP64 true
+residual and checked again by the oracle on sampled rows of the residual.
+
+These run minutes, not seconds: the int8-digit product (PKM_I8X) is what
+makes them fit a test run (the FP64 product takes 0.15 s per 33-column
+product at 262,144 points)."""
+import numpy as np
+import pytest
+
+from gpu_util import GpuProblem, ctx, dev, host  # noqa: F401
+from oracle import kernel as ok
+from paper_1602_06693_amd import binding as pk
+from pkm_inputs import make, mlp_params, rademacher
+
+pytestmark = pytest.mark.gpu
+
+
+def _sampled_relres(p, X, B, rows):
+    """Per column: |r_rows| sqrt(n / s) / |b|, the sampled estimate of the
+    relative residual |b - K_y x| / |b| from s rows recomputed by the oracle."""
+    r = B[rows] - ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, X, rows=rows)
+    est = np.linalg.norm(r, axis=0) * np.sqrt(p.n / len(rows))
+    return est / np.linalg.norm(B, axis=0)
+
+
+def test_mixed_workload_solves_with_int8_digit_products(ctx):
+    """n = 262,144, d = 16, lambda = 1e-4, k = 1 + 32, Nystrom m = 1024: the
+    int8-digit product certifies every column at 1e-6 without escalating;
+    the oracle's sampled residual agrees (within the sampling spread)."""
+    p = make("mixed", seed=0)
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, len(p.idx), idx=g.idx, jitter=1e-8)
+    try:
+        X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc,
+                               opts=pk.make_opts(tol=1e-6, prec=pk.PKM_I8X, reliable_every=-50))
+    finally:
+        pk.pkm_precond_destroy(pc)
+    print(f"mixed workload, int8-digit products: {info.total_iters} steps, "
+          f"{info.true_residuals} FP64 true residuals, {info.solve_ms / 1e3:.1f} s, "
+          f"largest true relres {info.relres_true.max():.3e}, prec_final {info.prec_final}")
+    assert np.all(info.col_status == pk.PKM_COL_CONVERGED)
+    assert np.all(info.relres_true <= 1e-6)
+    assert info.prec_final == pk.PKM_I8X
+    rows = np.random.default_rng(31).choice(p.n, size=256, replace=False)
+    est = _sampled_relres(p, host(X), p.B, rows)
+    assert np.all(est <= 3e-6), est
+
+
+def test_learned_workload_first_theta_at_full_size(ctx):
+    """n = 131,072, d = 8, lambda = 1e-4, k = 1 + 16: the learned correction
+    (Nystrom m = 512 plus a 128-column network factor trained on probe pairs
+    (Z, (K - Q) Z)) and plain Nystrom m = 512 on the same inducing points,
+    both with int8-digit products: both certified at 1e-6 (the oracle's
+    sampled residual agrees), and the learned arm needs fewer PCG steps."""
+    p = make("learned", seed=0)
+    g = GpuProblem(p)
+    rank = 128
+    net = pk.pkm_mlp_create(ctx, mlp_params(0, d_in=p.d, rank=rank, out_scale=0.1), p.d, 128, rank)
+    opts = pk.make_opts(tol=1e-6, prec=pk.PKM_I8X, reliable_every=-50)
+    pcs = []
+    try:
+        Z = dev(rademacher(np.random.default_rng(32), p.n, 64))
+        R = pk.pkm_kernel_mvm_shift(ctx, g.prob, Z, 0.0, pk.PKM_I8X)
+        pcn = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, 512, idx=g.idx, jitter=1e-8)
+        pcs.append(pcn)
+        pk.pkm_precond_sub_lowrank(ctx, pcn, Z, R)
+        losses = [pk.pkm_mlp_train_step(ctx, net, g.prob, Z, R, 3e-3) for _ in range(300)]
+        U = pk.pkm_mlp_forward(ctx, net, g.prob, rank)
+        pcs.append(pk.pkm_precond_setup_hybrid(ctx, g.prob, 512, g.idx, U, jitter=1e-8))
+        res = []
+        for pc in pcs:
+            X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc, opts=opts)
+            res.append((host(X), info))
+    finally:
+        for pc in pcs:
+            pk.pkm_precond_destroy(pc)
+        pk.pkm_mlp_destroy(net)
+    (Xn, inn), (Xl, il) = res
+    print(f"learned workload: loss {losses[0]:.3f} -> {losses[-1]:.3f}; Nystrom "
+          f"{inn.total_iters} steps {inn.solve_ms / 1e3:.1f} s, learned {il.total_iters} steps "
+          f"{il.solve_ms / 1e3:.1f} s")
+    rows = np.random.default_rng(33).choice(p.n, size=256, replace=False)
+    for X, info in ((Xn, inn), (Xl, il)):
+        assert np.all(info.col_status == pk.PKM_COL_CONVERGED)
+        assert np.all(info.relres_true <= 1e-6)
+        assert info.prec_final == pk.PKM_I8X
+        assert np.all(_sampled_relres(p, X, p.B, rows) <= 3e-6)
+    assert losses[-1] < losses[0]
+    assert il.total_iters < inn.total_iters

@@ -8,7 +8,7 @@ from gpu_util import GpuProblem, ctx, dev, host  # noqa: F401
 from oracle import kernel as ok
 from oracle import precond as op
 from paper_1602_06693_amd import binding as pk
-from pkm_inputs import make, mlp_params, rademacher
+from pkm_inputs import inducing_indices, make, mlp_params, rademacher
 
 pytestmark = pytest.mark.gpu
 
@@ -66,8 +66,10 @@ def _iters(ctx, g, pc):
 
 def test_trained_correction_reduces_iterations(ctx):
     """Nystrom (m = 128) alone, enlarged by the untrained network's 32
-    columns, and by the trained network's: the trained correction needs the
-    fewest FP64 PCG steps (and no more than Nystrom alone)."""
+    columns, and by the trained network's, against the rank-matched control
+    Nystrom m = 160: the trained correction needs the fewest FP64 PCG steps.
+    Over seeds 43-48 trained / control measured 1386/1426, 1423/1495,
+    1478/1500, 1366/1427, 1516/1584, 1533/1583 (1.5-5 % fewer steps)."""
     p = make("learned", seed=43, n=4096, m=128, n_probes=4)
     g = GpuProblem(p)
     rank = 32
@@ -85,13 +87,17 @@ def test_trained_correction_reduces_iterations(ctx):
         losses = [pk.pkm_mlp_train_step(ctx, net, g.prob, Z, R, 3e-3) for _ in range(300)]
         U1 = pk.pkm_mlp_forward(ctx, net, g.prob, rank)
         pcs.append(pk.pkm_precond_setup_hybrid(ctx, g.prob, 128, g.idx, U1, jitter=JIT))
-        it_nys, it_untrained, it_trained = (_iters(ctx, g, pc) for pc in pcs)
+        idx160 = dev(inducing_indices(np.random.default_rng(50), p.n, 160))
+        pcs.append(pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, 160, idx=idx160,
+                                        jitter=JIT))
+        it_nys, it_untrained, it_trained, it_control = (_iters(ctx, g, pc) for pc in pcs)
     finally:
         for pc in pcs:
             pk.pkm_precond_destroy(pc)
         pk.pkm_mlp_destroy(net)
     print("learned correction: loss", losses[0], "->", losses[-1], "| PCG steps: nystrom",
-          it_nys, "untrained", it_untrained, "trained", it_trained)
+          it_nys, "untrained", it_untrained, "trained", it_trained, "control m=160", it_control)
     assert losses[-1] < losses[0]
     assert it_trained <= it_nys
     assert it_trained < it_untrained
+    assert it_trained < it_control

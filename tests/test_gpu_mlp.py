@@ -113,8 +113,13 @@ def test_learned_factor_reduces_pcg_steps(ctx):
     Xc, ic = pk.pkm_solve(ctx, prob, dev(p.B), opts=pk.make_opts(tol=1e-6, prec=pk.PKM_FP64,
                                                                    max_iter=20000))
     assert np.all(il.col_status == pk.PKM_COL_CONVERGED)
-    # about half the steps (675-836 against 1307-1669); iteration counts move
-    # by a few with the rounding order of the dot products, so the margin is 0.6
-    assert il.iters.max() < 0.6 * ic.iters.max(), (il.iters, ic.iters)
+    # The learned/plain step ratio of this recipe, measured over seeds 1-8
+    # (network seed 5 + s - 1): 0.501, 0.633, 0.528, 0.502, 0.506, 0.601,
+    # 0.589, 0.483 (mean 0.54); this test's seed 1 gives 0.501 (836 / 1669).
+    # The bound is the largest of the eight, rounded up: 0.65.  Against
+    # Nystrom of equal rank (m = 64) the same factor ranged 0.84-1.04, so it
+    # is not asserted to beat it (the hybrid test in test_gpu_learned.py does
+    # assert that against a rank-matched control).
+    assert il.iters.max() < 0.65 * ic.iters.max(), (il.iters, ic.iters)
     r_true = p.B - ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, host(Xl))
     assert np.all(np.linalg.norm(r_true, axis=0) / np.linalg.norm(p.B, axis=0) <= 1e-6)
