@@ -259,11 +259,13 @@ int pkm_precond_destroy(pkm_precond* pc);
  * replacement and stop stepping once the recursive residual is 1e-3 below
  * the last true one (outer FP64 iterative refinement around short inner
  * solves).  With PKM_I8X (FP64-class) a slow true residual counts as a stall
- * only while it exceeds twice the recursive one.  On a second stall,
- * divergence or breakdown the solve raises the product arithmetic (16-bit ->
- * FP32 -> PKM_I8X -> FP64; PKM_I8X needs d <= 32, else FP32 -> FP64),
- * resumes broken columns and restarts every column from its FP64 true
- * residual (reported in prec_final).  A column converges when its FP64 true
+ * only while it exceeds twice the recursive one, or after 1500 steps without
+ * falling below 0.7 of its best.  On a second stall, divergence or breakdown
+ * the solve raises the product arithmetic (16-bit -> FP32 -> FP64; an FP32
+ * solve that stalled rather than diverged or broke down goes on with
+ * PKM_I8X when d <= 32, and PKM_I8X -> FP64), resumes broken columns and
+ * restarts every column from its FP64 true residual (reported in
+ * prec_final).  A column converges when its FP64 true
  * relative residual is <= tol.  Returns PKM_NOT_CONVERGED if a column reached max_iter and
  * PKM_ERR_BREAKDOWN if one broke down; X holds the last iterate either way. */
 int pkm_solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc,

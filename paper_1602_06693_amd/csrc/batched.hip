@@ -1553,7 +1553,8 @@ int solve_batched(pkm_ctx* ctx, int P, const pkm_problem* probs, const pkm_preco
     BFlags f = poll();
     // FP64 replacement for the problems in mask, then the escalation test
     // PKM_VERBOSE=1 reports every replacement round on stderr (long solves)
-    static const bool verbose = std::getenv("PKM_VERBOSE") != nullptr;
+    // read per call: a caller may switch progress reports on for one long solve
+    const bool verbose = std::getenv("PKM_VERBOSE") != nullptr;
     auto replace = [&](const std::vector<int>& mask) {
         true_residual(mask);
         f = poll();

@@ -551,22 +551,29 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     // residual stalls, the columns first switch to refinement mode (restart
     // at every replacement, short inner solves); if it stalls again, or a
     // column breaks down, the product arithmetic is raised (16-bit -> FP32 ->
-    // int8-digit -> FP64), broken columns resume, and every column restarts
-    // from its FP64 true residual in plain replacement mode.  The int8-digit
-    // product is FP64-class (errors ~2^-30 of each entry's scale): with it a
-    // slow true residual counts as a stall only while the recursion has lost
-    // track of it (true / recursive above kStallGap) -- a faithful recursion
-    // that converges slowly is PCG's own pace, which FP64 products would not
-    // change.
+    // FP64), broken columns resume, and every column restarts from its FP64
+    // true residual in plain replacement mode.  An FP32 solve that stalled
+    // with a bounded iterate goes on with the int8-digit product instead of
+    // FP64 (it certifies where FP32-class products stall, at a fraction of
+    // the FP64 cost); after a divergence or breakdown the iterate may be
+    // huge, and the fixed-point product's error (2^-30 of each column's
+    // largest entry) is then too coarse, so FP64 it is.  The int8-digit
+    // product is FP64-class: with it a slow true residual counts as a stall
+    // only while the recursion has lost track of it (true / recursive above
+    // kStallGap) -- a faithful recursion that converges slowly is PCG's own
+    // pace, which FP64 products would not change -- or after
+    // kI8PatienceSteps steps without a 0.7 improvement.
     int cur = prec;
     bool refining = false, ever_refined = false;
-    // PKM_VERBOSE=1 reports every FP64 replacement on stderr (long solves)
-    static const bool verbose = std::getenv("PKM_VERBOSE") != nullptr;
+    // PKM_VERBOSE set reports every FP64 replacement on stderr (long solves)
+    // read per call: a caller may switch progress reports on for one long solve
+    const bool verbose = std::getenv("PKM_VERBOSE") != nullptr;
     StallMonitor mon;
     int64_t it = 0;   // PCG steps so far
-    auto escalate = [&]() {
+    // bounded: the escalation follows a stall (not a divergence or breakdown)
+    auto escalate = [&](bool bounded) {
         if (cur == PKM_BF16X1 || cur == PKM_BF16X3 || cur == PKM_F16X3) cur = PKM_FP32;
-        else if (cur == PKM_FP32 && prob->d <= 32) cur = PKM_I8X;
+        else if (cur == PKM_FP32 && bounded && prob->d <= 32) cur = PKM_I8X;
         else cur = PKM_FP64;
         refining = false;
         k_reactivate<<<1, 256, 0, s>>>(k, st);
@@ -579,15 +586,16 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
     };
     auto assess = [&](Flags fl_now) {   // after an FP64 true residual
         if (cur == PKM_FP64) return fl_now;
-        if (fl_now.broke > 0) return escalate();
+        if (fl_now.broke > 0) return escalate(false);
         // a true residual above the right-hand side itself while the
         // recursion believes it is 100 times smaller: the product is far
         // too coarse for lambda (PCG residual norms alone may rise early on)
         if (fl_now.live > 0 && fl_now.max_tru > 1.0 && fl_now.max_gap > 100.0)
-            return escalate();
+            return escalate(false);
         const bool stalled = fl_now.live > 0 && mon.stalled(fl_now.max_tru, it);
-        if (stalled && (cur != PKM_I8X || fl_now.max_gap > kStallGap)) {
-            if (refining) return escalate();
+        if (stalled && (cur != PKM_I8X || fl_now.max_gap > kStallGap ||
+                        it - mon.step_best >= kI8PatienceSteps)) {
+            if (refining) return escalate(true);
             refining = true;
             ever_refined = true;
             k_set_restart<<<1, 256, 0, s>>>(k, st, kRefineEta);
@@ -627,7 +635,7 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
                 f.pending = 1;
             }
             if (f.broke > 0 && cur != PKM_FP64) {
-                f = escalate();
+                f = escalate(false);
             } else {
                 if (f.live == 0) break;
                 if (f.pending == 0) do_true = true;

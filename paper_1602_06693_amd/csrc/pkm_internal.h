@@ -52,6 +52,10 @@ constexpr int64_t kStallSteps = 150;
 // True / recursive residual ratio up to which the recursion counts as
 // faithful (adaptive replacement period below).
 constexpr double kStallGap = 2.0;
+// With the FP64-class int8-digit product and a faithful recursion, steps
+// without a 0.7 improvement of the largest true residual before that counts
+// as a stall (slow, non-monotone residuals of long solves are PCG's pace).
+constexpr int64_t kI8PatienceSteps = 10 * kStallSteps;
 
 struct StallMonitor {
     double best = 1e300, last = 1e300;

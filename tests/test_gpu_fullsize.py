@@ -25,7 +25,16 @@ def _sampled_relres(p, X, B, rows):
     return est / np.linalg.norm(B, axis=0)
 
 
-def test_mixed_workload_solves_with_int8_digit_products(ctx):
+@pytest.fixture
+def progress(capfd, monkeypatch):
+    """Long solves report every FP64 true residual on stderr (PKM_VERBOSE);
+    the context manager returned lets those reports through pytest's capture
+    while the test body runs, so that a solve of minutes is visibly alive."""
+    monkeypatch.setenv("PKM_VERBOSE", "1")
+    return capfd.disabled
+
+
+def test_mixed_workload_solves_with_int8_digit_products(ctx, progress):
     """n = 262,144, d = 16, lambda = 1e-4, k = 1 + 32, Nystrom m = 1024: the
     int8-digit product certifies every column at 1e-6 without escalating;
     the oracle's sampled residual agrees (within the sampling spread)."""
@@ -33,8 +42,9 @@ def test_mixed_workload_solves_with_int8_digit_products(ctx):
     g = GpuProblem(p)
     pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, len(p.idx), idx=g.idx, jitter=1e-8)
     try:
-        X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc,
-                               opts=pk.make_opts(tol=1e-6, prec=pk.PKM_I8X, reliable_every=-50))
+        with progress():
+            X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc,
+                                   opts=pk.make_opts(tol=1e-6, prec=pk.PKM_I8X, reliable_every=-50))
     finally:
         pk.pkm_precond_destroy(pc)
     print(f"mixed workload, int8-digit products: {info.total_iters} steps, "
@@ -48,7 +58,7 @@ def test_mixed_workload_solves_with_int8_digit_products(ctx):
     assert np.all(est <= 3e-6), est
 
 
-def test_learned_workload_first_theta_at_full_size(ctx):
+def test_learned_workload_first_theta_at_full_size(ctx, progress):
     """n = 131,072, d = 8, lambda = 1e-4, k = 1 + 16: the learned correction
     (Nystrom m = 512 plus a 128-column network factor trained on probe pairs
     (Z, (K - Q) Z)) and plain Nystrom m = 512 on the same inducing points,
@@ -71,7 +81,8 @@ def test_learned_workload_first_theta_at_full_size(ctx):
         pcs.append(pk.pkm_precond_setup_hybrid(ctx, g.prob, 512, g.idx, U, jitter=1e-8))
         res = []
         for pc in pcs:
-            X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc, opts=opts)
+            with progress():
+                X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc, opts=opts)
             res.append((host(X), info))
     finally:
         for pc in pcs:
