@@ -179,6 +179,19 @@ const char* pkm_version(void);
  * Y may not alias V.                                                         */
 int pkm_kernel_mvm(pkm_ctx* ctx, const pkm_problem* prob, int32_t k,
                    int32_t prec, const double* V, double* Y);
+/* Y = (K + lambda I) V like pkm_kernel_mvm, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the call allocates nothing.  prec must be
+ * PKM_I8X (else PKM_ERR_UNSUPPORTED); results equal pkm_kernel_mvm's with
+ * PKM_I8X bit for bit.  All scratch (prepared operands, packed V digits,
+ * partial sums) lives in one static device array of 128 MiB per device,
+ * reserved when the library loads and held until the process ends; its
+ * address is looked up by pkm_create.  A problem whose scratch exceeds it is
+ * rejected with PKM_ERR_INVALID before any launch (about n <= 65536 at
+ * d <= 16, k <= 33).  Every call on a device shares the array: calls that
+ * overlap on one device (several streams or contexts) race.               */
+int pkm_kernel_mvm_noalloc(pkm_ctx* ctx, const pkm_problem* prob, int32_t k,
+                           int32_t prec, const double* V, double* Y);
 /* Y = (K + shift I) V with any shift >= 0 (shift = 0: the plain K V, e.g.
  * the probe pairs (Z, K Z) that train the learned factor).                 */
 int pkm_kernel_mvm_shift(pkm_ctx* ctx, const pkm_problem* prob, int32_t k,

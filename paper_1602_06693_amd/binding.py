@@ -46,7 +46,7 @@ PKM_COL_BREAKDOWN = 2
 # every symbol include/pkm.h declares
 EXPORTS = (
     "pkm_create", "pkm_destroy", "pkm_last_error", "pkm_version", "pkm_kernel_mvm",
-    "pkm_kernel_mvm_shift",
+    "pkm_kernel_mvm_shift", "pkm_kernel_mvm_noalloc",
     "pkm_precond_setup", "pkm_precond_setup_pitc",
     "pkm_precond_setup_hybrid", "pkm_precond_setup_spectral", "pkm_precond_sub_lowrank",
     "pkm_precond_apply", "pkm_precond_diag", "pkm_precond_destroy",
@@ -146,6 +146,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "pkm_mlp_train_step": (C.c_int, [vp, vp, P(pkm_problem), i32, vp, vp, dbl, P(dbl)]),
         "pkm_adagrad_step": (C.c_int, [i32, P(dbl), P(dbl), P(dbl), dbl, dbl]),
         "pkm_tune_cache_load": (C.c_int, [C.c_char_p, P(i32), P(i32)]),
+        "pkm_kernel_mvm_noalloc": (C.c_int, [vp, P(pkm_problem), i32, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -528,6 +529,13 @@ def pkm_adagrad_step(theta, g, G, eta=1.0, eps=1e-8):
                                    g.ctypes.data_as(P), G.ctypes.data_as(P), float(eta),
                                    float(eps)))
     return theta
+
+
+def pkm_kernel_mvm_noalloc(ctx, prob: Problem, V, Y, prec=PKM_I8X):
+    """Y = (K + lambda I) V into the caller's Y without any device allocation."""
+    k = V.shape[1] if V.dim() == 2 else 1
+    _check(load().pkm_kernel_mvm_noalloc(ctx, prob.ref, k, prec, _ptr(V), _ptr(Y)), ctx)
+    return Y
 
 
 def pkm_tune_cache_load(path):

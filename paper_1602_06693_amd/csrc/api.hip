@@ -111,6 +111,7 @@ int pkm_create(pkm_ctx** out, int device, void* stream) {
         PKM_HIP(hipGetDeviceCount(&count));
         PKM_REQUIRE(device >= 0 && device < count, "device index out of range");
         PKM_HIP(hipSetDevice(device));
+        noalloc_init(device);   // per-device address of the allocation-free scratch
         ctx = new pkm_ctx();
         ctx->device = device;
         ctx->stream = static_cast<hipStream_t>(stream);
@@ -178,6 +179,23 @@ int pkm_kernel_mvm(pkm_ctx* ctx, const pkm_problem* prob, int32_t k, int32_t pre
         PKM_REQUIRE(V != Y, "Y may not alias V");
         prepare(ctx, prob, prec == PKM_FP64, prec != PKM_FP64 && prec != PKM_I8X);
         mvm(ctx, prec, k, V, Y);
+        return PKM_OK;
+    });
+}
+
+int pkm_kernel_mvm_noalloc(pkm_ctx* ctx, const pkm_problem* prob, int32_t k, int32_t prec,
+                           const double* V, double* Y) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        validate_problem(prob);
+        PKM_REQUIRE(k >= 1 && k <= 4096, "k must be in [1, 4096]");
+        if (prec != PKM_I8X)
+            fail(PKM_ERR_UNSUPPORTED, "pkm_kernel_mvm_noalloc supports PKM_I8X only");
+        check_prec(prec, prob->d);
+        require_dev(V, "V");
+        require_dev(Y, "Y");
+        PKM_REQUIRE(V != Y, "Y may not alias V");
+        mvm_i8_noalloc(ctx, prob, k, V, Y, prob->lambda);
         return PKM_OK;
     });
 }

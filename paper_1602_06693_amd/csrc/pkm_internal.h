@@ -270,6 +270,12 @@ void prepare_bf16(pkm_ctx* ctx);
 // FP64-class product on int8 matrix cores (prec PKM_I8X): Y = (K + shift I) V
 // for row-major n x k FP64 blocks (leading dimensions ldv, ldy).
 void mvm_i8(pkm_ctx* ctx, int k, const double* V, int ldv, double* Y, int ldy, double shift);
+// Allocation-free PKM_I8X product (noalloc.hip): scratch in a static device
+// array whose per-device address noalloc_init looks up (device current).
+void noalloc_init(int device);
+size_t noalloc_capacity();
+void mvm_i8_noalloc(pkm_ctx* ctx, const pkm_problem* prob, int k, const double* V, double* Y,
+                    double shift);
 
 // ---- PCG (pcg.hip): K_y X = B, or B_laplace X = B when wscale (W^1/2) is given
 int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, const double* B,
