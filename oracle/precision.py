@@ -45,6 +45,19 @@ Functions:
   int8_truncation_bound(...)      largest per-term error of the dropped pairs
   refinement_factor(apply, ...)   |E(d)| / |r| for d = A^-1 r: the contraction
                                   one refinement step achieves on residual r
+  woodbury_psi(D, Phi)            Psi of P^-1 = D^-1 - Psi Psi^T, P = D + Phi Phi^T
+  woodbury_apply(D, Psi, R, ...)  D^-1 R - Psi~ (Psi~^T R), Psi~ = Psi or its
+                                  FP32 rounding (the stored-FP32 apply)
+  psi_rounding_bound(Psi, R)      entrywise bound on what the rounding changes
+
+  * ``stored-FP32 Psi``: the Woodbury apply (Section 3.2's matrix inversion
+    lemma written as P^-1 = D^-1 - Psi Psi^T) with Psi rounded once to FP32
+    and everything else FP64.  Since Psi~ = Psi (1 + delta), |delta| <= u =
+    2^-24 entrywise, (Psi~ Psi~^T - Psi Psi^T)_ij = sum_a Psi_ia Psi_ja
+    (delta_ia + delta_ja + delta_ia delta_ja): the operator stays symmetric,
+    and it moves by at most (2u + u^2) |Psi| |Psi|^T entrywise.  It is a
+    different preconditioner, not a product error: PCG stays exact in FP64
+    around it, only its step count can change.
 """
 from __future__ import annotations
 
@@ -58,7 +71,8 @@ from .mlp import round_bf16
 __all__ = ["round_fp32", "round_bf16", "round_fp16", "split_fp16", "perturbed_kernel",
            "rho", "refine",
            "fp32_solution_residual", "augmented_fp32_kernel", "signed_digits",
-           "int8_digit_product", "int8_truncation_bound", "refinement_factor"]
+           "int8_digit_product", "int8_truncation_bound", "refinement_factor",
+           "woodbury_psi", "woodbury_apply", "psi_rounding_bound"]
 
 
 def round_fp32(a):
@@ -242,3 +256,33 @@ def refinement_factor(apply, K, lam, R):
     D = np.linalg.solve(A, R)
     E = apply(D) - A @ D
     return np.linalg.norm(E, axis=0) / np.linalg.norm(R, axis=0)
+
+
+def woodbury_psi(D, Phi):
+    """Psi with P^-1 = D^-1 - Psi Psi^T for P = diag(D) + Phi Phi^T (the
+    matrix inversion lemma, Section 3.2): C = I + Phi^T D^-1 Phi = L L^T
+    (Cholesky), Psi = D^-1 Phi L^-T."""
+    D = np.asarray(D, dtype=np.float64)
+    Phi = np.asarray(Phi, dtype=np.float64)
+    DPhi = Phi / D[:, None]
+    C = np.eye(Phi.shape[1]) + Phi.T @ DPhi
+    L = np.linalg.cholesky(C)
+    return np.linalg.solve(L, DPhi.T).T          # D^-1 Phi L^-T
+
+
+def woodbury_apply(D, Psi, R, round_psi=False):
+    """D^-1 R - Psi~ (Psi~^T R), Psi~ = round_fp32(Psi) when round_psi (the
+    apply from Psi stored in FP32), else Psi; FP64 arithmetic throughout."""
+    D = np.asarray(D, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    P = round_fp32(Psi) if round_psi else np.asarray(Psi, dtype=np.float64)
+    return R / D[:, None] - P @ (P.T @ R)
+
+
+def psi_rounding_bound(Psi, R):
+    """Entrywise bound on |apply(Psi~) - apply(Psi)| for R, from
+    |Psi~ Psi~^T - Psi Psi^T| <= (2u + u^2) |Psi| |Psi|^T, u = 2^-24 (exact
+    arithmetic; the FP64 sums add ~1e-16 relative on top)."""
+    u = 2.0 ** -24
+    A = np.abs(np.asarray(Psi, dtype=np.float64))
+    return (2 * u + u * u) * (A @ (A.T @ np.abs(np.asarray(R, dtype=np.float64))))

@@ -253,3 +253,88 @@ def test_int8_model_error_against_exact_product():
     got3 = pr.int8_digit_product(X, 1.7, ls, V, shift=1e-4, min_class=3, K=K)
     err3 = np.linalg.norm(got3 - exact, axis=0) / np.linalg.norm(exact, axis=0)
     assert np.all(err3 > 2 * err), (err3, err)
+
+
+# ---- stored-FP32 Psi in the Woodbury apply ----------------------------------
+
+def _nystrom_factor(X, sigma2, ls, idx, jitter=1e-8):
+    """Phi = K_XU L^-T with K_UU + jitter I = L L^T (so Phi Phi^T = Q)."""
+    from oracle.kernel import rbf_block
+    Xu = X[idx]
+    L = np.linalg.cholesky(rbf_block(Xu, Xu, sigma2, ls) + jitter * np.eye(len(idx)))
+    return np.linalg.solve(L, rbf_block(X, Xu, sigma2, ls).T).T
+
+
+def _c2_like(seed, n=900, d=8, m=64, lam=1e-3):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, d))
+    ls = np.full(d, 1.5)
+    idx = np.sort(rng.choice(n, size=m, replace=False))
+    return X, 1.0, ls, lam, _nystrom_factor(X, 1.0, ls, idx)
+
+
+def test_woodbury_psi_apply_is_the_dense_inverse():
+    """D^-1 - Psi Psi^T from woodbury_psi is (diag(D) + Phi Phi^T)^-1 itself
+    (brute force: a dense solve), for a FITC-like varying D."""
+    rng = np.random.default_rng(3)
+    n, m = 300, 20
+    Phi = rng.standard_normal((n, m)) * 0.7
+    D = 1e-2 + rng.random(n)
+    R = rng.standard_normal((n, 5))
+    Psi = pr.woodbury_psi(D, Phi)
+    want = np.linalg.solve(np.diag(D) + Phi @ Phi.T, R)
+    got = pr.woodbury_apply(D, Psi, R)
+    assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want))
+
+
+def test_fp32_psi_apply_is_symmetric_and_within_its_bound():
+    """The stored-FP32 apply of a C2-like Nystrom preconditioner (lambda =
+    1e-3): symmetric as an operator (both factors rounded alike), changed by
+    no more than the entrywise bound, and changed (the rounding bites at a
+    visible fraction of the bound)."""
+    X, s2, ls, lam, Phi = _c2_like(5)
+    n = X.shape[0]
+    D = np.full(n, lam)
+    Psi = pr.woodbury_psi(D, Phi)
+    R = np.random.default_rng(6).standard_normal((n, 7))
+    z64 = pr.woodbury_apply(D, Psi, R)
+    z32 = pr.woodbury_apply(D, Psi, R, round_psi=True)
+    bound = pr.psi_rounding_bound(Psi, R)
+    slack = 1e-13 * (np.abs(R) / lam + np.abs(Psi) @ (np.abs(Psi).T @ np.abs(R)))
+    dev = np.abs(z32 - z64)
+    assert np.all(dev <= bound + slack)
+    assert dev.max() >= 1e-3 * bound.max()
+    E = np.eye(n)
+    M = pr.woodbury_apply(D, Psi, E, round_psi=True)
+    assert np.max(np.abs(M - M.T)) <= 1e-12 * np.max(np.abs(M))
+
+
+@pytest.mark.parametrize("lam,changes", [(1e-2, False), (1e-3, True)])
+def test_fp32_psi_step_effect_follows_its_perturbation(lam, changes):
+    """PCG (oracle, FP64) to 1e-6 on a 900-point system with the exact and the
+    stored-FP32 Nystrom apply (m = 64).  The rounding moves the preconditioned
+    operator by at most eta = (2u + u^2) || |Psi| ||^2 ||K_y|| (from the
+    entrywise bound); where eta is small (lambda = 1e-2) the step counts agree
+    within 10 % + 2, where it is not (lambda = 1e-3: Psi grows like
+    lambda^-1/2) the rounded preconditioner costs more than 10 % more steps.
+    Either way it stays positive definite and PCG converges."""
+    from oracle.pcg import pcg
+    X, s2, ls, _, Phi = _c2_like(7)
+    n = X.shape[0]
+    K = kernel_matrix(X, s2, ls) + lam * np.eye(n)
+    D = np.full(n, lam)
+    Psi = pr.woodbury_psi(D, Phi)
+    u = 2.0 ** -24
+    eta = (2 * u + u * u) * np.linalg.norm(np.abs(Psi), 2) ** 2 * np.linalg.norm(K, 2)
+    B = np.random.default_rng(8).standard_normal((n, 4))
+    r64 = pcg(lambda V: K @ V, B, precond=lambda R: pr.woodbury_apply(D, Psi, R), tol=1e-6)
+    r32 = pcg(lambda V: K @ V, B, precond=lambda R: pr.woodbury_apply(D, Psi, R, round_psi=True),
+              tol=1e-6)
+    Pinv32 = pr.woodbury_apply(D, Psi, np.eye(n), round_psi=True)
+    assert np.linalg.eigvalsh(0.5 * (Pinv32 + Pinv32.T)).min() > 0
+    assert np.all(r32.relres <= 1e-6) and np.all(r64.relres <= 1e-6)
+    i32, i64 = int(r32.iters.max()), int(r64.iters.max())
+    if changes:
+        assert eta > 0.1 and i32 > 1.1 * i64, (eta, i32, i64)
+    else:
+        assert eta < 0.05 and abs(i32 - i64) <= 0.1 * i64 + 2, (eta, i32, i64)
