@@ -257,21 +257,33 @@ def hyper_mode(pk, ctx, p, a):
     m = len(p.idx)
     learned = hyper.LearnedArm(ctx, mlp_params(a.seed, d_in=p.d, rank=a.rank, out_scale=0.1),
                                p.d, a.rank, p.n, m, seed=a.seed, log=log)
-    # control: as many extra random inducing points as the learned columns
-    arms = [hyper.NystromArm(p.n, m, seed=a.seed), learned,
-            hyper.NystromArm(p.n, m + a.rank, seed=a.seed, name=f"nystrom_m{m + a.rank}")]
+    arms = [hyper.NystromArm(p.n, m, seed=a.seed), learned]
+    if not a.no_control:   # as many extra random inducing points as the learned columns
+        arms.append(hyper.NystromArm(p.n, m + a.rank, seed=a.seed, name=f"nystrom_m{m + a.rank}"))
+    if a.lowrank_arm:   # the plain factor form P = U U^T + lambda I, capped solves
+        arms.append(hyper.LowRankArm(
+            ctx, mlp_params(a.seed, d_in=p.d, rank=a.rank, out_scale=0.1), p.d, a.rank, p.n,
+            seed=a.seed, log=log,
+            opts=pk.make_opts(tol=p.tol, prec=precs[a.prec], reliable_every=a.reliable,
+                              max_iter=a.lowrank_max_iter)))
     t0 = time.perf_counter()
     try:
         traj, rec = hyper.run(ctx, dev(p.X), dev(p.y), dev(p.Z), theta0, p.lam, arms,
-                              a.hyper_steps, eta=1.0, opts=opts, log=log)
+                              a.hyper_steps, eta=1.0, opts=opts, log=log,
+                              checkpoint=a.checkpoint, max_wall_s=a.max_wall)
     finally:
         learned.close()
+        if a.lowrank_arm:
+            arms[-1].close()
     wall = time.perf_counter() - t0
     out = {"mode": "hyper", "workload": p.name, "n": p.n, "d": p.d, "k": 1 + p.Z.shape[1],
-           "lambda": p.lam, "steps": a.hyper_steps, "product": a.prec, "wall_s": wall,
+           "lambda": p.lam, "steps": a.hyper_steps, "steps_done": len(traj) - 1,
+           "product": a.prec, "wall_s_this_call": wall,
            "theta_final": [float(v) for v in traj[-1]], "learned_rank": a.rank,
            "nystrom_m": len(p.idx), "mlp_train_s": learned.train_s,
-           "mlp_loss_first_last": [learned.losses[0], learned.losses[-1]]}
+           "mlp_loss_first_last": [learned.losses[0], learned.losses[-1]],
+           "learned_fallbacks": learned.fallbacks,
+           "theta_trajectory": [[float(v) for v in th] for th in traj]}
     for name, rs in rec.items():
         out[name] = {"iters": [r["iters"] for r in rs],
                      "solve_grad_s": sum(r["solve_grad_s"] for r in rs),
@@ -444,6 +456,19 @@ def main():
     ap.add_argument("--hyper-steps", type=int, default=20)
     ap.add_argument("--n", type=int, default=None, help="override the workload's n")
     ap.add_argument("--rank", type=int, default=128)
+    ap.add_argument("--lowrank-arm", action="store_true",
+                    help="hyper mode: also solve with P = U U^T + lambda I from the network "
+                         "trained on (Z, K Z)")
+    ap.add_argument("--lowrank-max-iter", type=int, default=15000)
+    ap.add_argument("--psi32", action="store_true",
+                    help="step mode: the first arm applies the preconditioner from Psi rounded "
+                         "to FP32 (pkm_precond_psi_f32)")
+    ap.add_argument("--no-control", action="store_true",
+                    help="hyper mode: leave out the Nystrom m + rank control arm")
+    ap.add_argument("--checkpoint", default=None,
+                    help="hyper mode: .npz written after every step; resumed from if present")
+    ap.add_argument("--max-wall", type=float, default=None,
+                    help="hyper mode: stop after the first step ending past this many seconds")
     ap.add_argument("--count", type=int, default=64, help="batched mode: number of problems")
     ap.add_argument("--mode", choices=("step", "mvm", "hyper", "batched", "laplace"),
                     default="step",
@@ -494,13 +519,15 @@ def main():
     precs = {"fp64": pk.PKM_FP64, "fp32": pk.PKM_FP32, "bf16x1": pk.PKM_BF16X1,
              "bf16x3": pk.PKM_BF16X3, "f16x3": pk.PKM_F16X3, "i8x": pk.PKM_I8X}
 
-    def run_variant(prec, steps, warmup, label, kind=None):
+    def run_variant(prec, steps, warmup, label, kind=None, psi32=False):
         opts = pk.make_opts(tol=p.tol, prec=prec, reliable_every=a.reliable)
         kind = pk.PKM_PC_NYSTROM if kind is None else kind
 
         def step():
             pc = pk.pkm_precond_setup(ctx, prob, kind, m, idx=idx, jitter=1e-8)
             try:
+                if psi32:
+                    pk.pkm_precond_psi_f32(ctx, pc, True)
                 return pk.pkm_lml_grad(ctx, prob, y, Z, pc=pc, opts=opts, sol=sol)
             finally:
                 pk.pkm_precond_destroy(pc)
@@ -540,7 +567,8 @@ def main():
                 "fp64_ms": st64["ms"] / max(st64["launches"], 1),
                 "fp64_launches": st64["launches"] // max(steps, 1)}
 
-    mixed = run_variant(precs[a.prec], a.steps, a.warmup, a.prec)
+    mixed = run_variant(precs[a.prec], a.steps, a.warmup, a.prec + ("+psi32" if a.psi32 else ""),
+                        psi32=a.psi32)
     plain = None
     if a.plain != "none" and a.plain != a.prec:
         plain = run_variant(precs[a.plain], a.steps, a.warmup, a.plain)
@@ -581,6 +609,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": _describe(p, m, a.prec, a.reliable), "n": p.n, "d": p.d,
                    "k": 1 + N, "m": m, "preconditioner": "nystrom", "product": a.prec,
+                   "psi_storage": "fp32" if a.psi32 else "fp64",
                    "parallelism": "single GPU"},
         "iters": int(info.total_iters),
         "true_residual_products": int(info.true_residuals),

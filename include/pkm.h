@@ -250,6 +250,21 @@ int pkm_precond_setup_spectral(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
                                const double* W, pkm_precond** out);
 int pkm_precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int32_t k,
                       const double* R, double* Z);
+/* Storage of Psi in the apply Z = D^-1 R - Psi (Psi^T R) (the matrix
+ * inversion lemma of Section 3.2).  on = 1 rounds Psi to FP32 once (round to
+ * nearest) and every later pkm_precond_apply and single-problem solve reads
+ * that copy, widening each entry to FP64 before FP64 matrix-core sums: the
+ * apply is then exactly that of the symmetric operator D^-1 - Psi~ Psi~^T
+ * (Psi~ the rounded copy), at half the bytes of Psi read per apply;
+ * |Psi~ Psi~^T - Psi Psi^T| <= (2u + u^2) |Psi| |Psi|^T entrywise, u = 2^-24.
+ * on = 0 frees the copy and goes back to Psi.  The batched solver reads the
+ * FP64 Psi either way.  The rounding changes the preconditioned operator by
+ * up to eta = (2u + u^2) || |Psi| ||^2 ||K + lambda I||, and Psi grows like
+ * lambda^-1/2: worth it only while eta << 1 (lambda >= 1e-2 for unit-variance
+ * kernels; at lambda = 1e-3 the extra PCG steps outweigh the halved bytes).
+ * PKM_ERR_INVALID for another on, or a preconditioner created on another
+ * device.                                                                   */
+int pkm_precond_psi_f32(pkm_ctx* ctx, pkm_precond* pc, int32_t on);
 /* Host copy of the preconditioner's diagonal part D (n values).           */
 int pkm_precond_diag(pkm_ctx* ctx, const pkm_precond* pc, double* D_host);
 int pkm_precond_destroy(pkm_precond* pc);
@@ -414,6 +429,16 @@ int pkm_mlp_create(pkm_ctx* ctx, int32_t d_in, int32_t hidden, int32_t rank,
 int pkm_mlp_destroy(pkm_mlp* net);
 /* Host copy of the FP32 master weights (same layout as params).             */
 int pkm_mlp_params(pkm_ctx* ctx, const pkm_mlp* net, float* params);
+/* Training state for checkpoints.  pkm_mlp_nparams reports the parameter
+ * count P (no device work).  state (host, 3 P FP32) holds the master
+ * weights, Adam's first moments and Adam's second moments, each in params
+ * layout, one after the other; t is Adam's step count (bias corrections).
+ * pkm_mlp_state_set restores both (t >= 0, every value finite, else
+ * PKM_ERR_INVALID and the network is unchanged) and refreshes the BF16
+ * copies, so that training continues as if never interrupted.             */
+int pkm_mlp_nparams(const pkm_mlp* net, int64_t* nparams);
+int pkm_mlp_state_get(pkm_ctx* ctx, const pkm_mlp* net, float* state, int64_t* t);
+int pkm_mlp_state_set(pkm_ctx* ctx, pkm_mlp* net, const float* state, int64_t t);
 /* U = net(X / l) for the problem's inputs (prob->d == d_in); U device
  * n x rank FP64, ready for pkm_precond_setup(PKM_PC_LOWRANK).               */
 int pkm_mlp_forward(pkm_ctx* ctx, pkm_mlp* net, const pkm_problem* prob, double* U);

@@ -54,6 +54,7 @@ EXPORTS = (
     "pkm_laplace_mode", "pkm_laplace_grad", "pkm_laplace_predict", "pkm_grad_pass", "pkm_lml_grad", "pkm_timing_enable", "pkm_mvm_stats",
     "pkm_mvm_stats_reset", "pkm_mlp_create", "pkm_mlp_destroy", "pkm_mlp_params",
     "pkm_mlp_forward", "pkm_mlp_loss_grad", "pkm_mlp_train_step", "pkm_adagrad_step",
+    "pkm_mlp_nparams", "pkm_mlp_state_get", "pkm_mlp_state_set", "pkm_precond_psi_f32",
     "pkm_tune_cache_load",
 )
 
@@ -118,6 +119,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "pkm_precond_apply": (C.c_int, [vp, vp, i32, vp, vp]),
         "pkm_precond_diag": (C.c_int, [vp, vp, P(dbl)]),
         "pkm_precond_destroy": (C.c_int, [vp]),
+        "pkm_precond_psi_f32": (C.c_int, [vp, vp, i32]),
         "pkm_solve": (C.c_int, [vp, P(pkm_problem), vp, i32, vp, vp, P(pkm_solve_opts),
                                 P(pkm_solve_info)]),
         "pkm_solve_batched": (C.c_int, [vp, i32, P(pkm_problem), P(vp), i32, P(vp), P(vp),
@@ -144,6 +146,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "pkm_mlp_loss_grad": (C.c_int, [vp, vp, P(pkm_problem), i32, vp, vp, P(dbl),
                                         P(C.c_float)]),
         "pkm_mlp_train_step": (C.c_int, [vp, vp, P(pkm_problem), i32, vp, vp, dbl, P(dbl)]),
+        "pkm_mlp_nparams": (C.c_int, [vp, P(i64)]),
+        "pkm_mlp_state_get": (C.c_int, [vp, vp, P(C.c_float), P(i64)]),
+        "pkm_mlp_state_set": (C.c_int, [vp, vp, P(C.c_float), i64]),
         "pkm_adagrad_step": (C.c_int, [i32, P(dbl), P(dbl), P(dbl), dbl, dbl]),
         "pkm_tune_cache_load": (C.c_int, [C.c_char_p, P(i32), P(i32)]),
         "pkm_kernel_mvm_noalloc": (C.c_int, [vp, P(pkm_problem), i32, i32, vp, vp]),
@@ -292,6 +297,10 @@ def pkm_precond_diag(ctx, pc, n):
     D = np.empty(n)
     _check(load().pkm_precond_diag(ctx, pc, D.ctypes.data_as(C.POINTER(C.c_double))), ctx)
     return D
+
+
+def pkm_precond_psi_f32(ctx, pc, on=True):
+    _check(load().pkm_precond_psi_f32(ctx, pc, 1 if on else 0), ctx)
 
 
 def pkm_precond_destroy(pc):
@@ -493,6 +502,29 @@ def pkm_mlp_params(ctx, net, d_in, hidden, rank):
     flat = np.zeros(n, np.float32)
     _check(load().pkm_mlp_params(ctx, net, flat.ctypes.data_as(C.POINTER(C.c_float))), ctx)
     return mlp_unflatten(flat, d_in, hidden, rank)
+
+
+def pkm_mlp_nparams(net):
+    n = C.c_int64()
+    _check(load().pkm_mlp_nparams(net, C.byref(n)))
+    return n.value
+
+
+def pkm_mlp_state_get(ctx, net):
+    """(state, t): FP32 [weights | Adam m | Adam v] and Adam's step count."""
+    state = np.zeros(3 * pkm_mlp_nparams(net), np.float32)
+    t = C.c_int64()
+    _check(load().pkm_mlp_state_get(ctx, net, state.ctypes.data_as(C.POINTER(C.c_float)),
+                                    C.byref(t)), ctx)
+    return state, t.value
+
+
+def pkm_mlp_state_set(ctx, net, state, t):
+    state = np.ascontiguousarray(np.asarray(state, dtype=np.float32))
+    if state.size != 3 * pkm_mlp_nparams(net):
+        raise ValueError("state must hold 3 x nparams values")
+    _check(load().pkm_mlp_state_set(ctx, net, state.ctypes.data_as(C.POINTER(C.c_float)),
+                                    int(t)), ctx)
 
 
 def pkm_mlp_forward(ctx, net, prob: Problem, rank, U=None):

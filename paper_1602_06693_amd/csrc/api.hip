@@ -12,6 +12,7 @@ namespace pkm {
 void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const int32_t* idx,
                    const double* Phi, double jitter, pkm_precond* pc, int aux);
 void precond_sub_lowrank(pkm_ctx* ctx, const pkm_precond* pc, int k, const double* V, double* Y);
+void precond_psi_f32(pkm_ctx* ctx, pkm_precond* pc, bool on);
 int laplace_mode(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* base, const double* y,
                  const pkm_solve_opts* o, int max_newton, double tol, double* f, double* a,
                  pkm_laplace_info* info);
@@ -42,6 +43,8 @@ int64_t mlp_nparams(const pkm_mlp* net);
 float* mlp_grad_ptr(pkm_mlp* net);
 const float* mlp_param_ptr(const pkm_mlp* net);
 int mlp_d_in(const pkm_mlp* net);
+void mlp_state_get(pkm_ctx* ctx, const pkm_mlp* net, float* state, int64_t* t);
+void mlp_state_set(pkm_ctx* ctx, pkm_mlp* net, const float* state, int64_t t);
 }  // namespace pkm
 
 using namespace pkm;
@@ -471,11 +474,23 @@ int pkm_precond_diag(pkm_ctx* ctx, const pkm_precond* pc, double* D_host) {
     });
 }
 
+int pkm_precond_psi_f32(pkm_ctx* ctx, pkm_precond* pc, int32_t on) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        PKM_REQUIRE(pc != nullptr, "NULL argument");
+        PKM_REQUIRE(pc->device == ctx->device, "preconditioner on another device");
+        PKM_REQUIRE(on == 0 || on == 1, "on must be 0 or 1");
+        precond_psi_f32(ctx, pc, on == 1);
+        return PKM_OK;
+    });
+}
+
 int pkm_precond_destroy(pkm_precond* pc) {
     if (!pc) return PKM_OK;
     (void)hipSetDevice(pc->device);
     (void)hipDeviceSynchronize();
     pc->psi.release();
+    pc->psi32.release();
     pc->dinv.release();
     pc->dblk.release();
     pc->phi.release();
@@ -658,6 +673,35 @@ int pkm_mlp_params(pkm_ctx* ctx, const pkm_mlp* net, float* params) {
         PKM_HIP(hipMemcpyAsync(params, mlp_param_ptr(net), sizeof(float) * mlp_nparams(net),
                                hipMemcpyDeviceToHost, ctx->stream));
         PKM_HIP(hipStreamSynchronize(ctx->stream));
+        return PKM_OK;
+    });
+}
+
+int pkm_mlp_nparams(const pkm_mlp* net, int64_t* nparams) {
+    if (!net || !nparams) return PKM_ERR_INVALID;
+    *nparams = mlp_nparams(net);
+    return PKM_OK;
+}
+
+int pkm_mlp_state_get(pkm_ctx* ctx, const pkm_mlp* net, float* state, int64_t* t) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        PKM_REQUIRE(net != nullptr && state != nullptr && t != nullptr, "NULL argument");
+        PKM_REQUIRE(net->device == ctx->device, "network on another device");
+        mlp_state_get(ctx, net, state, t);
+        return PKM_OK;
+    });
+}
+
+int pkm_mlp_state_set(pkm_ctx* ctx, pkm_mlp* net, const float* state, int64_t t) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        PKM_REQUIRE(net != nullptr && state != nullptr, "NULL argument");
+        PKM_REQUIRE(net->device == ctx->device, "network on another device");
+        PKM_REQUIRE(t >= 0, "Adam step count must be >= 0");
+        for (int64_t i = 0; i < 3 * mlp_nparams(net); ++i)
+            PKM_REQUIRE(std::isfinite(state[i]), "state holds a non-finite value");
+        mlp_state_set(ctx, net, state, t);
         return PKM_OK;
     });
 }

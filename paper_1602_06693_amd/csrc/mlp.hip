@@ -487,6 +487,29 @@ double mlp_train_step(pkm_ctx* ctx, pkm_mlp* net, int64_t n, const double* xs, i
     return loss;
 }
 
+// Checkpoint state: master weights, Adam first and second moments (each
+// nparams FP32 in params layout, one after the other) and the Adam step count.
+void mlp_state_get(pkm_ctx* ctx, const pkm_mlp* net, float* state, int64_t* t) {
+    const size_t bytes = sizeof(float) * net->nparams;
+    const pkm::DevBuf* parts[3] = {&net->p32, &net->m32, &net->v32};
+    for (int i = 0; i < 3; ++i)
+        PKM_HIP(hipMemcpyAsync(state + i * net->nparams, parts[i]->p, bytes,
+                               hipMemcpyDeviceToHost, ctx->stream));
+    PKM_HIP(hipStreamSynchronize(ctx->stream));
+    *t = net->t;
+}
+
+void mlp_state_set(pkm_ctx* ctx, pkm_mlp* net, const float* state, int64_t t) {
+    const size_t bytes = sizeof(float) * net->nparams;
+    pkm::DevBuf* parts[3] = {&net->p32, &net->m32, &net->v32};
+    for (int i = 0; i < 3; ++i)
+        PKM_HIP(hipMemcpyAsync(parts[i]->p, state + i * net->nparams, bytes,
+                               hipMemcpyHostToDevice, ctx->stream));
+    net->t = t;
+    repack(ctx, net);
+    PKM_HIP(hipStreamSynchronize(ctx->stream));
+}
+
 int64_t mlp_nparams(const pkm_mlp* net) { return net->nparams; }
 float* mlp_grad_ptr(pkm_mlp* net) { return net->g32.as<float>(); }
 const float* mlp_param_ptr(const pkm_mlp* net) { return net->p32.as<float>(); }

@@ -108,6 +108,15 @@ constexpr double kRefineEta = 1e-3;
 // larger d takes the FP64 vector-ALU product on direct differences.
 constexpr int kAug64MaxD4 = 36;
 
+// 16-bit products: columns per pass (nine 16-column tiles; wider blocks go in
+// passes of this many), and the column-maxima slots of the FP16 scales.
+constexpr int kBf16MaxCols = 144;
+constexpr int kColmaxSlots = 256;
+// i-tiles of 16 rows per wave in the 16-bit product: four up to five column
+// tiles, two above (the accumulators of nine tiles at four i-tiles would
+// not fit the register file).
+constexpr int bf16_u(int kt) { return kt <= 5 ? 4 : 2; }
+
 // Grow-only device buffer.
 struct DevBuf {
     void* p = nullptr;
@@ -214,6 +223,8 @@ struct pkm_precond {
     int m = 0;
     int device = 0;
     pkm::DevBuf psi;    // n x m FP64: P^-1 = D^-1 - psi psi^T
+    pkm::DevBuf psi32;  // n x m FP32 rounding of psi, read by the apply when psi32_on
+    bool psi32_on = false;
     pkm::DevBuf dinv;   // n FP64: 1 / diag(D)
     int block = 0;      // PITC: block size b; dblk holds blockdiag(D^-1), n x b
     pkm::DevBuf dblk;

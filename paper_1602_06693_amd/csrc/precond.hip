@@ -503,6 +503,12 @@ constexpr int AT = 64;   // Psi columns per work-group (phase 1), rows (phase 2)
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// Psi is read as FP64 or as its FP32 rounding (pkm_precond_psi_f32); either
+// way every entry is widened to FP64 on load and the sums are FP64 MFMA.
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
 // Phase 1: part[chunk][j][c] = sum_{i in chunk} Psi[i][j] R[i][c] on 16x16x4
 // FP64 MFMA.  Wave w owns the 16 Psi columns j0 .. j0 + 15; lane l feeds
 // A[j0 + l % 16][i] = Psi[i][j0 + l % 16] and B[i][c] = R[i][c0 + 16 kt + l % 16]
@@ -516,8 +522,8 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // PAIR (JT = 2, m even): lane cc of the wave's two tiles takes the adjacent
 // Psi columns j0 + 2 cc and j0 + 2 cc + 1, one 16-byte load for both tiles;
 // output row rho of tile t is then column j0 + 2 rho + t.
-template <int KT, int JT, bool PAIR>
-__global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, int m,
+template <int KT, int JT, bool PAIR, typename PT>
+__global__ __launch_bounds__(256) void k_psit_r(const PT* __restrict__ psi, int m,
                                                 const double* __restrict__ R, int k, int c0,
                                                 int kc, int64_t n, int64_t rows_per_chunk,
                                                 double* __restrict__ part) {
@@ -550,12 +556,13 @@ __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, 
         for (int q = 0; q < 4; ++q) {
             const int64_t i = ib + 4 * g + q;
             if (PAIR) {
-                const double2 x = *reinterpret_cast<const double2*>(psi + i * m + jc[0]);
-                la[0][q] = x.x;
-                la[1][q] = x.y;
+                using P2 = typename Vec2<PT>::type;
+                const P2 x = *reinterpret_cast<const P2*>(psi + i * m + jc[0]);
+                la[0][q] = double(x.x);
+                la[1][q] = double(x.y);
             } else {
 #pragma unroll
-                for (int t = 0; t < JT; ++t) la[t][q] = psi[i * m + jc[t]];
+                for (int t = 0; t < JT; ++t) la[t][q] = double(psi[i * m + jc[t]]);
             }
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt) lb[q][kt] = R[i * k + col[kt]];
@@ -593,7 +600,7 @@ __global__ __launch_bounds__(256) void k_psit_r(const double* __restrict__ psi, 
             const int64_t i = ifull + 4 * g + q;
             const bool iv = i < i1;
 #pragma unroll
-            for (int t = 0; t < JT; ++t) a[t][q] = iv ? psi[i * m + jc[t]] : 0.0;
+            for (int t = 0; t < JT; ++t) a[t][q] = iv ? double(psi[i * m + jc[t]]) : 0.0;
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt) b[q][kt] = iv ? R[i * k + col[kt]] : 0.0;
         }
@@ -645,8 +652,8 @@ __global__ __launch_bounds__(256) void k_sum_chunks(const double* __restrict__ p
 // index q pairs with the matching rows of T.  Whole 16-column blocks load
 // without guards (a row past n reads row 0 and is never stored) and one
 // block ahead of their MFMAs; a ragged last block loads under guards.
-template <int KT, int U, bool VEC>
-__global__ __launch_bounds__(256) void k_apply_z(const double* __restrict__ psi, int m,
+template <int KT, int U, bool VEC, typename PT>
+__global__ __launch_bounds__(256) void k_apply_z(const PT* __restrict__ psi, int m,
                                                  const double* __restrict__ T, int ldt,
                                                  const double* __restrict__ dinv,
                                                  const double* __restrict__ R, int k, int c0,
@@ -655,7 +662,7 @@ __global__ __launch_bounds__(256) void k_apply_z(const double* __restrict__ psi,
     const int g = lane >> 4, rr = lane & 15;
     const int64_t row0 = (int64_t(blockIdx.x) * 4 + w) * 16 * U;
     if (row0 >= n) return;
-    const double* prow[U];
+    const PT* prow[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t row = row0 + 16 * u + rr;
@@ -685,16 +692,22 @@ __global__ __launch_bounds__(256) void k_apply_z(const double* __restrict__ psi,
     auto load = [&](int m0, double (&la)[U][4], double (&lt)[4][KT]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (VEC) {   // the lane's four consecutive entries as two 16-byte loads
+            if (VEC && sizeof(PT) == 8) {   // the lane's four entries: two 16-byte loads
                 const double2* p2 = reinterpret_cast<const double2*>(prow[u] + m0 + 4 * g);
                 const double2 x0 = p2[0], x1 = p2[1];
                 la[u][0] = x0.x;
                 la[u][1] = x0.y;
                 la[u][2] = x1.x;
                 la[u][3] = x1.y;
+            } else if (VEC) {               // FP32: one 16-byte load
+                const float4 x = *reinterpret_cast<const float4*>(prow[u] + m0 + 4 * g);
+                la[u][0] = double(x.x);
+                la[u][1] = double(x.y);
+                la[u][2] = double(x.z);
+                la[u][3] = double(x.w);
             } else {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) la[u][q] = prow[u][m0 + 4 * g + q];
+                for (int q = 0; q < 4; ++q) la[u][q] = double(prow[u][m0 + 4 * g + q]);
             }
         }
         load_t(m0, lt);
@@ -728,7 +741,7 @@ __global__ __launch_bounds__(256) void k_apply_z(const double* __restrict__ psi,
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int mm = mfull + 4 * g + q;
-                a[u][q] = mm < m ? prow[u][mm] : 0.0;
+                a[u][q] = mm < m ? double(prow[u][mm]) : 0.0;
             }
         load_t(mfull, t);
         step(a, t);
@@ -770,12 +783,21 @@ static void apply_chunk(pkm_ctx* ctx, const pkm_precond* pc, int k, int c0, cons
     // phase 1: each wave takes kPsitJT 16-column tiles of Psi, so the R rows
     // it loads serve kPsitJT MFMA tiles
     const dim3 grid1((unsigned)cdiv(m, AT * kPsitJT), (unsigned)nchunk);
-    if (kPsitJT == 2 && m % 2 == 0)   // rows 16-byte aligned: paired column loads
-        k_psit_r<KT, kPsitJT, true><<<grid1, 256, 0, s>>>(pc->psi.as<double>(), m, R, k, c0, kc, n,
-                                                           rpc, part);
-    else
-        k_psit_r<KT, kPsitJT, false><<<grid1, 256, 0, s>>>(pc->psi.as<double>(), m, R, k, c0, kc, n,
-                                                            rpc, part);
+    const bool p32 = pc->psi32_on;
+    const float* psi32 = pc->psi32.as<float>();
+    const double* psi64 = pc->psi.as<double>();
+    // m even: a lane's two adjacent Psi columns are one aligned 16- (8-) byte load
+    if (kPsitJT == 2 && m % 2 == 0) {
+        if (p32)
+            k_psit_r<KT, kPsitJT, true><<<grid1, 256, 0, s>>>(psi32, m, R, k, c0, kc, n, rpc, part);
+        else
+            k_psit_r<KT, kPsitJT, true><<<grid1, 256, 0, s>>>(psi64, m, R, k, c0, kc, n, rpc, part);
+    } else {
+        if (p32)
+            k_psit_r<KT, kPsitJT, false><<<grid1, 256, 0, s>>>(psi32, m, R, k, c0, kc, n, rpc, part);
+        else
+            k_psit_r<KT, kPsitJT, false><<<grid1, 256, 0, s>>>(psi64, m, R, k, c0, kc, n, rpc, part);
+    }
     PKM_CHECK_LAUNCH();
     k_sum_chunks<<<cdiv(int64_t(m_pad) * ldt, 64), 256, 0, s>>>(part, int(nchunk), m, k, c0, kc,
                                                                 m_pad, ldt, T);
@@ -783,14 +805,42 @@ static void apply_chunk(pkm_ctx* ctx, const pkm_precond* pc, int k, int c0, cons
     // PITC: Z already holds blockdiag(D^-1) R; the kernel subtracts Psi T
     const double* dv = pc->kind == PKM_PC_PITC ? nullptr : pc->dinv.as<double>();
     constexpr int U = KT >= 2 ? 2 : 1;
-    // Psi rows are 16-byte aligned when m is even: vector loads in phase 2
-    if (m % 2 == 0)
-        k_apply_z<KT, U, true><<<(unsigned)cdiv(n, 64 * U), 256, 0, s>>>(pc->psi.as<double>(), m, T,
-                                                                        ldt, dv, R, k, c0, n, Z);
-    else
-        k_apply_z<KT, U, false><<<(unsigned)cdiv(n, 64 * U), 256, 0, s>>>(pc->psi.as<double>(), m, T,
-                                                                         ldt, dv, R, k, c0, n, Z);
+    // Psi rows are 16-byte aligned when m is even (FP64) or a multiple of 4
+    // (FP32): vector loads in phase 2
+    const unsigned grid2 = (unsigned)cdiv(n, 64 * U);
+    if (p32) {
+        if (m % 4 == 0)
+            k_apply_z<KT, U, true><<<grid2, 256, 0, s>>>(psi32, m, T, ldt, dv, R, k, c0, n, Z);
+        else
+            k_apply_z<KT, U, false><<<grid2, 256, 0, s>>>(psi32, m, T, ldt, dv, R, k, c0, n, Z);
+    } else {
+        if (m % 2 == 0)
+            k_apply_z<KT, U, true><<<grid2, 256, 0, s>>>(psi64, m, T, ldt, dv, R, k, c0, n, Z);
+        else
+            k_apply_z<KT, U, false><<<grid2, 256, 0, s>>>(psi64, m, T, ldt, dv, R, k, c0, n, Z);
+    }
     PKM_CHECK_LAUNCH();
+}
+
+__global__ void k_round_f32(int64_t tot, const double* __restrict__ src, float* __restrict__ dst) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e < tot) dst[e] = float(src[e]);   // round to nearest even
+}
+
+// Apply from the FP32 rounding of Psi (on) or from Psi itself (off).
+void precond_psi_f32(pkm_ctx* ctx, pkm_precond* pc, bool on) {
+    if (!on) {
+        pc->psi32_on = false;
+        pc->psi32.release();
+        return;
+    }
+    const int64_t tot = pc->n * int64_t(pc->m);
+    pc->psi32.ensure(sizeof(float) * tot);
+    k_round_f32<<<cdiv(tot, 256), 256, 0, ctx->stream>>>(tot, pc->psi.as<double>(),
+                                                         pc->psi32.as<float>());
+    PKM_CHECK_LAUNCH();
+    PKM_HIP(hipStreamSynchronize(ctx->stream));
+    pc->psi32_on = true;
 }
 
 // Y <- Y - Phi Phi^T V (V, Y n x k; Phi the kept low-rank factor)

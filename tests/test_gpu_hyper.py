@@ -79,3 +79,46 @@ def test_learned_arm_falls_back_to_nystrom(ctx):
         learned.close()
     assert [r["iters"] for r in rec["learned"]] == [r["iters"] for r in rec["nystrom"]]
     assert all(r["converged"] for r in rec["learned"])
+
+
+def test_checkpoint_resume_matches_uninterrupted_run(ctx, tmp_path):
+    """Three ADAGRAD steps with the Nystrom, learned and low-rank arms, once
+    straight through and once as 1 step + (fresh arms, resumed from the
+    checkpoint) 2 steps: the same theta trajectory, PCG step counts and
+    network training losses, bit for bit (the solves are deterministic)."""
+    p = make("learned", seed=6, n=2000, n_probes=4)
+    d = p.d
+    theta0 = hyper.theta_of(1.0, p.lengthscales)
+    opts = pk.make_opts(tol=1e-6, prec=pk.PKM_FP32)
+
+    def arms_fresh():
+        return [hyper.NystromArm(p.n, 96, seed=8),
+                hyper.LearnedArm(ctx, mlp_params(3, d_in=d, rank=32), d, 32, p.n, 96,
+                                 n_train_probes=16, first_steps=20, steps_per_theta=5,
+                                 lr=3e-3, seed=8),
+                hyper.LowRankArm(ctx, mlp_params(4, d_in=d, rank=32), d, 32, p.n,
+                                 n_train_probes=16, first_steps=20, steps_per_theta=5,
+                                 lr=3e-3, seed=8, opts=pk.make_opts(tol=1e-6, prec=pk.PKM_FP32,
+                                                                   max_iter=3000))]
+
+    def go(arms, steps, ckpt=None, max_wall=None):
+        try:
+            traj, rec = hyper.run(ctx, dev(p.X), dev(p.y), dev(p.Z), theta0, p.lam, arms,
+                                  steps, eta=0.1, opts=opts, checkpoint=ckpt,
+                                  max_wall_s=max_wall)
+            return traj, rec, [list(a.losses) for a in arms[1:]]
+        finally:
+            for a in arms[1:]:
+                a.close()
+
+    traj_a, rec_a, loss_a = go(arms_fresh(), 3)
+    ckpt = str(tmp_path / "hyper.npz")
+    traj_1, _, _ = go(arms_fresh(), 3, ckpt=ckpt, max_wall=0.0)   # stops after one step
+    assert len(traj_1) == 2
+    traj_b, rec_b, loss_b = go(arms_fresh(), 3, ckpt=ckpt)
+    assert len(traj_b) == 4
+    for u, v in zip(traj_a, traj_b):
+        assert np.array_equal(u, v), (u, v)
+    for name in rec_a:
+        assert [r["iters"] for r in rec_a[name]] == [r["iters"] for r in rec_b[name]], name
+    assert loss_a == loss_b

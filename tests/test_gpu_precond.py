@@ -221,3 +221,81 @@ def test_spectral_preconditioner_cuts_cg_steps_for_smooth_kernels(ctx):
     assert np.all(with_pc.relres_true <= 1e-8) and np.all(plain.relres_true <= 1e-8)
     print("spectral m=45:", with_pc.iters, "plain CG:", plain.iters)
     assert with_pc.iters.max() < plain.iters.max()
+
+
+# ---- Psi stored in FP32 (pkm_precond_psi_f32) --------------------------------
+
+def _nystrom_phi(p, jitter=JIT):
+    """Phi = K_XU L^-T, K_UU + jitter I = L L^T: the factor whose Psi the
+    library forms (for the rounding bound, which needs |Psi| only)."""
+    from oracle.kernel import rbf_block
+    Xu = p.X[p.idx]
+    L = np.linalg.cholesky(rbf_block(Xu, Xu, p.sigma2, p.lengthscales) + jitter * np.eye(len(p.idx)))
+    return np.linalg.solve(L, rbf_block(p.X, Xu, p.sigma2, p.lengthscales).T).T
+
+
+@pytest.mark.parametrize("kind,n,m,k", [(pk.PKM_PC_NYSTROM, 3000, 128, 17),   # m % 4 == 0
+                                        (pk.PKM_PC_NYSTROM, 2000, 130, 33),   # m even only
+                                        (pk.PKM_PC_FITC, 1500, 97, 1),        # m odd
+                                        (pk.PKM_PC_FITC, 1031, 64, 4)])
+def test_psi_f32_apply_within_rounding_bound(ctx, kind, n, m, k):
+    """The apply from FP32-rounded Psi moves each entry by no more than the
+    derived bound (2u + u^2) |Psi| (|Psi|^T |R|) (plus FP64-sum slack), moves
+    it visibly, and switching back gives the FP64 apply bit for bit."""
+    from oracle import precision as pr
+    p = make("small_fp64", seed=24, n=n, m=m, n_probes=k - 1)
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, kind, m, idx=g.idx, jitter=JIT)
+    try:
+        z64 = host(pk.pkm_precond_apply(ctx, pc, g.B))
+        pk.pkm_precond_psi_f32(ctx, pc, True)
+        z32 = host(pk.pkm_precond_apply(ctx, pc, g.B))
+        pk.pkm_precond_psi_f32(ctx, pc, False)
+        z64b = host(pk.pkm_precond_apply(ctx, pc, g.B))
+        D = pk.pkm_precond_diag(ctx, pc, n)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    assert np.array_equal(z64, z64b)
+    Psi = pr.woodbury_psi(D, _nystrom_phi(p))
+    R = p.B
+    bound = pr.psi_rounding_bound(Psi, R)
+    slack = 1e-12 * (np.abs(R) / D[:, None] + np.abs(Psi) @ (np.abs(Psi).T @ np.abs(R)))
+    dev_ = np.abs(z32 - z64)
+    assert np.all(dev_ <= 1.001 * bound + slack), np.max(dev_ / (bound + slack))
+    assert dev_.max() > 0
+
+
+@pytest.mark.parametrize("lam", [1e-2, 1e-3])
+def test_psi_f32_solve_is_certified(ctx, lam):
+    """Solves with the FP32-stored Psi are exact PCG around a slightly
+    different preconditioner: certified at 1e-6 either way; at lambda = 1e-2
+    (small rounding perturbation) the step count stays within 10 % + 2 of the
+    FP64 Psi's.  (At 1e-3 it rises, as the oracle's pin predicts.)"""
+    import dataclasses
+    p = dataclasses.replace(make("block_fp32", seed=25, n=12000, m=256, n_probes=8), lam=lam)
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, 256, idx=g.idx, jitter=JIT)
+    opts = pk.make_opts(tol=1e-6, prec=pk.PKM_FP64)
+    try:
+        _, i64 = pk.pkm_solve(ctx, g.prob, g.B, pc=pc, opts=opts)
+        pk.pkm_precond_psi_f32(ctx, pc, True)
+        _, i32 = pk.pkm_solve(ctx, g.prob, g.B, pc=pc, opts=opts)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    print(f"lambda {lam:g}: PCG steps FP64 Psi {i64.total_iters}, FP32 Psi {i32.total_iters}")
+    for info in (i64, i32):
+        assert np.all(info.col_status == pk.PKM_COL_CONVERGED)
+        assert np.all(info.relres_true <= 1e-6)
+    if lam >= 1e-2:
+        assert abs(i32.total_iters - i64.total_iters) <= 0.1 * i64.total_iters + 2
+
+
+def test_psi_f32_rejects_bad_flag(ctx):
+    p = make("small_fp64", seed=26, n=300, m=20, n_probes=1)
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, 20, idx=g.idx, jitter=JIT)
+    try:
+        rc = pk.load().pkm_precond_psi_f32(ctx, pc, 2)
+        assert rc == pk.PKM_ERR_INVALID
+    finally:
+        pk.pkm_precond_destroy(pc)
