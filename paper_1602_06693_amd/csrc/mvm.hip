@@ -291,28 +291,6 @@ __global__ __launch_bounds__(256) void k_mvm_f64(const double* __restrict__ xs, 
     }
 }
 
-// 2^S in FP64, table-driven (Tang's method, ACM TOMS 1989): S = N / 64 + r
-// with N = rint(64 S) and |r| <= 1/128, so 2^S = 2^(N >> 6) * 2^((N & 63) / 64)
-// * 2^r.  2^(j / 64) comes from a 64-entry table; 2^r = e^(r ln 2) is its
-// Taylor polynomial of degree 6 (truncation below 3e-20 relative on
-// |r| <= 1/128).  S below -1100 gives 0 (2^-1100 underflows); NaN stays NaN.
-__device__ inline double exp2_tab(double S, const double* __restrict__ tab) {
-    constexpr double L = 0.6931471805599453;   // ln 2
-    constexpr double c1 = L, c2 = c1 * L / 2, c3 = c2 * L / 3, c4 = c3 * L / 4,
-                     c5 = c4 * L / 5, c6 = c5 * L / 6;
-    S = S < -1100.0 ? -1100.0 : S;
-    const double y = rint(S * 64.0);
-    const double r = fma(y, -1.0 / 64.0, S);   // exact
-    const int N = int(y);
-    double p = fma(c6, r, c5);
-    p = fma(p, r, c4);
-    p = fma(p, r, c3);
-    p = fma(p, r, c2);
-    p = fma(p, r, c1);
-    p = fma(p, r, 1.0);
-    return ldexp(tab[N & 63] * p, N >> 6);
-}
-
 // FP64 product on 16x16x4 FP64 MFMA, same structure as the FP32 one: per
 // 16-row j-tile, the exponent tile S^T = B_J A_I^T (S4 MFMAs over the
 // augmented operands) leaves lane l with S[i = l % 16][j = l / 16 + 4 r],
@@ -589,13 +567,14 @@ void cross_k64(pkm_ctx* ctx, const pkm_problem* prob, const double* Xa, int64_t 
 }
 
 // Y = sum_splits(part32) + lambda V, FP64 out.
-// (zero_after: 128 slots cleared for the next product, by the first work-group)
+// (zero_after: the column-maxima slots cleared for the next product, by the
+// first work-group)
 __global__ void k_finish32(const float* __restrict__ part, int nsplit, int64_t sstride, int kp,
                            int64_t n, int k, const double* __restrict__ V, int64_t ldv,
                            double lambda, double* __restrict__ Y, int64_t ldy,
                            unsigned long long* __restrict__ zero_after) {
     int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (zero_after && e < 128) zero_after[e] = 0ull;
+    if (zero_after && e < kColmaxSlots) zero_after[e] = 0ull;
     if (e >= n * k) return;
     int64_t i = e / k;
     int c = int(e - i * k);
@@ -631,8 +610,14 @@ void mvm_shift(pkm_ctx* ctx, int prec, int k, const double* V, double* Y, double
     }
     PKM_REQUIRE(prec == PKM_FP32 || prec == PKM_BF16X1 || prec == PKM_BF16X3 || prec == PKM_F16X3,
                 "unknown precision");
-    for (int c0 = 0; c0 < k; c0 += 65) {
-        int kc = std::min(65, k - c0);
+    // FP32 products take up to 65 columns per pass, 16-bit ones up to seven
+    // tiles; a wider block is split into passes of equal width (k = 129 as
+    // 65 + 64: 3.62 ms at 65,536 points against 3.85 ms as 112 + 17)
+    const int kmax = prec == PKM_FP32 ? 65 : kBf16MaxCols;
+    const int npass = int(cdiv(k, kmax));
+    const int width = int(cdiv(k, npass));
+    for (int c0 = 0; c0 < k; c0 += width) {
+        int kc = std::min(width, k - c0);
         F32Out o = prec == PKM_FP32 ? mvm_k32(ctx, kc, V + c0, k)
                                     : mvm_kbf16(ctx, prec, kc, V + c0, k);
         k_finish32<<<cdiv(n * kc, 256), 256, 0, s>>>(o.y, o.jsplit, o.stride, o.kp, n, kc, V + c0, k,

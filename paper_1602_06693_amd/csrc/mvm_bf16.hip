@@ -122,7 +122,7 @@ __global__ void k_aug_bf16(const double* __restrict__ X, int64_t n, int64_t n_pa
 // L = blockDim / k rows per pass, so a pass reads consecutive addresses.
 __global__ void k_colmax(const double* __restrict__ V, int64_t ldv, int64_t n, int k,
                          unsigned long long* __restrict__ colmax) {
-    __shared__ unsigned long long sm[128];
+    __shared__ unsigned long long sm[kColmaxSlots];
     const int t = threadIdx.x;
     if (t < k) sm[t] = 0ull;
     __syncthreads();
@@ -137,6 +137,10 @@ __global__ void k_colmax(const double* __restrict__ V, int64_t ldv, int64_t n, i
     }
     __syncthreads();
     if (t < k) atomicMax(&colmax[t], sm[t]);
+}
+
+__global__ void k_zero_slots(unsigned long long* __restrict__ slots) {
+    slots[threadIdx.x] = 0ull;   // one block of kColmaxSlots threads
 }
 
 // Power-of-two exponent that takes column c's largest magnitude into
@@ -240,6 +244,10 @@ __device__ inline uint32_t pack_f16x2(float a, float b) {
 // is exact in FP32; v_fma_mix_f32 forms it as fma(-K_h, 1, K) with K_h read
 // as the FP16 half (op_sel) of the packed dword.  The compiler keeps a
 // conversion back to FP32 plus a subtraction for the same expression.
+// (Measured and dropped: v_fma_mixlo_f16 / v_fma_mixhi_f16 writing the
+// rounded remainders straight into the two halves of the K_l dword -- two
+// ops per entry pair instead of three, bit-identical results -- ran 2-5 %
+// slower at 65,536 points, k = 17 to 65.)
 __device__ inline void split_k_f16(const float (&kf)[8], f16x8& kh, f16x8& kl) {
     u32x4 h, l;
 #pragma unroll
@@ -397,17 +405,20 @@ void prepare_bf16(pkm_ctx* ctx) {
     P.validb = true;
 }
 
+constexpr int kBf16U = 4;   // i-tiles of 16 rows per wave
+
 template <int S6, int NP, bool ML>
 static void launch_bf16_s(int KT, dim3 grid, hipStream_t s, const bf16x8* js, const bf16x8* is,
                           const bf16x8* vb, float* y, int nchunk, int nrb, int jsplit, int cps,
                           int64_t stride, const unsigned long long* colmax, float s2, int kout) {
 #define PKM_B_CASE(kt)                                                                         \
     if (KT == kt) {                                                                            \
-        k_mvm_bf16<S6, kt, 4, NP, ML><<<grid, 256, 0, s>>>(js, is, vb, y, nchunk, nrb, jsplit, cps, \
-                                                        stride, colmax, s2, kout);             \
+        k_mvm_bf16<S6, kt, kBf16U, NP, ML><<<grid, 256, 0, s>>>(                               \
+            js, is, vb, y, nchunk, nrb, jsplit, cps, stride, colmax, s2, kout);                \
         return;                                                                                \
     }
     PKM_B_CASE(1) PKM_B_CASE(2) PKM_B_CASE(3) PKM_B_CASE(4) PKM_B_CASE(5)
+    PKM_B_CASE(6) PKM_B_CASE(7)
 #undef PKM_B_CASE
     fail(PKM_ERR_UNSUPPORTED, "BF16 product: unsupported column count");
 }
@@ -433,7 +444,7 @@ static void launch_bf16(int S6, int KT, dim3 grid, hipStream_t s, const bf16x8* 
 F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     Prepared& P = ctx->P();
     prepare_bf16(ctx);
-    PKM_REQUIRE(k >= 1 && k <= 80, "16-bit product supports 1 <= k <= 80 columns per call");
+    PKM_REQUIRE(k >= 1 && k <= kBf16MaxCols, "16-bit product: 1 <= k <= 112 columns per pass");
     const int NP = prec == PKM_F16X3 ? 4 : prec == PKM_BF16X3 ? 3 : 1;
     const int NPV = NP == 1 ? 1 : 2;
     const int KT = int(cdiv(k, 16));   // every column on the matrix cores
@@ -448,21 +459,24 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
     __bf16* vb = ctx->vbf.as<__bf16>();
     float* yrp = reinterpret_cast<float*>(reinterpret_cast<char*>(vb) + vb_bytes);
     unsigned long long* colmax = nullptr;
-    if (NP == 4) {   // column scales for the FP16 parts (128 slots; padded columns stay 0)
+    if (NP == 4) {   // column scales for the FP16 parts (padded columns' slots stay 0)
         // the PCG direction update may have filled the slots for this V already
         const bool ready = ctx->colmax_src == V && ctx->colmax_k == k && ldv == k &&
-                           ctx->colmax.bytes >= 128 * sizeof(unsigned long long);
+                           ctx->colmax.bytes >= kColmaxSlots * sizeof(unsigned long long);
         ctx->colmax_src = nullptr;
         if (ready) {
             colmax = ctx->colmax.as<unsigned long long>();
         } else {
             // the slots start at zero: the previous product's k_finish32 cleared
             // them (cleared here after a fresh allocation or an interrupted call)
-            if (ctx->colmax.bytes < 128 * sizeof(unsigned long long)) ctx->colmax_clean = false;
-            ctx->colmax.ensure(128 * sizeof(unsigned long long));
+            if (ctx->colmax.bytes < kColmaxSlots * sizeof(unsigned long long))
+                ctx->colmax_clean = false;
+            ctx->colmax.ensure(kColmaxSlots * sizeof(unsigned long long));
             colmax = ctx->colmax.as<unsigned long long>();
-            if (!ctx->colmax_clean)
-                PKM_HIP(hipMemsetAsync(colmax, 0, 128 * sizeof(unsigned long long), s));
+            if (!ctx->colmax_clean) {   // a fill kernel, not a memset node (graph capture)
+                k_zero_slots<<<1, kColmaxSlots, 0, s>>>(colmax);
+                PKM_CHECK_LAUNCH();
+            }
             ctx->colmax_clean = false;
             const int rows_per_pass = 256 / k;
             const int64_t blocks = std::min<int64_t>(512, cdiv(P.n, rows_per_pass));
@@ -477,7 +491,7 @@ F32Out mvm_kbf16(pkm_ctx* ctx, int prec, int k, const double* V, int ldv) {
                                                   ml ? 1 : 0, vb, yrp);
     PKM_CHECK_LAUNCH();
 
-    constexpr int U = 4;
+    constexpr int U = kBf16U;
     const int64_t nrb = cdiv(P.n_pad, 64 * U);
     int jsplit = 1;
     while (jsplit < 8 && nrb * jsplit < 2048 && nchunk / (jsplit * 2) >= 8) jsplit <<= 1;

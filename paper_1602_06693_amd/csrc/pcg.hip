@@ -373,7 +373,7 @@ __global__ __launch_bounds__(256) void k_update_p_cm(int64_t n, int k,
                                                      const double* __restrict__ z,
                                                      double* __restrict__ p,
                                                      unsigned long long* __restrict__ colmax) {
-    __shared__ unsigned long long sm[128];
+    __shared__ unsigned long long sm[kColmaxSlots];
     const int t = threadIdx.x;
     if (t < k) sm[t] = 0ull;
     __syncthreads();
@@ -661,8 +661,8 @@ int solve(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* pc, int k, c
         dot_part(ctx, r, z, n, k, partB);
         k_beta<<<1, 256, 0, s>>>(partB, k, st);
         PKM_CHECK_LAUNCH();
-        if (cur == PKM_F16X3 && !wscale && k <= 80 && ctx->colmax_clean &&
-            ctx->colmax.bytes >= 128 * sizeof(unsigned long long)) {
+        if (cur == PKM_F16X3 && !wscale && k <= kBf16MaxCols && ctx->colmax_clean &&
+            ctx->colmax.bytes >= kColmaxSlots * sizeof(unsigned long long)) {
             // the next product's column maxima come with the update (the
             // slots are clean: the last product's k_finish32 cleared them)
             const int64_t blocks = std::min<int64_t>(512, cdiv(n, 256 / k));

@@ -57,6 +57,28 @@ constexpr double kStallGap = 2.0;
 // as a stall (slow, non-monotone residuals of long solves are PCG's pace).
 constexpr int64_t kI8PatienceSteps = 10 * kStallSteps;
 
+// 2^S in FP64, table-driven (Tang's method, ACM TOMS 1989): S = N / 64 + r
+// with N = rint(64 S) and |r| <= 1/128, so 2^S = 2^(N >> 6) * 2^((N & 63) / 64)
+// * 2^r.  2^(j / 64) comes from a 64-entry table; 2^r = e^(r ln 2) is its
+// Taylor polynomial of degree 6 (truncation below 3e-20 relative on
+// |r| <= 1/128).  S below -1100 gives 0 (2^-1100 underflows); NaN stays NaN.
+__device__ inline double exp2_tab(double S, const double* __restrict__ tab) {
+    constexpr double L = 0.6931471805599453;   // ln 2
+    constexpr double c1 = L, c2 = c1 * L / 2, c3 = c2 * L / 3, c4 = c3 * L / 4,
+                     c5 = c4 * L / 5, c6 = c5 * L / 6;
+    S = S < -1100.0 ? -1100.0 : S;
+    const double y = rint(S * 64.0);
+    const double r = fma(y, -1.0 / 64.0, S);   // exact
+    const int N = int(y);
+    double p = fma(c6, r, c5);
+    p = fma(p, r, c4);
+    p = fma(p, r, c3);
+    p = fma(p, r, c2);
+    p = fma(p, r, c1);
+    p = fma(p, r, 1.0);
+    return ldexp(tab[N & 63] * p, N >> 6);
+}
+
 struct StallMonitor {
     double best = 1e300, last = 1e300;
     int since = 0;
@@ -108,14 +130,14 @@ constexpr double kRefineEta = 1e-3;
 // larger d takes the FP64 vector-ALU product on direct differences.
 constexpr int kAug64MaxD4 = 36;
 
-// 16-bit products: columns per pass (nine 16-column tiles; wider blocks go in
-// passes of this many), and the column-maxima slots of the FP16 scales.
-constexpr int kBf16MaxCols = 144;
+// 16-bit products: columns per pass (seven 16-column tiles; wider blocks go
+// in passes of this many), and the column-maxima slots of the FP16 scales.
+// Measured at 65,536 points (FP16x3): one pass of seven tiles 2.23 ms at
+// k = 100 against 2.84 ms as two passes; eight or nine tiles per pass ran
+// slower than splitting (k = 144: 6.8 ms in one pass at four i-tiles per
+// wave, 4.1 ms at two, 3.4 ms as two passes).
+constexpr int kBf16MaxCols = 112;
 constexpr int kColmaxSlots = 256;
-// i-tiles of 16 rows per wave in the 16-bit product: four up to five column
-// tiles, two above (the accumulators of nine tiles at four i-tiles would
-// not fit the register file).
-constexpr int bf16_u(int kt) { return kt <= 5 ? 4 : 2; }
 
 // Grow-only device buffer.
 struct DevBuf {

@@ -12,7 +12,10 @@ from pkm_inputs import make
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n,N,d", [(600, 4, 8), (257, 16, 3), (400, 1, 16), (300, 20, 32)])
+@pytest.mark.parametrize("n,N,d", [(600, 4, 8), (257, 16, 3), (400, 1, 16), (300, 20, 32),
+                                   (5000, 16, 8), (700, 40, 5), (300, 3, 1), (300, 3, 10),
+                                   (300, 3, 12), (300, 3, 18), (300, 3, 20), (300, 3, 24),
+                                   (300, 3, 26), (300, 3, 28), (1, 2, 4), (17, 1, 6)])
 def test_grad_pass_matches_oracle_on_same_solutions(ctx, n, N, d):
     rng = np.random.default_rng(n + N)
     X = rng.random((n, d))

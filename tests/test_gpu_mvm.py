@@ -101,7 +101,8 @@ def test_invalid_arguments_rejected(ctx):
 @pytest.mark.parametrize("prec,tol", [(pk.PKM_BF16X1, 1e-2), (pk.PKM_BF16X3, 1e-4),
                                       (pk.PKM_F16X3, TOL32)])
 @pytest.mark.parametrize("n,k", [(1000, 1), (777, 17), (600, 33), (513, 64), (300, 65), (1, 1),
-                                 (40, 2), (257, 7)])
+                                 (40, 2), (257, 7), (400, 81), (333, 100), (300, 129), (260, 144),
+                                 (200, 145), (150, 300)])
 def test_bf16_product(ctx, prec, tol, n, k):
     p = make("block_fp32", seed=15, n=n, n_probes=max(k - 1, 0))
     g = GpuProblem(p)
@@ -122,6 +123,23 @@ def test_16bit_product_dimensions(ctx, d, prec, tol):
     V = rng.standard_normal((n, k))
     prob = pk.Problem(dev(X), ls, 0.7, 1e-3)
     want = ok.kernel_mvm(X, 0.7, ls, 1e-3, V)
+    got = host(pk.pkm_kernel_mvm(ctx, prob, dev(V), prec))
+    assert np.all(rel_err(got, want) < tol)
+
+
+@pytest.mark.parametrize("prec,tol", [(pk.PKM_BF16X3, 1e-4), (pk.PKM_F16X3, TOL32)])
+@pytest.mark.parametrize("d,k", [(8, 112), (36, 112), (8, 137), (36, 137)])
+def test_16bit_product_wide_blocks(ctx, d, k, prec, tol):
+    """k = 112 (one pass of seven 16-column tiles) and k = 137 (two passes),
+    at the smallest and the largest exponent-slice count, with columns of
+    very different scales."""
+    rng = np.random.default_rng(200 + d + k)
+    n = 900
+    X = rng.random((n, d))
+    ls = np.exp(rng.uniform(np.log(0.2 * np.sqrt(d)), np.log(np.sqrt(d)), size=d))
+    V = rng.standard_normal((n, k)) * np.exp(rng.uniform(-3, 3, size=k))
+    prob = pk.Problem(dev(X), ls, 1.3, 1e-3)
+    want = ok.kernel_mvm(X, 1.3, ls, 1e-3, V)
     got = host(pk.pkm_kernel_mvm(ctx, prob, dev(V), prec))
     assert np.all(rel_err(got, want) < tol)
 

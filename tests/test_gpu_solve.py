@@ -147,6 +147,23 @@ def test_bf16_products_reach_tolerance_with_reliable_updates(ctx, prec, lam):
     assert np.all(tr <= 1e-6), tr
 
 
+@pytest.mark.parametrize("k", [100, 150])
+def test_f16x3_solve_of_a_wide_block(ctx, k):
+    """k = 100 (one pass of seven column tiles, the column maxima formed by
+    the direction update) and k = 150 (two passes) with FP16x3 products:
+    every column certified at 1e-6 against the exact K."""
+    p = make("block_fp32", seed=9, n=2500, m=100, n_probes=k - 1)
+    g = GpuProblem(p)
+    pc = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, len(p.idx), idx=g.idx, jitter=JIT)
+    try:
+        X, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc,
+                               opts=pk.make_opts(tol=1e-6, prec=pk.PKM_F16X3), allow_warning=False)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    tr = true_relres(p, host(X))
+    assert np.all(tr <= 1e-6), tr.max()
+
+
 def test_too_coarse_product_escalates_and_still_converges(ctx):
     """A smooth kernel with small noise (d = 4, long lengthscales, lambda ~ 1e-4)
     where FP32 products stagnate: the solve raises the arithmetic itself and
