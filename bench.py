@@ -48,7 +48,8 @@ ISSUE_MFMA_HALF, ISSUE_EXP, ISSUE_VALU, SIMDS, CLOCK_HZ = 8.5, 8.0, 4.0, 1024, 2
 # WRITE_SIZE runs, calibrated on a 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE
 # x 1.0): (workload, product, n, k) -> bytes.  Valid while the kernel is
 # unchanged since the counters were taken.
-RECORDED_TRAFFIC = {("block_fp32", "f16x3", 65536, 17): (41863.0 * 2.0 + 34816.0) * 1024}
+RECORDED_TRAFFIC = {("block_fp32", "f16x3", 65536, 17): (41863.0 * 2.0 + 34816.0) * 1024,
+                    ("mixed", "i8x", 262144, 33): (6654787.0 * 2.0 + 540672.0) * 1024}
 
 
 def _recorded_traffic(p, prec):
@@ -188,7 +189,8 @@ def small_lambda_leg(pk, ctx, a):
                "flops_per_launch": fl, "flop_count": "n^2 (2 d + 2 k) per product",
                "achieved": tf, "unit": "TFLOP/s",
                "frac_of_fp64_peak": tf / PEAK_FP64_TFLOPS,
-               "frac_of_int8_peak": tf / PEAK_INT8_MFMA_TOPS}}
+               "frac_of_int8_peak": tf / PEAK_INT8_MFMA_TOPS,
+               "traffic": _recorded_traffic(p, "i8x")}}
     if not a.no_cpu_baseline:
         from oracle import kernel as ok
         threads = int(os.environ.get("PKM_ORACLE_THREADS", os.cpu_count() or 1))
