@@ -97,6 +97,18 @@ def _describe(p, m, prec, reliable):
             f"step = preconditioner setup + block PCG solve + gradient pass")
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), for the baseline record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(p, gpu_iters, budget_rows=1024):
     """FP64 oracle on a bounded sample: product rows, setup, gradient rows."""
     from oracle import gradient as og
@@ -130,7 +142,8 @@ def cpu_baseline(p, gpu_iters, budget_rows=1024):
               f"and one preconditioner apply timed in full; gradient forms on a "
               f"{grows}x{grows} block scaled by (n/{grows})^2; extrapolated, FP64")
     return {"value": total, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": sample, "per_product_s": t_mvm, "setup_s": t_setup}
+            "sample": sample, "per_product_s": t_mvm, "setup_s": t_setup,
+            "cpu_model": cpu_model()}
 
 
 PEAK_INT8_MFMA_TOPS = 5000.0   # dense
@@ -199,7 +212,7 @@ def small_lambda_leg(pk, ctx, a):
         ok.kernel_mvm(p.X, p.sigma2, p.lengthscales, p.lam, p.B, rows=rows, threads=threads)
         per = (time.perf_counter() - t1) * p.n / len(rows)
         out["cpu_baseline"] = {"value": per * int(info.total_iters), "unit": "s",
-                               "cores": threads, "kind": "oracle",
+                               "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
                                "sample": (f"oracle kernel_mvm on 256 of {p.n} rows, scaled to a "
                                           f"whole product ({per:.1f} s) and by the GPU solve's "
                                           f"{int(info.total_iters)} steps; extrapolated, FP64, "
