@@ -57,3 +57,15 @@ def test_noalloc_rejects_oversized_and_other_arithmetic(ctx):
     with pytest.raises(pk.PkmError) as e:
         pk.pkm_kernel_mvm_noalloc(ctx, prob, B, torch.empty_like(B), prec=pk.PKM_F16X3)
     assert e.value.code == pk.PKM_ERR_UNSUPPORTED
+
+
+def test_noalloc_column_groups(ctx):
+    """k = 70 takes three column groups of at most 33 through the same
+    scratch (each group's digits and partial planes overwrite the last's):
+    still bit-identical to the allocating entry point."""
+    torch = torch_cuda()
+    p, prob, B = _case(45, 9000, 70)
+    Y = torch.full_like(B, np.nan)
+    pk.pkm_kernel_mvm_noalloc(ctx, prob, B, Y)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(Y), host(pk.pkm_kernel_mvm(ctx, prob, B, pk.PKM_I8X)))
