@@ -33,6 +33,15 @@ standard normal draws W (m x d); 2 pi s_r = W_r / l.
 K_UU carries a jitter delta I (the caller's value; the same on both sides),
 which changes P but never the solution of the preconditioned system.
 
+Section 3.2 (partial SVD, randomised truncated form): with m standard
+normal sketch columns Omega (n x l), q power iterations and the r largest
+eigenpairs,
+    Y = K Omega;  q times: Q = orth(Y), Y = K Q;  Q = orth(Y),
+    B = Q^T K Q = V diag(w) V^T,   Phi = Q V_r diag(w_r)^1/2,
+so Phi Phi^T approximates K by its leading eigenpairs, and P = Phi Phi^T +
+lambda I as in the factor form.  Negative eigenvalues of B (rounding)
+are clipped to zero.
+
 Pinned by (tests/test_oracle_precond.py): each apply against a direct solve
 with the dense P it defines; m = n Nystrom reproduces K (so PCG stops after
 one step); FITC has diag(P) = diag(K) + lambda exactly and D_u = lambda at
@@ -197,3 +206,23 @@ def lowrank(Phi, lam):
         return Phi @ Phi.T + lam * np.eye(Phi.shape[0])
 
     return Preconditioner(apply, dense, {"Phi": Phi})
+
+
+def rsvd_factor(X, sigma2, lengthscales, Omega, r, q=0):
+    """Phi (n x r) of the randomised truncated SVD of K (Section 3.2):
+    range of K^(q+1) Omega, Rayleigh-Ritz on it, the r largest eigenpairs."""
+    X = np.asarray(X, dtype=np.float64)
+    K = rbf_block(X, X, sigma2, lengthscales)
+    Y = K @ np.asarray(Omega, dtype=np.float64)
+    for _ in range(q):
+        Q, _ = np.linalg.qr(Y)
+        Y = K @ Q
+    Q, _ = np.linalg.qr(Y)
+    B = Q.T @ K @ Q
+    w, V = np.linalg.eigh(0.5 * (B + B.T))
+    order = np.argsort(w)[::-1][:r]
+    return Q @ (V[:, order] * np.sqrt(np.maximum(w[order], 0.0)))
+
+
+def rsvd(X, sigma2, lengthscales, lam, Omega, r, q=0):
+    return lowrank(rsvd_factor(X, sigma2, lengthscales, Omega, r, q), lam)

@@ -2,6 +2,7 @@
 import numpy as np
 
 from oracle import kernel as ok
+from oracle.kernel import kernel_matrix
 from oracle import precond as op
 from oracle.pcg import pcg
 from pkm_inputs import make
@@ -168,3 +169,62 @@ def test_spectral_features_closed_forms():
     Kbig = op.spectral_features(X, s2, ls, Wbig)
     err = np.abs(Kbig @ Kbig.T - ok.kernel_matrix(X, s2, ls)).max()
     assert err < 5 * s2 / np.sqrt(200000)   # Monte Carlo, ~1/sqrt(m)
+
+
+# ---- randomised truncated SVD (Section 3.2, partial SVD) --------------------
+
+def test_rsvd_recovers_a_low_rank_kernel_exactly():
+    """X with c distinct points (each repeated) gives rank(K) = c; a sketch of
+    l >= c columns spans K's range, so with r >= c the factor reproduces K
+    and P = K + lambda I (PCG needs one step)."""
+    from oracle.pcg import pcg
+    rng = np.random.default_rng(11)
+    c, rep, d = 12, 9, 3
+    X = np.repeat(rng.random((c, d)), rep, axis=0)
+    ls = np.full(d, 0.4)
+    K = kernel_matrix(X, 1.3, ls)
+    Omega = rng.standard_normal((X.shape[0], 16))
+    Phi = op.rsvd_factor(X, 1.3, ls, Omega, r=14, q=0)
+    assert np.max(np.abs(Phi @ Phi.T - K)) <= 1e-10 * np.max(np.abs(K))
+    P = op.rsvd(X, 1.3, ls, 1e-2, Omega, r=14)
+    b = rng.standard_normal(X.shape[0])
+    res = pcg(lambda V: K @ V + 1e-2 * V, b, precond=P, tol=1e-10)
+    assert int(res.iters[0]) <= 2
+
+
+def test_rsvd_with_power_iterations_is_near_the_best_rank_r():
+    """Eckart-Young: no rank-r Phi Phi^T gets closer to K (2-norm) than the
+    (r+1)-th eigenvalue; with 4 power iterations and 10 oversampling columns
+    the randomised factor comes within 1 % of it."""
+    rng = np.random.default_rng(12)
+    X = rng.random((300, 4))
+    ls = np.full(4, 0.35)
+    K = kernel_matrix(X, 1.0, ls)
+    lam_K = np.sort(np.linalg.eigvalsh(K))[::-1]
+    r = 20
+    Phi = op.rsvd_factor(X, 1.0, ls, rng.standard_normal((300, r + 10)), r=r, q=4)
+    err = np.linalg.norm(K - Phi @ Phi.T, 2)
+    assert lam_K[r] * (1 - 1e-9) <= err <= 1.01 * lam_K[r], (err, lam_K[r])
+    # Rayleigh-Ritz: the factor's eigenvalues (Ritz values) never exceed the
+    # corresponding eigenvalues of K and here come within 0.1 % of them
+    w = np.sort(np.linalg.eigvalsh(Phi.T @ Phi))[::-1]
+    assert np.all(w <= lam_K[:r] * (1 + 1e-12))
+    assert np.allclose(w, lam_K[:r], rtol=1e-3)
+
+
+def test_rsvd_is_the_factor_form():
+    """P from the randomised SVD is the factor form P = Phi Phi^T + lambda I
+    (dense solve), symmetric positive definite with P >= lambda I; unlike
+    Nystrom it is a projection Pi K Pi of K, which may exceed K in some
+    directions."""
+    rng = np.random.default_rng(13)
+    X = rng.random((120, 2))
+    ls = np.full(2, 0.3)
+    K = kernel_matrix(X, 0.8, ls)
+    lam = 1e-3
+    P = op.rsvd(X, 0.8, ls, lam, rng.standard_normal((120, 30)), r=24, q=1)
+    R = rng.standard_normal((120, 3))
+    dense = P.dense()
+    assert np.allclose(P(R), np.linalg.solve(dense, R), rtol=1e-8, atol=1e-10)
+    assert np.allclose(dense, dense.T, atol=1e-12)
+    assert np.linalg.eigvalsh(dense).min() >= lam * (1 - 1e-9)
