@@ -458,6 +458,9 @@ def main():
                     help="also time this mixed arithmetic (reported beside the headline)")
     ap.add_argument("--plain", default="fp32", choices=("fp32", "fp64", "i8x", "none"),
                     help="also time this product arithmetic for the mixed-vs-plain comparison")
+    ap.add_argument("--rsvd", action="store_true",
+                    help="step mode: also time the step with the randomised truncated SVD "
+                         "preconditioner of the same rank (one power iteration, FP32 sketch)")
     ap.add_argument("--fitc", action=argparse.BooleanOptionalAction, default=False,
                     help="step mode: also time the mixed step with FITC (same m and points)")
     ap.add_argument("--small-lambda", action=argparse.BooleanOptionalAction, default=True,
@@ -539,7 +542,10 @@ def main():
         kind = pk.PKM_PC_NYSTROM if kind is None else kind
 
         def step():
-            pc = pk.pkm_precond_setup(ctx, prob, kind, m, idx=idx, jitter=1e-8)
+            if kind == "rsvd":   # randomised truncated SVD, rank m, 20 oversampling columns
+                pc = pk.pkm_precond_setup_rsvd(ctx, prob, m, omega, q=1, prec=pk.PKM_FP32)
+            else:
+                pc = pk.pkm_precond_setup(ctx, prob, kind, m, idx=idx, jitter=1e-8)
             try:
                 if psi32:
                     pk.pkm_precond_psi_f32(ctx, pc, True)
@@ -593,6 +599,11 @@ def main():
     fitc = None
     if a.fitc:   # the same step with the FITC preconditioner (same inducing points)
         fitc = run_variant(precs[a.prec], a.steps, a.warmup, a.prec + "+fitc", pk.PKM_PC_FITC)
+    rsvd = None
+    if a.rsvd:   # the same step with the randomised truncated SVD of the same rank
+        omega = torch.from_numpy(np.random.default_rng(a.seed + 17).standard_normal(
+            (p.n, m + 20))).to("cuda:0")
+        rsvd = run_variant(precs[a.prec], a.steps, a.warmup, a.prec + "+rsvd", "rsvd")
     small = None
     if a.small_lambda and a.workload == "block_fp32" and a.n is None:
         small = small_lambda_leg(pk, ctx, a)
@@ -651,6 +662,12 @@ def main():
                         "true_residual_products": int(plain["info"].true_residuals),
                         "mvm_ms": plain["mvm_ms"], "mvm_tflops": plain["tflops"]}
         out["speedup_vs_plain"] = out["plain"]["value"] / value
+    if rsvd is not None:
+        out["rsvd"] = {"product": a.prec, "preconditioner": f"randomised SVD r={m}, l={m + 20}, q=1",
+                       "value": statistics.median(rsvd["times"]),
+                       "iters": int(rsvd["info"].total_iters),
+                       "true_residual_products": int(rsvd["info"].true_residuals),
+                       "max_true_relres": rsvd["max_rel"]}
     if fitc is not None:
         out["fitc"] = {"product": a.prec, "preconditioner": "fitc",
                        "value": statistics.median(fitc["times"]),

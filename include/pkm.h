@@ -248,6 +248,26 @@ int pkm_precond_sub_lowrank(pkm_ctx* ctx, const pkm_precond* pc, int32_t k,
  * matrix inversion lemma.  1 <= m <= 2048.                                  */
 int pkm_precond_setup_spectral(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
                                const double* W, pkm_precond** out);
+/* Randomised truncated SVD (Section 3.2, partial SVD by random sampling):
+ * Omega (device n x l FP64, caller-owned: standard normal draws), q power
+ * iterations; Y = K Omega, then q times Q = orth(Y), Y = K Q; Q = orth(Y),
+ * B = Q^T K Q = V diag(w) V^T and Phi = Q V_r diag(w_r)^1/2 from the r
+ * largest eigenvalues (negatives clipped to 0); P = Phi Phi^T + lambda I
+ * through the matrix inversion lemma (a PKM_PC_LOWRANK preconditioner).
+ * The products with K use arithmetic prec; orth is shifted Cholesky QR
+ * plus two Cholesky QR passes in FP64 on the device; the l x l
+ * eigenproblem is solved on the host.  1 <= r <= l <= min(n, 1024),
+ * 0 <= q <= 8; PKM_ERR_BREAKDOWN if the sketch is zero or non-finite.    */
+int pkm_precond_setup_rsvd(pkm_ctx* ctx, const pkm_problem* prob, int32_t r, int32_t l,
+                           const double* Omega, int32_t q, int32_t prec,
+                           pkm_precond** out);
+/* Host utility (no device work, no context): eigenvalues w (descending) and
+ * eigenvectors (the columns of Z, row-major n x n) of the symmetric n x n
+ * host matrix A (row-major; its symmetric part is used), by Householder
+ * tridiagonalisation and implicit QR steps with Wilkinson shifts -- the
+ * eigensolver of pkm_precond_setup_rsvd.  1 <= n <= 4096, finite A, else
+ * PKM_ERR_INVALID.                                                         */
+int pkm_sym_eig(int32_t n, const double* A, double* w, double* Z);
 int pkm_precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int32_t k,
                       const double* R, double* Z);
 /* Storage of Psi in the apply Z = D^-1 R - Psi (Psi^T R) (the matrix

@@ -55,6 +55,7 @@ EXPORTS = (
     "pkm_mvm_stats_reset", "pkm_mlp_create", "pkm_mlp_destroy", "pkm_mlp_params",
     "pkm_mlp_forward", "pkm_mlp_loss_grad", "pkm_mlp_train_step", "pkm_adagrad_step",
     "pkm_mlp_nparams", "pkm_mlp_state_get", "pkm_mlp_state_set", "pkm_precond_psi_f32",
+    "pkm_precond_setup_rsvd", "pkm_sym_eig",
     "pkm_tune_cache_load",
 )
 
@@ -120,6 +121,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "pkm_precond_diag": (C.c_int, [vp, vp, P(dbl)]),
         "pkm_precond_destroy": (C.c_int, [vp]),
         "pkm_precond_psi_f32": (C.c_int, [vp, vp, i32]),
+        "pkm_precond_setup_rsvd": (C.c_int, [vp, P(pkm_problem), i32, i32, vp, i32, i32, P(vp)]),
+        "pkm_sym_eig": (C.c_int, [i32, P(dbl), P(dbl), P(dbl)]),
         "pkm_solve": (C.c_int, [vp, P(pkm_problem), vp, i32, vp, vp, P(pkm_solve_opts),
                                 P(pkm_solve_info)]),
         "pkm_solve_batched": (C.c_int, [vp, i32, P(pkm_problem), P(vp), i32, P(vp), P(vp),
@@ -297,6 +300,25 @@ def pkm_precond_diag(ctx, pc, n):
     D = np.empty(n)
     _check(load().pkm_precond_diag(ctx, pc, D.ctypes.data_as(C.POINTER(C.c_double))), ctx)
     return D
+
+
+def pkm_precond_setup_rsvd(ctx, prob: Problem, r, Omega, q=0, prec=PKM_FP32):
+    out = C.c_void_p()
+    _check(load().pkm_precond_setup_rsvd(ctx, prob.ref, int(r), int(Omega.shape[1]), _ptr(Omega),
+                                         int(q), int(prec), C.byref(out)), ctx)
+    return out
+
+
+def pkm_sym_eig(A):
+    """(w descending, Z with eigenvectors as columns) of a symmetric host matrix."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+    n = A.shape[0]
+    w = np.zeros(n)
+    Z = np.zeros((n, n))
+    P = C.POINTER(C.c_double)
+    _check(load().pkm_sym_eig(int(n), A.ctypes.data_as(P), w.ctypes.data_as(P),
+                              Z.ctypes.data_as(P)))
+    return w, Z
 
 
 def pkm_precond_psi_f32(ctx, pc, on=True):

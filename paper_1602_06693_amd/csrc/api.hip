@@ -13,6 +13,9 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const
                    const double* Phi, double jitter, pkm_precond* pc, int aux);
 void precond_sub_lowrank(pkm_ctx* ctx, const pkm_precond* pc, int k, const double* V, double* Y);
 void precond_psi_f32(pkm_ctx* ctx, pkm_precond* pc, bool on);
+void precond_setup_rsvd(pkm_ctx* ctx, const pkm_problem* prob, int r, int l, const double* Omega,
+                        int q, int prec, pkm_precond* pc);
+void sym_eig_host(int n, const double* A, double* w, double* Z);
 int laplace_mode(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* base, const double* y,
                  const pkm_solve_opts* o, int max_newton, double tol, double* f, double* a,
                  pkm_laplace_info* info);
@@ -322,6 +325,43 @@ int pkm_precond_setup_spectral(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
         return rc;
     }
     *out = pc;
+    return PKM_OK;
+}
+
+int pkm_precond_setup_rsvd(pkm_ctx* ctx, const pkm_problem* prob, int32_t r, int32_t l,
+                           const double* Omega, int32_t q, int32_t prec, pkm_precond** out) {
+    if (!ctx) return PKM_ERR_INVALID;
+    if (out) *out = nullptr;
+    pkm_precond* pc = nullptr;
+    int rc = guarded(ctx, [&] {
+        PKM_REQUIRE(out != nullptr, "out is NULL");
+        validate_problem(prob);
+        PKM_REQUIRE(l >= 1 && l <= 1024 && l <= prob->n, "l must be in [1, min(n, 1024)]");
+        PKM_REQUIRE(r >= 1 && r <= l, "r must be in [1, l]");
+        PKM_REQUIRE(q >= 0 && q <= 8, "q must be in [0, 8]");
+        check_prec(prec, prob->d);
+        require_dev(Omega, "Omega");
+        pc = new pkm_precond();
+        precond_setup_rsvd(ctx, prob, r, l, Omega, q, prec, pc);
+        return PKM_OK;
+    });
+    if (rc != PKM_OK) {
+        if (pc) pkm_precond_destroy(pc);
+        return rc;
+    }
+    *out = pc;
+    return PKM_OK;
+}
+
+int pkm_sym_eig(int32_t n, const double* A, double* w, double* Z) {
+    if (n < 1 || n > 4096 || !A || !w || !Z) return PKM_ERR_INVALID;
+    for (int64_t i = 0; i < int64_t(n) * n; ++i)
+        if (!std::isfinite(A[i])) return PKM_ERR_INVALID;
+    try {
+        sym_eig_host(n, A, w, Z);
+    } catch (...) {
+        return PKM_ERR_BREAKDOWN;
+    }
     return PKM_OK;
 }
 

@@ -1,0 +1,243 @@
+// Randomised truncated SVD preconditioner (Section 3.2, partial SVD by
+// random sampling) and the host symmetric eigensolver it needs.
+//
+//   Y = K Omega;  q times: Q = orth(Y), Y = K Q;  Q = orth(Y);
+//   B = Q^T (K Q) = V diag(w) V^T;  Phi = Q V_r diag(w_r)^1/2 (r largest w,
+//   negatives clipped to 0);  P = Phi Phi^T + lambda I (the factor form).
+//
+// The products with K run on the library's kernel products (the arithmetic
+// the caller picks); orth is shifted Cholesky QR followed by two plain
+// Cholesky QR passes in FP64 on the device; the l x l eigenproblem is solved
+// on the host (Householder tridiagonalisation, then implicit symmetric QR
+// steps with Wilkinson shifts, eigenvectors accumulated).
+
+#include "pkm_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <numeric>
+#include <vector>
+
+namespace pkm {
+
+void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const int32_t* idx,
+                   const double* Phi, double jitter, pkm_precond* pc, int aux);
+
+// ---------------------------------------------------------------------------
+// Host symmetric eigensolver: A (n x n, row-major, symmetric) -> eigenvalues
+// w (descending) and eigenvectors as the columns of Z (row-major n x n).
+// ---------------------------------------------------------------------------
+
+// Householder reduction: A = Q T Q^T with T tridiagonal (diagonal d, first
+// off-diagonal e, e[i] coupling i and i + 1); A is overwritten.
+static void tridiagonalize(int n, std::vector<double>& A, std::vector<double>& d,
+                           std::vector<double>& e, std::vector<double>& Q) {
+    Q.assign(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) Q[size_t(i) * n + i] = 1.0;
+    std::vector<double> v(n), p(n), w(n);
+    auto a = [&](int i, int j) -> double& { return A[size_t(i) * n + j]; };
+    for (int k = 0; k + 2 < n; ++k) {
+        double norm2 = 0.0;
+        for (int i = k + 1; i < n; ++i) norm2 += a(i, k) * a(i, k);
+        if (norm2 == 0.0) continue;
+        const double x0 = a(k + 1, k);
+        const double alpha = x0 > 0.0 ? -std::sqrt(norm2) : std::sqrt(norm2);
+        // v = (x - alpha e_1) / |x - alpha e_1| on rows k + 1 .. n - 1
+        v[k + 1] = x0 - alpha;
+        for (int i = k + 2; i < n; ++i) v[i] = a(i, k);
+        const double vn2 = norm2 - x0 * x0 + v[k + 1] * v[k + 1];
+        if (vn2 == 0.0) continue;
+        const double sc = 1.0 / std::sqrt(vn2);
+        for (int i = k + 1; i < n; ++i) v[i] *= sc;
+        // trailing block <- H A H = A - v w^T - w v^T, w = 2 A v - 2 (v^T A v) v
+        double vav = 0.0;
+        for (int i = k + 1; i < n; ++i) {
+            double s = 0.0;
+            for (int j = k + 1; j < n; ++j) s += a(i, j) * v[j];
+            p[i] = s;
+            vav += v[i] * s;
+        }
+        for (int i = k + 1; i < n; ++i) w[i] = 2.0 * (p[i] - vav * v[i]);
+        for (int i = k + 1; i < n; ++i)
+            for (int j = k + 1; j < n; ++j) a(i, j) -= v[i] * w[j] + w[i] * v[j];
+        a(k + 1, k) = a(k, k + 1) = alpha;
+        for (int i = k + 2; i < n; ++i) a(i, k) = a(k, i) = 0.0;
+        // Q <- Q H on columns k + 1 .. n - 1
+        for (int r = 0; r < n; ++r) {
+            double* qr = &Q[size_t(r) * n];
+            double t = 0.0;
+            for (int j = k + 1; j < n; ++j) t += qr[j] * v[j];
+            t *= 2.0;
+            for (int j = k + 1; j < n; ++j) qr[j] -= t * v[j];
+        }
+    }
+    d.resize(n);
+    e.assign(std::max(n - 1, 0), 0.0);
+    for (int i = 0; i < n; ++i) d[i] = a(i, i);
+    for (int i = 0; i + 1 < n; ++i) e[i] = a(i + 1, i);
+}
+
+// Implicit symmetric QR steps with Wilkinson shifts on the unreduced
+// trailing block until every off-diagonal has deflated; each rotation R on
+// (k, k + 1) (R [x; z] = [r; 0]) updates T <- R T R^T and Q <- Q R^T.
+static void tridiagonal_qr(int n, std::vector<double>& d, std::vector<double>& e,
+                           std::vector<double>& Q) {
+    const double eps = std::numeric_limits<double>::epsilon();
+    int hi = n - 1;
+    int64_t steps = 0;
+    while (hi > 0) {
+        for (int i = 0; i < hi; ++i)
+            if (std::fabs(e[i]) <= eps * (std::fabs(d[i]) + std::fabs(d[i + 1])) ||
+                std::fabs(e[i]) < std::numeric_limits<double>::min())
+                e[i] = 0.0;
+        while (hi > 0 && e[hi - 1] == 0.0) --hi;
+        if (hi == 0) break;
+        int lo = hi - 1;
+        while (lo > 0 && e[lo - 1] != 0.0) --lo;
+        PKM_REQUIRE(++steps <= int64_t(60) * n + 60, "symmetric eigensolver did not converge");
+        const double a = d[hi - 1], b = e[hi - 1], c = d[hi];
+        const double delta = 0.5 * (a - c);
+        const double den = delta + std::copysign(std::hypot(delta, b), delta == 0.0 ? 1.0 : delta);
+        const double mu = den != 0.0 ? c - b * b / den : c - std::fabs(b);
+        double x = d[lo] - mu, z = e[lo];
+        for (int k = lo; k < hi; ++k) {
+            const double r = std::hypot(x, z);
+            const double cs = r == 0.0 ? 1.0 : x / r, sn = r == 0.0 ? 0.0 : z / r;
+            if (k > lo) e[k - 1] = r;
+            const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+            d[k] = cs * cs * dk + 2.0 * cs * sn * ek + sn * sn * dk1;
+            d[k + 1] = sn * sn * dk - 2.0 * cs * sn * ek + cs * cs * dk1;
+            e[k] = cs * sn * (dk1 - dk) + (cs * cs - sn * sn) * ek;
+            if (k + 1 < hi) {   // the rotation pushes e[k + 1] into a bulge at (k, k + 2)
+                const double f = e[k + 1];
+                x = e[k];
+                z = sn * f;
+                e[k + 1] = cs * f;
+            }
+            for (int row = 0; row < n; ++row) {
+                double* q = &Q[size_t(row) * n];
+                const double qk = q[k], qk1 = q[k + 1];
+                q[k] = cs * qk + sn * qk1;
+                q[k + 1] = -sn * qk + cs * qk1;
+            }
+        }
+    }
+}
+
+void sym_eig_host(int n, const double* A, double* w, double* Z) {
+    std::vector<double> M(A, A + size_t(n) * n), d, e, Q;
+    for (int i = 0; i < n; ++i)   // symmetrise against rounding in the caller's matrix
+        for (int j = 0; j < i; ++j) M[size_t(i) * n + j] = M[size_t(j) * n + i] =
+            0.5 * (M[size_t(i) * n + j] + M[size_t(j) * n + i]);
+    tridiagonalize(n, M, d, e, Q);
+    tridiagonal_qr(n, d, e, Q);
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return d[x] > d[y]; });
+    for (int c = 0; c < n; ++c) {
+        w[c] = d[order[c]];
+        for (int r = 0; r < n; ++r) Z[size_t(r) * n + c] = Q[size_t(r) * n + order[c]];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Device orthonormalisation of Y (n x l, row-major) in place.
+// ---------------------------------------------------------------------------
+
+__global__ void k_add_diag_r(int64_t m, double* __restrict__ A, int64_t lda, double v) {
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i < m) A[i * lda + i] += v;
+}
+
+// One Cholesky QR pass: G = Y^T Y (+ shift I), G = L L^T, Y <- Y L^-T.
+// Returns false (Y untouched) when G is not positive definite.
+static bool cholqr_pass(pkm_ctx* ctx, int64_t n, int l, double* Y, double shift) {
+    hipStream_t s = ctx->stream;
+    ctx->ws_setup[0].ensure(sizeof(double) * int64_t(l) * l);
+    ctx->ws_setup[1].ensure(sizeof(double) * int64_t(round_up(l, 64)) * 64);
+    ctx->ws_setup[3].ensure(256);
+    double* G = ctx->ws_setup[0].as<double>();
+    double* winv = ctx->ws_setup[1].as<double>();
+    int* dinfo = ctx->ws_setup[3].as<int>();
+    dgemm(ctx, true, false, l, l, n, 1.0, Y, l, Y, l, 0.0, G, l);
+    if (shift > 0.0) {
+        k_add_diag_r<<<cdiv(l, 256), 256, 0, s>>>(l, G, l, shift);
+        PKM_CHECK_LAUNCH();
+    }
+    dpotrf_lower(ctx, l, G, l, winv, dinfo);
+    int hinfo = 0;
+    PKM_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+    PKM_HIP(hipStreamSynchronize(s));
+    if (hinfo != 0) return false;
+    dtrsm_right_lt(ctx, n, l, G, l, winv, Y, l);
+    return true;
+}
+
+// Shifted Cholesky QR, then two plain passes (CholeskyQR3 with a shift in
+// the first pass: the shift keeps the first factorisation defined for an
+// ill-conditioned or rank-deficient Y, the plain passes restore
+// orthonormality).  A later pass that finds G singular (a rank-deficient
+// sketch) is shifted by l u: the sketch's null directions then stay of
+// negligible norm, contributing nothing to Q B Q^T.
+static void orthonormalize(pkm_ctx* ctx, int64_t n, int l, double* Y) {
+    hipStream_t s = ctx->stream;
+    ctx->ws_setup[0].ensure(sizeof(double) * int64_t(l) * l);
+    double* G = ctx->ws_setup[0].as<double>();
+    dgemm(ctx, true, false, l, l, n, 1.0, Y, l, Y, l, 0.0, G, l);
+    std::vector<double> hg(size_t(l) * l);
+    PKM_HIP(hipMemcpyAsync(hg.data(), G, sizeof(double) * hg.size(), hipMemcpyDeviceToHost, s));
+    PKM_HIP(hipStreamSynchronize(s));
+    double trace = 0.0;
+    for (int i = 0; i < l; ++i) trace += hg[size_t(i) * l + i];
+    PKM_REQUIRE(std::isfinite(trace), "randomised SVD: non-finite sketch");
+    if (trace == 0.0) fail(PKM_ERR_BREAKDOWN, "randomised SVD: the sketch K Omega is zero");
+    const double u = std::numeric_limits<double>::epsilon() / 2;
+    const double shift = 11.0 * (double(n) * l + double(l) * (l + 1)) * u * trace;
+    if (!cholqr_pass(ctx, n, l, Y, shift))
+        fail(PKM_ERR_BREAKDOWN, "randomised SVD: shifted Cholesky QR failed");
+    for (int pass = 0; pass < 2; ++pass)
+        if (!cholqr_pass(ctx, n, l, Y, 0.0) && !cholqr_pass(ctx, n, l, Y, l * u))
+            fail(PKM_ERR_BREAKDOWN, "randomised SVD: Cholesky QR failed");
+}
+
+// ---------------------------------------------------------------------------
+// Setup
+// ---------------------------------------------------------------------------
+
+void precond_setup_rsvd(pkm_ctx* ctx, const pkm_problem* prob, int r, int l, const double* Omega,
+                        int q, int prec, pkm_precond* pc) {
+    const int64_t n = prob->n;
+    hipStream_t s = ctx->stream;
+    prepare(ctx, prob, true, prec != PKM_FP64);
+    ctx->ws_pitc[0].ensure(sizeof(double) * n * l);
+    ctx->ws_pitc[1].ensure(sizeof(double) * n * l);
+    double* Y = ctx->ws_pitc[0].as<double>();
+    double* W = ctx->ws_pitc[1].as<double>();
+    mvm_shift(ctx, prec, l, Omega, Y, 0.0);          // Y = K Omega
+    for (int it = 0; it < q; ++it) {
+        orthonormalize(ctx, n, l, Y);
+        mvm_shift(ctx, prec, l, Y, W, 0.0);          // W = K Q
+        PKM_HIP(hipMemcpyAsync(Y, W, sizeof(double) * n * l, hipMemcpyDeviceToDevice, s));
+    }
+    orthonormalize(ctx, n, l, Y);                    // Q
+    mvm_shift(ctx, prec, l, Y, W, 0.0);              // K Q
+    ctx->ws_setup[0].ensure(sizeof(double) * int64_t(l) * l);
+    double* B = ctx->ws_setup[0].as<double>();
+    dgemm(ctx, true, false, l, l, n, 1.0, Y, l, W, l, 0.0, B, l);   // Q^T K Q
+    std::vector<double> hb(size_t(l) * l), w(l), V(size_t(l) * l);
+    PKM_HIP(hipMemcpyAsync(hb.data(), B, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, s));
+    PKM_HIP(hipStreamSynchronize(s));
+    for (double v : hb) PKM_REQUIRE(std::isfinite(v), "randomised SVD: non-finite Q^T K Q");
+    sym_eig_host(l, hb.data(), w.data(), V.data());
+    // C = V_r diag(w_r)^1/2 (l x r), Phi = Q C (n x r)
+    std::vector<double> hc(size_t(l) * r);
+    for (int i = 0; i < l; ++i)
+        for (int c = 0; c < r; ++c) hc[size_t(i) * r + c] = V[size_t(i) * l + c] * std::sqrt(std::max(w[c], 0.0));
+    PKM_HIP(hipMemcpyAsync(B, hc.data(), sizeof(double) * hc.size(), hipMemcpyHostToDevice, s));
+    dgemm_large(ctx, false, false, n, r, l, 1.0, Y, l, B, r, 0.0, W, r);
+    PKM_HIP(hipStreamSynchronize(s));   // hc is pageable host memory
+    precond_setup(ctx, prob, PKM_PC_LOWRANK, r, nullptr, W, 0.0, pc, 0);
+}
+
+}  // namespace pkm

@@ -5,6 +5,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_1602_06693_amd import binding
@@ -102,3 +103,42 @@ def test_tune_cache_rejects_shapes_the_library_does_not_instantiate(tmp_path):
     assert binding.pkm_tune_cache_load(f) == (3, 6)
     with pytest.raises(binding.PkmError):
         binding.pkm_tune_cache_load(None)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 10, 64, 200])
+def test_host_eigensolver_matches_numpy(n):
+    """pkm_sym_eig (the randomised-SVD setup's host eigensolver) against
+    numpy's symmetric eigensolver: eigenvalues, orthonormal eigenvectors and
+    the residual A Z - Z diag(w).  Host-only, no GPU."""
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libpkm.so not built")
+    rng = np.random.default_rng(100 + n)
+    M = rng.standard_normal((n, n))
+    for A in (M + M.T, M @ M.T, np.diag(rng.standard_normal(n))):
+        w, Z = binding.pkm_sym_eig(A)
+        scale = max(np.abs(A).max(), 1e-300)
+        want = np.sort(np.linalg.eigvalsh(A))[::-1]
+        assert np.all(np.diff(w) <= 0)
+        assert np.allclose(w, want, rtol=0, atol=1e-12 * n * scale)
+        assert np.allclose(Z.T @ Z, np.eye(n), atol=1e-12 * n)
+        assert np.abs(A @ Z - Z * w).max() <= 1e-12 * n * scale
+
+
+def test_host_eigensolver_degenerate_spectra():
+    """Repeated eigenvalues (identity, a rank-1 matrix), the zero matrix and a
+    tridiagonal input: still an orthonormal eigenbasis with the right
+    eigenvalues.  Invalid input is rejected."""
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libpkm.so not built")
+    v = np.arange(1.0, 9.0)
+    T = np.diag(np.full(8, 2.0)) - np.diag(np.ones(7), 1) - np.diag(np.ones(7), -1)
+    for A, want in ((np.eye(8), np.ones(8)), (np.outer(v, v), np.r_[v @ v, np.zeros(7)]),
+                    (np.zeros((5, 5)), np.zeros(5)),
+                    (T, np.sort(2 - 2 * np.cos(np.arange(1, 9) * np.pi / 9))[::-1])):
+        w, Z = binding.pkm_sym_eig(A)
+        n = A.shape[0]
+        assert np.allclose(w, want, atol=1e-12 * max(1.0, np.abs(A).max()) * n)
+        assert np.allclose(Z.T @ Z, np.eye(n), atol=1e-12 * n)
+        assert np.abs(A @ Z - Z * w).max() <= 1e-11 * max(1.0, np.abs(A).max())
+    with pytest.raises(binding.PkmError):
+        binding.pkm_sym_eig(np.array([[np.nan]]))

@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 from gpu_util import GpuProblem, ctx, dev, host, rel_err  # noqa: F401
+from oracle import kernel as ok
 from oracle import precond as op
 from paper_1602_06693_amd import binding as pk
 from pkm_inputs import make
@@ -299,3 +300,124 @@ def test_psi_f32_rejects_bad_flag(ctx):
         assert rc == pk.PKM_ERR_INVALID
     finally:
         pk.pkm_precond_destroy(pc)
+
+
+# ---- randomised truncated SVD (Section 3.2) ---------------------------------
+
+def _rsvd_case(seed, n, d, ls, l):
+    rng = np.random.default_rng(seed)
+    X = rng.random((n, d))
+    Omega = rng.standard_normal((n, l))
+    R = rng.standard_normal((n, 5))
+    return X, np.full(d, ls), Omega, R
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_rsvd_apply_matches_oracle_without_truncation(ctx, q):
+    """r = l: P = Q Q^T K Q Q^T + lambda I depends only on span(K^(q+1) Omega),
+    so the GPU (FP64 products, Cholesky QR) and the oracle (Householder QR)
+    agree to within the span's sensitivity, ~u cond(Y) cond(P)."""
+    X, ls, Omega, R = _rsvd_case(40 + q, 600, 3, 0.3, 40)
+    lam, s2 = 1e-2, 1.1
+    prob = pk.Problem(dev(X), ls, s2, lam)
+    pc = pk.pkm_precond_setup_rsvd(ctx, prob, 40, dev(Omega), q=q, prec=pk.PKM_FP64)
+    try:
+        got = host(pk.pkm_precond_apply(ctx, pc, dev(R)))
+    finally:
+        pk.pkm_precond_destroy(pc)
+    P = op.rsvd(X, s2, ls, lam, Omega, r=40, q=q)
+    want = P(R)
+    K = ok.kernel_matrix(X, s2, ls)
+    Y = np.linalg.matrix_power(K, q + 1) @ Omega
+    tol = max(1e-11, 64 * 2.2e-16 * np.linalg.cond(Y) * np.linalg.cond(P.dense()))
+    assert np.all(rel_err(got, want) < tol), (rel_err(got, want), tol)
+
+
+def test_rsvd_truncation_with_a_spectral_gap(ctx):
+    """Eight tight clusters give eight dominant eigenvalues; r = 8 of l = 24
+    keeps exactly them (a wide gap makes the truncated factor well defined):
+    the GPU apply matches the oracle's."""
+    rng = np.random.default_rng(50)
+    centres = rng.random((8, 4))
+    X = np.repeat(centres, 60, axis=0) + 0.01 * rng.standard_normal((480, 4))
+    ls = np.full(4, 0.5)
+    Omega = rng.standard_normal((480, 24))
+    R = rng.standard_normal((480, 3))
+    lam, s2 = 5e-2, 1.0
+    prob = pk.Problem(dev(X), ls, s2, lam)
+    pc = pk.pkm_precond_setup_rsvd(ctx, prob, 8, dev(Omega), q=1, prec=pk.PKM_FP64)
+    try:
+        got = host(pk.pkm_precond_apply(ctx, pc, dev(R)))
+    finally:
+        pk.pkm_precond_destroy(pc)
+    want = op.rsvd(X, s2, ls, lam, Omega, r=8, q=1)(R)
+    assert np.all(rel_err(got, want) < 1e-8), rel_err(got, want)
+
+
+def test_rsvd_recovers_a_rank_deficient_kernel(ctx):
+    """Twelve distinct points, each repeated nine times: rank(K) = 12 < l = 16
+    (the sketch is rank-deficient, the Cholesky QR's later passes need their
+    fallback shift), and r = 14 reproduces K, so PCG converges in a few
+    steps."""
+    rng = np.random.default_rng(51)
+    X = np.repeat(rng.random((12, 3)), 9, axis=0)
+    ls = np.full(3, 0.4)
+    Omega = rng.standard_normal((108, 16))
+    lam, s2 = 1e-2, 1.3
+    prob = pk.Problem(dev(X), ls, s2, lam)
+    B = rng.standard_normal((108, 2))
+    pc = pk.pkm_precond_setup_rsvd(ctx, prob, 14, dev(Omega), q=0, prec=pk.PKM_FP64)
+    try:
+        Xs, info = pk.pkm_solve(ctx, prob, dev(B), pc=pc,
+                                opts=pk.make_opts(tol=1e-10, prec=pk.PKM_FP64),
+                                allow_warning=False)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    assert info.total_iters <= 4, info.total_iters
+    K = ok.kernel_matrix(X, s2, ls) + lam * np.eye(108)
+    assert np.allclose(host(Xs), np.linalg.solve(K, B), rtol=1e-8, atol=1e-10)
+
+
+def test_rsvd_solve_certifies_and_cuts_steps(ctx):
+    """Randomised SVD (r = 200 of l = 220, one power iteration, FP32 products
+    for the sketch) preconditioning an 8000-point solve of the smooth
+    learned-workload recipe (l = 0.5 on [0, 1]^8, lambda = 1e-3): certified
+    at 1e-6 and far fewer PCG steps than no preconditioner.  (Like every
+    low-rank preconditioner here it helps smooth kernels; on the rougher
+    65,536-point recipe it costs steps, as the paper finds for short
+    lengthscales.)"""
+    import dataclasses
+    p = dataclasses.replace(make("learned", seed=52, n=8000, m=200, n_probes=4), lam=1e-3)
+    g = GpuProblem(p)
+    Omega = dev(np.random.default_rng(53).standard_normal((p.n, 220)))
+    opts = pk.make_opts(tol=1e-6, prec=pk.PKM_FP32)
+    pc = pk.pkm_precond_setup_rsvd(ctx, g.prob, 200, Omega, q=1, prec=pk.PKM_FP32)
+    try:
+        _, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc, opts=opts)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    _, plain = pk.pkm_solve(ctx, g.prob, g.B, opts=opts)
+    pcn = pk.pkm_precond_setup(ctx, g.prob, pk.PKM_PC_NYSTROM, 200, idx=g.idx, jitter=JIT)
+    try:
+        _, nys = pk.pkm_solve(ctx, g.prob, g.B, pc=pcn, opts=opts)
+    finally:
+        pk.pkm_precond_destroy(pcn)
+    print(f"8000 points: randomised SVD r = 200: {info.total_iters} PCG steps, "
+          f"Nystrom m = 200: {nys.total_iters}, none: {plain.total_iters}")
+    assert np.all(info.col_status == pk.PKM_COL_CONVERGED)
+    assert np.all(info.relres_true <= 1e-6)
+    assert info.total_iters < 0.75 * plain.total_iters
+
+
+def test_rsvd_rejects_bad_arguments(ctx):
+    X, ls, Omega, _ = _rsvd_case(54, 100, 2, 0.3, 10)
+    prob = pk.Problem(dev(X), ls, 1.0, 1e-2)
+    Om = dev(Omega)
+    lib = pk.load()
+    out = pk.C.c_void_p()
+    for r, l, q in ((11, 10, 0), (0, 10, 0), (5, 10, 9), (5, 101, 0)):
+        rc = lib.pkm_precond_setup_rsvd(ctx, prob.ref, r, l, pk._ptr(Om), q, pk.PKM_FP64,
+                                        pk.C.byref(out))
+        assert rc == pk.PKM_ERR_INVALID, (r, l, q)
+    rc = lib.pkm_precond_setup_rsvd(ctx, prob.ref, 5, 10, None, 0, pk.PKM_FP64, pk.C.byref(out))
+    assert rc == pk.PKM_ERR_INVALID
