@@ -30,59 +30,95 @@ void precond_setup(pkm_ctx* ctx, const pkm_problem* prob, int kind, int m, const
 // ---------------------------------------------------------------------------
 
 // Householder reduction: A = Q T Q^T with T tridiagonal (diagonal d, first
-// off-diagonal e, e[i] coupling i and i + 1); A is overwritten.
-static void tridiagonalize(int n, std::vector<double>& A, std::vector<double>& d,
-                           std::vector<double>& e, std::vector<double>& Q) {
-    Q.assign(size_t(n) * n, 0.0);
-    for (int i = 0; i < n; ++i) Q[size_t(i) * n + i] = 1.0;
-    std::vector<double> v(n), p(n), w(n);
-    auto a = [&](int i, int j) -> double& { return A[size_t(i) * n + j]; };
+// off-diagonal e, e[i] coupling i and i + 1).  Only the lower triangle of A
+// is read and updated (A is overwritten); Qt = Q^T is formed afterwards by
+// applying the reflectors to the identity in reverse order, each touching
+// only its trailing block.
+static void tridiagonalize(int n, std::vector<double>& Avec, std::vector<double>& d,
+                           std::vector<double>& e, std::vector<double>& Qt) {
+    double* __restrict__ A = Avec.data();
+    d.assign(n, 0.0);
+    e.assign(std::max(n - 1, 0), 0.0);
+    std::vector<double> V(size_t(n) * n, 0.0);   // reflector k in row k, entries k + 1 .. n - 1
+    std::vector<char> has(n, 0);
+    std::vector<double> pbuf(n), wbuf(n);
+    double* __restrict__ p = pbuf.data();
+    double* __restrict__ w = wbuf.data();
     for (int k = 0; k + 2 < n; ++k) {
-        double norm2 = 0.0;
-        for (int i = k + 1; i < n; ++i) norm2 += a(i, k) * a(i, k);
-        if (norm2 == 0.0) continue;
-        const double x0 = a(k + 1, k);
-        const double alpha = x0 > 0.0 ? -std::sqrt(norm2) : std::sqrt(norm2);
+        d[k] = A[size_t(k) * n + k];
+        const double x0 = A[size_t(k + 1) * n + k];
+        double tail = 0.0;
+        for (int i = k + 2; i < n; ++i) tail += A[size_t(i) * n + k] * A[size_t(i) * n + k];
+        if (tail == 0.0) {   // column k is already tridiagonal
+            e[k] = x0;
+            continue;
+        }
+        const double alpha = -std::copysign(std::sqrt(x0 * x0 + tail), x0);
+        double* __restrict__ v = &V[size_t(k) * n];
         // v = (x - alpha e_1) / |x - alpha e_1| on rows k + 1 .. n - 1
         v[k + 1] = x0 - alpha;
-        for (int i = k + 2; i < n; ++i) v[i] = a(i, k);
-        const double vn2 = norm2 - x0 * x0 + v[k + 1] * v[k + 1];
-        if (vn2 == 0.0) continue;
-        const double sc = 1.0 / std::sqrt(vn2);
+        for (int i = k + 2; i < n; ++i) v[i] = A[size_t(i) * n + k];
+        const double sc = 1.0 / std::sqrt(v[k + 1] * v[k + 1] + tail);
         for (int i = k + 1; i < n; ++i) v[i] *= sc;
+        has[k] = 1;
+        e[k] = alpha;
+        // p = A v over the trailing block, one pass over its lower triangle
+        for (int i = k + 1; i < n; ++i) p[i] = 0.0;
+        for (int i = k + 1; i < n; ++i) {
+            const double* __restrict__ ai = &A[size_t(i) * n];
+            const double vi = v[i];
+            double s[4] = {0.0, 0.0, 0.0, 0.0};   // four partial sums: independent chains
+            int j = k + 1;
+            for (; j + 3 < i; j += 4)
+                for (int u = 0; u < 4; ++u) {
+                    s[u] += ai[j + u] * v[j + u];
+                    p[j + u] += ai[j + u] * vi;
+                }
+            for (; j < i; ++j) {
+                s[0] += ai[j] * v[j];
+                p[j] += ai[j] * vi;
+            }
+            p[i] += ((s[0] + s[1]) + (s[2] + s[3])) + ai[i] * vi;
+        }
         // trailing block <- H A H = A - v w^T - w v^T, w = 2 A v - 2 (v^T A v) v
         double vav = 0.0;
-        for (int i = k + 1; i < n; ++i) {
-            double s = 0.0;
-            for (int j = k + 1; j < n; ++j) s += a(i, j) * v[j];
-            p[i] = s;
-            vav += v[i] * s;
-        }
+        for (int i = k + 1; i < n; ++i) vav += v[i] * p[i];
         for (int i = k + 1; i < n; ++i) w[i] = 2.0 * (p[i] - vav * v[i]);
-        for (int i = k + 1; i < n; ++i)
-            for (int j = k + 1; j < n; ++j) a(i, j) -= v[i] * w[j] + w[i] * v[j];
-        a(k + 1, k) = a(k, k + 1) = alpha;
-        for (int i = k + 2; i < n; ++i) a(i, k) = a(k, i) = 0.0;
-        // Q <- Q H on columns k + 1 .. n - 1
-        for (int r = 0; r < n; ++r) {
-            double* qr = &Q[size_t(r) * n];
-            double t = 0.0;
-            for (int j = k + 1; j < n; ++j) t += qr[j] * v[j];
-            t *= 2.0;
-            for (int j = k + 1; j < n; ++j) qr[j] -= t * v[j];
+        for (int i = k + 1; i < n; ++i) {
+            double* __restrict__ ai = &A[size_t(i) * n];
+            const double vi = v[i], wi = w[i];
+            for (int j = k + 1; j <= i; ++j) ai[j] -= vi * w[j] + wi * v[j];
         }
     }
-    d.resize(n);
-    e.assign(std::max(n - 1, 0), 0.0);
-    for (int i = 0; i < n; ++i) d[i] = a(i, i);
-    for (int i = 0; i + 1 < n; ++i) e[i] = a(i + 1, i);
+    for (int k = std::max(n - 2, 0); k < n; ++k) d[k] = A[size_t(k) * n + k];
+    if (n >= 2) e[n - 2] = A[size_t(n - 1) * n + (n - 2)];
+    // Qt = H_{n-3} ... H_0: right-multiply the identity by H_k for k
+    // descending; H_k changes rows k + 1 .. n - 1 on columns k + 1 .. n - 1
+    Qt.assign(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) Qt[size_t(i) * n + i] = 1.0;
+    for (int k = n - 3; k >= 0; --k) {
+        if (!has[k]) continue;
+        const double* __restrict__ v = &V[size_t(k) * n];
+        for (int i = k + 1; i < n; ++i) {
+            double* __restrict__ qi = &Qt[size_t(i) * n];
+            double s[4] = {0.0, 0.0, 0.0, 0.0};
+            int j = k + 1;
+            for (; j + 3 < n; j += 4)
+                for (int u = 0; u < 4; ++u) s[u] += qi[j + u] * v[j + u];
+            for (; j < n; ++j) s[0] += qi[j] * v[j];
+            const double t = 2.0 * ((s[0] + s[1]) + (s[2] + s[3]));
+            for (int j = k + 1; j < n; ++j) qi[j] -= t * v[j];
+        }
+    }
 }
 
 // Implicit symmetric QR steps with Wilkinson shifts on the unreduced
 // trailing block until every off-diagonal has deflated; each rotation R on
-// (k, k + 1) (R [x; z] = [r; 0]) updates T <- R T R^T and Q <- Q R^T.
+// (k, k + 1) (R [x; z] = [r; 0]) updates T <- R T R^T and Q <- Q R^T.  Q is
+// held transposed (Qt, row c = column c of Q), so that a rotation combines
+// two contiguous rows.
 static void tridiagonal_qr(int n, std::vector<double>& d, std::vector<double>& e,
-                           std::vector<double>& Q) {
+                           std::vector<double>& Qt) {
     const double eps = std::numeric_limits<double>::epsilon();
     int hi = n - 1;
     int64_t steps = 0;
@@ -115,29 +151,30 @@ static void tridiagonal_qr(int n, std::vector<double>& d, std::vector<double>& e
                 z = sn * f;
                 e[k + 1] = cs * f;
             }
+            double* __restrict__ q0 = &Qt[size_t(k) * n];
+            double* __restrict__ q1 = &Qt[size_t(k + 1) * n];
             for (int row = 0; row < n; ++row) {
-                double* q = &Q[size_t(row) * n];
-                const double qk = q[k], qk1 = q[k + 1];
-                q[k] = cs * qk + sn * qk1;
-                q[k + 1] = -sn * qk + cs * qk1;
+                const double qk = q0[row], qk1 = q1[row];
+                q0[row] = cs * qk + sn * qk1;
+                q1[row] = -sn * qk + cs * qk1;
             }
         }
     }
 }
 
 void sym_eig_host(int n, const double* A, double* w, double* Z) {
-    std::vector<double> M(A, A + size_t(n) * n), d, e, Q;
+    std::vector<double> M(A, A + size_t(n) * n), d, e, Qt;
     for (int i = 0; i < n; ++i)   // symmetrise against rounding in the caller's matrix
         for (int j = 0; j < i; ++j) M[size_t(i) * n + j] = M[size_t(j) * n + i] =
             0.5 * (M[size_t(i) * n + j] + M[size_t(j) * n + i]);
-    tridiagonalize(n, M, d, e, Q);
-    tridiagonal_qr(n, d, e, Q);
+    tridiagonalize(n, M, d, e, Qt);
+    tridiagonal_qr(n, d, e, Qt);
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return d[x] > d[y]; });
     for (int c = 0; c < n; ++c) {
         w[c] = d[order[c]];
-        for (int r = 0; r < n; ++r) Z[size_t(r) * n + c] = Q[size_t(r) * n + order[c]];
+        for (int r = 0; r < n; ++r) Z[size_t(r) * n + c] = Qt[size_t(order[c]) * n + r];
     }
 }
 
