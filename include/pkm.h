@@ -265,8 +265,9 @@ int pkm_precond_setup_rsvd(pkm_ctx* ctx, const pkm_problem* prob, int32_t r, int
  * eigenvectors (the columns of Z, row-major n x n) of the symmetric n x n
  * host matrix A (row-major; its symmetric part is used), by Householder
  * tridiagonalisation and implicit QR steps with Wilkinson shifts -- the
- * eigensolver of pkm_precond_setup_rsvd.  1 <= n <= 4096, finite A, else
- * PKM_ERR_INVALID.                                                         */
+ * eigensolver of pkm_precond_setup_rsvd.  The eigenvector rotations run on
+ * up to 16 host threads (PKM_EIG_THREADS in the environment sets the
+ * count).  1 <= n <= 4096, finite A, else PKM_ERR_INVALID.                 */
 int pkm_sym_eig(int32_t n, const double* A, double* w, double* Z);
 int pkm_precond_apply(pkm_ctx* ctx, const pkm_precond* pc, int32_t k,
                       const double* R, double* Z);

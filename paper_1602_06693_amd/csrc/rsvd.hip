@@ -14,9 +14,13 @@
 #include "pkm_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <limits>
+#include <memory>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 namespace pkm {
@@ -112,13 +116,65 @@ static void tridiagonalize(int n, std::vector<double>& Avec, std::vector<double>
     }
 }
 
+struct Rotation {
+    int k;
+    double c, s;
+};
+
+// Applies the rotations in order to Qt (n x n, row-major): rotation (k, c, s)
+// replaces rows k, k + 1 by (c q_k + s q_k1, -s q_k + c q_k1).  Every column
+// of Qt is rotated on its own, so blocks of 64 columns are handed to host
+// threads (PKM_EIG_THREADS of them if set, else up to 16), each running the
+// whole sequence over its block (which stays in cache); the rows are padded
+// to 64-byte multiples so that no two threads write one cache line.
+static void apply_rotations(int n, const std::vector<Rotation>& rots, std::vector<double>& Qt) {
+    if (rots.empty()) return;
+    constexpr int kCols = 64;
+    const int ld = (n + 7) / 8 * 8;
+    std::unique_ptr<double, void (*)(void*)> buf(
+        static_cast<double*>(std::aligned_alloc(64, sizeof(double) * size_t(ld) * n)), std::free);
+    PKM_REQUIRE(buf != nullptr, "host eigensolver: out of memory");
+    double* P = buf.get();
+    for (int i = 0; i < n; ++i)
+        std::copy(&Qt[size_t(i) * n], &Qt[size_t(i) * n] + n, P + size_t(i) * ld);
+    const int nblocks = (n + kCols - 1) / kCols;
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        for (int b; (b = next.fetch_add(1)) < nblocks;) {
+            const int c0 = b * kCols, c1 = std::min(n, c0 + kCols);
+            for (const Rotation& R : rots) {
+                double* __restrict__ q0 = P + size_t(R.k) * ld;
+                double* __restrict__ q1 = q0 + ld;
+                const double c = R.c, s = R.s;
+                for (int j = c0; j < c1; ++j) {
+                    const double a = q0[j], b2 = q1[j];
+                    q0[j] = c * a + s * b2;
+                    q1[j] = -s * a + c * b2;
+                }
+            }
+        }
+    };
+    int want = std::min(16, int(std::max(1u, std::thread::hardware_concurrency())));
+    if (const char* env = std::getenv("PKM_EIG_THREADS")) want = std::max(1, std::atoi(env));
+    const int nt = std::min({want, nblocks,
+                             int(std::max<size_t>(1, rots.size() * size_t(n) / (size_t(1) << 22)))});
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+    for (int i = 0; i < n; ++i)
+        std::copy(P + size_t(i) * ld, P + size_t(i) * ld + n, &Qt[size_t(i) * n]);
+}
+
 // Implicit symmetric QR steps with Wilkinson shifts on the unreduced
 // trailing block until every off-diagonal has deflated; each rotation R on
 // (k, k + 1) (R [x; z] = [r; 0]) updates T <- R T R^T and Q <- Q R^T.  Q is
-// held transposed (Qt, row c = column c of Q), so that a rotation combines
-// two contiguous rows.
+// held transposed (Qt, row c = column c of Q); the rotations are recorded
+// while T is reduced and applied to Qt afterwards, in order.
 static void tridiagonal_qr(int n, std::vector<double>& d, std::vector<double>& e,
                            std::vector<double>& Qt) {
+    std::vector<Rotation> rots;
+    rots.reserve(size_t(n) * n + 16);
     const double eps = std::numeric_limits<double>::epsilon();
     int hi = n - 1;
     int64_t steps = 0;
@@ -151,15 +207,10 @@ static void tridiagonal_qr(int n, std::vector<double>& d, std::vector<double>& e
                 z = sn * f;
                 e[k + 1] = cs * f;
             }
-            double* __restrict__ q0 = &Qt[size_t(k) * n];
-            double* __restrict__ q1 = &Qt[size_t(k + 1) * n];
-            for (int row = 0; row < n; ++row) {
-                const double qk = q0[row], qk1 = q1[row];
-                q0[row] = cs * qk + sn * qk1;
-                q1[row] = -sn * qk + cs * qk1;
-            }
+            rots.push_back(Rotation{k, cs, sn});
         }
     }
+    apply_rotations(n, rots, Qt);
 }
 
 void sym_eig_host(int n, const double* A, double* w, double* Z) {

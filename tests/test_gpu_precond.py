@@ -378,9 +378,10 @@ def test_rsvd_recovers_a_rank_deficient_kernel(ctx):
     assert np.allclose(host(Xs), np.linalg.solve(K, B), rtol=1e-8, atol=1e-10)
 
 
-def test_rsvd_solve_certifies_and_cuts_steps(ctx):
-    """Randomised SVD (r = 200 of l = 220, one power iteration, FP32 products
-    for the sketch) preconditioning an 8000-point solve of the smooth
+@pytest.mark.parametrize("sketch_prec", ["fp32", "f16x3"])
+def test_rsvd_solve_certifies_and_cuts_steps(ctx, sketch_prec):
+    """Randomised SVD (r = 200 of l = 220, one power iteration, FP32 or FP16x3
+    products for the sketch, two passes of 110 columns) preconditioning an 8000-point solve of the smooth
     learned-workload recipe (l = 0.5 on [0, 1]^8, lambda = 1e-3): certified
     at 1e-6 and far fewer PCG steps than no preconditioner.  (Like every
     low-rank preconditioner here it helps smooth kernels; on the rougher
@@ -391,7 +392,8 @@ def test_rsvd_solve_certifies_and_cuts_steps(ctx):
     g = GpuProblem(p)
     Omega = dev(np.random.default_rng(53).standard_normal((p.n, 220)))
     opts = pk.make_opts(tol=1e-6, prec=pk.PKM_FP32)
-    pc = pk.pkm_precond_setup_rsvd(ctx, g.prob, 200, Omega, q=1, prec=pk.PKM_FP32)
+    sp = {"fp32": pk.PKM_FP32, "f16x3": pk.PKM_F16X3}[sketch_prec]
+    pc = pk.pkm_precond_setup_rsvd(ctx, g.prob, 200, Omega, q=1, prec=sp)
     try:
         _, info = pk.pkm_solve(ctx, g.prob, g.B, pc=pc, opts=opts)
     finally:
@@ -402,7 +404,7 @@ def test_rsvd_solve_certifies_and_cuts_steps(ctx):
         _, nys = pk.pkm_solve(ctx, g.prob, g.B, pc=pcn, opts=opts)
     finally:
         pk.pkm_precond_destroy(pcn)
-    print(f"8000 points: randomised SVD r = 200: {info.total_iters} PCG steps, "
+    print(f"8000 points: randomised SVD r = 200 ({sketch_prec} sketch): {info.total_iters} PCG steps, "
           f"Nystrom m = 200: {nys.total_iters}, none: {plain.total_iters}")
     assert np.all(info.col_status == pk.PKM_COL_CONVERGED)
     assert np.all(info.relres_true <= 1e-6)
