@@ -159,7 +159,10 @@ static void apply_rotations(int n, const std::vector<Rotation>& rots, std::vecto
     const int nt = std::min({want, nblocks,
                              int(std::max<size_t>(1, rots.size() * size_t(n) / (size_t(1) << 22)))});
     std::vector<std::thread> pool;
-    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    try {
+        for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    } catch (...) {   // fewer threads: the started ones and this one share the blocks
+    }
     work();
     for (auto& th : pool) th.join();
     for (int i = 0; i < n; ++i)

@@ -3,7 +3,8 @@
 child process with the ASan runtime preloaded, and the host-only entry points
 run through their valid and invalid inputs -- ADAGRAD steps, tuning-cache
 files with malformed and oversized lines, error strings, object lifetimes
-with NULL handles, context creation without a device.  Any sanitizer report
+with NULL handles, context creation without a device, the threaded host
+eigensolver.  Any sanitizer report
 aborts the child (UBSan does not recover)."""
 import os
 import subprocess
@@ -62,6 +63,24 @@ CHILD = textwrap.dedent(r'''
     assert lib.pkm_lml_grad(None, None, None, None, 1, None, None, None, None, None) \
         == pk.PKM_ERR_INVALID
     assert lib.pkm_kernel_mvm_noalloc(None, None, 1, pk.PKM_I8X, None, None) == pk.PKM_ERR_INVALID
+    # host eigensolver: sizes around the 64-column blocks of its threaded
+    # rotation pass, a degenerate spectrum, rejected inputs
+    rng = np.random.default_rng(0)
+    for m in (1, 2, 3, 63, 65, 130):
+        A = rng.standard_normal((m, m)); A = A + A.T
+        w, Z = pk.pkm_sym_eig(A)
+        assert np.abs(Z @ np.diag(w) @ Z.T - A).max() < 1e-10 * max(1.0, np.abs(A).max())
+    w, Z = pk.pkm_sym_eig(np.eye(70))
+    assert np.allclose(w, 1.0) and np.allclose(Z.T @ Z, np.eye(70))
+    os.environ["PKM_EIG_THREADS"] = "3"
+    A = rng.standard_normal((200, 200)); A = A + A.T
+    w, Z = pk.pkm_sym_eig(A)
+    assert np.abs(Z @ np.diag(w) @ Z.T - A).max() < 1e-10 * np.abs(A).max()
+    w0, Z0 = np.zeros(4), np.zeros(16)
+    bad = np.full(16, np.nan)
+    assert lib.pkm_sym_eig(4, bad.ctypes.data_as(P), w0.ctypes.data_as(P),
+                           Z0.ctypes.data_as(P)) == pk.PKM_ERR_INVALID
+    assert lib.pkm_sym_eig(0, None, None, None) == pk.PKM_ERR_INVALID
     print("host sanitizer run clean")
 ''')
 
