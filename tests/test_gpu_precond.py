@@ -378,6 +378,35 @@ def test_rsvd_recovers_a_rank_deficient_kernel(ctx):
     assert np.allclose(host(Xs), np.linalg.solve(K, B), rtol=1e-8, atol=1e-10)
 
 
+@pytest.mark.parametrize("n", [1, 17, 300])
+def test_rsvd_full_sketch_is_exact(ctx, n):
+    """l = r = n (one point, a ragged 17, several MFMA tiles): Q spans the
+    whole space, so P = Q (Q^T K Q) Q^T + lambda I is K + lambda I up to
+    rounding; its apply is the dense solve and PCG stops after one or two
+    steps."""
+    rng = np.random.default_rng(60 + n)
+    X = rng.random((n, 2))
+    ls = np.array([0.5, 0.7])
+    lam, s2 = 1e-2, 1.2
+    Omega = rng.standard_normal((n, n))
+    R = rng.standard_normal((n, 3))
+    prob = pk.Problem(dev(X), ls, s2, lam)
+    pc = pk.pkm_precond_setup_rsvd(ctx, prob, n, dev(Omega), q=0, prec=pk.PKM_FP64)
+    try:
+        got = host(pk.pkm_precond_apply(ctx, pc, dev(R)))
+        Xs, info = pk.pkm_solve(ctx, prob, dev(R), pc=pc,
+                                opts=pk.make_opts(tol=1e-9, prec=pk.PKM_FP64),
+                                allow_warning=False)
+    finally:
+        pk.pkm_precond_destroy(pc)
+    Ky = ok.kernel_matrix(X, s2, ls) + lam * np.eye(n)
+    want = np.linalg.solve(Ky, R)
+    assert np.all(rel_err(got, want) < 1e-8), rel_err(got, want)
+    assert np.all(info.col_status == pk.PKM_COL_CONVERGED)
+    assert info.total_iters <= 2 * 3, info.total_iters
+    assert np.allclose(host(Xs), want, rtol=1e-7, atol=1e-9)
+
+
 @pytest.mark.parametrize("sketch_prec", ["fp32", "f16x3"])
 def test_rsvd_solve_certifies_and_cuts_steps(ctx, sketch_prec):
     """Randomised SVD (r = 200 of l = 220, one power iteration, FP32 or FP16x3
