@@ -20,6 +20,8 @@ Cunningham and Filippone, ICML 2016) by eye:
             backward and Adam (not in the paper; a low-rank
             factor of the Section 3.2 form learned from data)
   adagrad   ADAGRAD ascent on log-hyperparameters              -- Section 5
+  rng       counter-based SplitMix64 Rademacher probes (the
+            published generator, for the Section 2.1 estimate)
 
 Parity status per function is stated in each module header.
 """
