@@ -261,6 +261,19 @@ int pkm_precond_setup_spectral(pkm_ctx* ctx, const pkm_problem* prob, int32_t m,
 int pkm_precond_setup_rsvd(pkm_ctx* ctx, const pkm_problem* prob, int32_t r, int32_t l,
                            const double* Omega, int32_t q, int32_t prec,
                            pkm_precond** out);
+/* Rademacher probes for the stochastic trace estimate (Section 2.1) on the
+ * device, from the SplitMix64 generator (Steele, Lea and Flood 2014):
+ * seeded with `seed`, output t >= 1 is mix(seed + t * 0x9E3779B97F4A7C15
+ * mod 2^64) with the reference finaliser (xor-shift 30, multiply by
+ * 0xBF58476D1CE4E5B9, xor-shift 27, multiply by 0x94D049BB133111EB,
+ * xor-shift 31); Z[i * ldz + c] (device, n x ncols row-major with leading
+ * dimension ldz, FP64) is -1 if output i * ncols + c + 1 has its top bit
+ * set, else +1.  Asynchronous on the context's stream; entries of a row
+ * beyond ncols are not written.  1 <= n <= 2^36, 1 <= ncols <= 4096,
+ * ldz >= ncols, else PKM_ERR_INVALID.  (The other calls take probes from
+ * the caller; this is an optional source of them.)                       */
+int pkm_rademacher(pkm_ctx* ctx, int64_t n, int32_t ncols, uint64_t seed, double* Z,
+                   int64_t ldz);
 /* Host utility (no device work, no context): eigenvalues w (descending) and
  * eigenvectors (the columns of Z, row-major n x n) of the symmetric n x n
  * host matrix A (row-major; its symmetric part is used), by Householder

@@ -55,7 +55,7 @@ EXPORTS = (
     "pkm_mvm_stats_reset", "pkm_mlp_create", "pkm_mlp_destroy", "pkm_mlp_params",
     "pkm_mlp_forward", "pkm_mlp_loss_grad", "pkm_mlp_train_step", "pkm_adagrad_step",
     "pkm_mlp_nparams", "pkm_mlp_state_get", "pkm_mlp_state_set", "pkm_precond_psi_f32",
-    "pkm_precond_setup_rsvd", "pkm_sym_eig",
+    "pkm_precond_setup_rsvd", "pkm_sym_eig", "pkm_rademacher",
     "pkm_tune_cache_load",
 )
 
@@ -123,6 +123,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "pkm_precond_psi_f32": (C.c_int, [vp, vp, i32]),
         "pkm_precond_setup_rsvd": (C.c_int, [vp, P(pkm_problem), i32, i32, vp, i32, i32, P(vp)]),
         "pkm_sym_eig": (C.c_int, [i32, P(dbl), P(dbl), P(dbl)]),
+        "pkm_rademacher": (C.c_int, [vp, i64, i32, C.c_uint64, vp, i64]),
         "pkm_solve": (C.c_int, [vp, P(pkm_problem), vp, i32, vp, vp, P(pkm_solve_opts),
                                 P(pkm_solve_info)]),
         "pkm_solve_batched": (C.c_int, [vp, i32, P(pkm_problem), P(vp), i32, P(vp), P(vp),
@@ -307,6 +308,17 @@ def pkm_precond_setup_rsvd(ctx, prob: Problem, r, Omega, q=0, prec=PKM_FP32):
     _check(load().pkm_precond_setup_rsvd(ctx, prob.ref, int(r), int(Omega.shape[1]), _ptr(Omega),
                                          int(q), int(prec), C.byref(out)), ctx)
     return out
+
+
+def pkm_rademacher(ctx, n, ncols, seed, Z=None):
+    """n x ncols FP64 +-1 block from the device SplitMix64 generator, written
+    into the first ncols columns of Z (contiguous n x ldz, ldz >= ncols)."""
+    import torch
+    if Z is None:
+        Z = torch.empty((n, ncols), dtype=torch.float64, device="cuda")
+    _check(load().pkm_rademacher(ctx, int(n), int(ncols), int(seed) & ((1 << 64) - 1), _ptr(Z),
+                                 int(Z.shape[1])), ctx)
+    return Z
 
 
 def pkm_sym_eig(A):

@@ -16,6 +16,7 @@ void precond_psi_f32(pkm_ctx* ctx, pkm_precond* pc, bool on);
 void precond_setup_rsvd(pkm_ctx* ctx, const pkm_problem* prob, int r, int l, const double* Omega,
                         int q, int prec, pkm_precond* pc);
 void sym_eig_host(int n, const double* A, double* w, double* Z);
+void rademacher(pkm_ctx* ctx, int64_t n, int ncols, uint64_t seed, double* Z, int64_t ldz);
 int laplace_mode(pkm_ctx* ctx, const pkm_problem* prob, const pkm_precond* base, const double* y,
                  const pkm_solve_opts* o, int max_newton, double tol, double* f, double* a,
                  pkm_laplace_info* info);
@@ -351,6 +352,19 @@ int pkm_precond_setup_rsvd(pkm_ctx* ctx, const pkm_problem* prob, int32_t r, int
     }
     *out = pc;
     return PKM_OK;
+}
+
+int pkm_rademacher(pkm_ctx* ctx, int64_t n, int32_t ncols, uint64_t seed, double* Z,
+                   int64_t ldz) {
+    if (!ctx) return PKM_ERR_INVALID;
+    return guarded(ctx, [&] {
+        PKM_REQUIRE(n >= 1 && n <= (int64_t(1) << 36), "n must be in [1, 2^36]");
+        PKM_REQUIRE(ncols >= 1 && ncols <= 4096, "ncols must be in [1, 4096]");
+        PKM_REQUIRE(ldz >= ncols, "ldz must be >= ncols");
+        require_dev(Z, "Z");
+        rademacher(ctx, n, ncols, seed, Z, ldz);
+        return PKM_OK;
+    });
 }
 
 int pkm_sym_eig(int32_t n, const double* A, double* w, double* Z) {

@@ -1,0 +1,47 @@
+"""Device SplitMix64 Rademacher probes against the oracle's generator, bit for
+bit (every element is a sign, so the comparison is exact)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import rng as orng
+from paper_1602_06693_amd import binding as pk
+
+from gpu_util import ctx, host  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,ncols,seed", [(1, 1, 0), (17, 5, 1234567), (1000, 16, 2**63 + 11),
+                                          (4097, 65, 2**64 - 1), (300, 130, 42)])
+def test_probes_match_oracle(ctx, n, ncols, seed):
+    Z = host(pk.pkm_rademacher(ctx, n, ncols, seed))
+    assert np.array_equal(Z, orng.rademacher(n, ncols, seed))
+
+
+def test_leading_dimension_leaves_padding_untouched(ctx):
+    Z = torch.full((333, 40), 7.0, dtype=torch.float64, device="cuda")
+    pk.pkm_rademacher(ctx, 333, 33, 99, Z)
+    Zh = host(Z)
+    assert np.array_equal(Zh[:, :33], orng.rademacher(333, 33, 99))
+    assert np.all(Zh[:, 33:] == 7.0)
+
+
+def test_full_size_probe_block_on_sampled_rows(ctx):
+    """The 131,072 x 16 probe block of the largest learned workload: sampled
+    rows against the oracle's counter form, and the signs' balance."""
+    n, nc, seed = 131072, 16, 2024
+    Zh = host(pk.pkm_rademacher(ctx, n, nc, seed))
+    rows = np.random.default_rng(0).choice(n, 64, replace=False)
+    t = rows[:, None].astype(np.uint64) * np.uint64(nc) + np.arange(nc, dtype=np.uint64) + np.uint64(1)
+    want = np.where((orng.splitmix64_at(seed, t) >> np.uint64(63)) == 1, -1.0, 1.0)
+    assert np.array_equal(Zh[rows], want)
+    assert abs(Zh.mean()) < 4 / np.sqrt(Zh.size)
+
+
+def test_rejects_bad_arguments(ctx):
+    lib = pk.load()
+    Z = torch.empty((4, 4), dtype=torch.float64, device="cuda")
+    for n, nc, ldz in ((0, 1, 1), (4, 0, 4), (4, 5, 4), (4, 4097, 4097)):
+        assert lib.pkm_rademacher(ctx, n, nc, 0, pk._ptr(Z), ldz) == pk.PKM_ERR_INVALID
+    assert lib.pkm_rademacher(ctx, 4, 4, 0, None, 4) == pk.PKM_ERR_INVALID
