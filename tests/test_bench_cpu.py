@@ -36,7 +36,7 @@ def test_recorded_traffic_only_for_the_measured_configuration():
 
         class B:
             shape = (65536, 17)
-    assert bench._recorded_traffic(P, "f16x3") == pytest.approx((41863.0 * 2.0 + 34816.0) * 1024)
+    assert bench._recorded_traffic(P, "f16x3") == pytest.approx((41858.1 * 2.0 + 34816.0) * 1024)
     assert bench._recorded_traffic(P, "bf16x3") is None
     P.n = 4096
     assert bench._recorded_traffic(P, "f16x3") is None
