@@ -5,7 +5,7 @@ import pytest
 
 def torch_cuda():
     import torch
-    assert torch.cuda.is_available(), "GPU tests need a GPU (run them with -m gpu on a GPU box)"
+    assert torch.cuda.is_available(), "GPU tests need a GPU (select them with -m gpu on a machine with an MI355X)"
     return torch
 
 
