@@ -269,7 +269,7 @@ int pkm_precond_setup_rsvd(pkm_ctx* ctx, const pkm_problem* prob, int32_t r, int
  * xor-shift 31); Z[i * ldz + c] (device, n x ncols row-major with leading
  * dimension ldz, FP64) is -1 if output i * ncols + c + 1 has its top bit
  * set, else +1.  Asynchronous on the context's stream; entries of a row
- * beyond ncols are not written.  1 <= n <= 2^36, 1 <= ncols <= 4096,
+ * beyond ncols are not written.  1 <= n <= 2^32, 1 <= ncols <= 4096,
  * ldz >= ncols, else PKM_ERR_INVALID.  (The other calls take probes from
  * the caller; this is an optional source of them.)                       */
 int pkm_rademacher(pkm_ctx* ctx, int64_t n, int32_t ncols, uint64_t seed, double* Z,

@@ -358,7 +358,7 @@ int pkm_rademacher(pkm_ctx* ctx, int64_t n, int32_t ncols, uint64_t seed, double
                    int64_t ldz) {
     if (!ctx) return PKM_ERR_INVALID;
     return guarded(ctx, [&] {
-        PKM_REQUIRE(n >= 1 && n <= (int64_t(1) << 36), "n must be in [1, 2^36]");
+        PKM_REQUIRE(n >= 1 && n <= (int64_t(1) << 32), "n must be in [1, 2^32]");
         PKM_REQUIRE(ncols >= 1 && ncols <= 4096, "ncols must be in [1, 4096]");
         PKM_REQUIRE(ldz >= ncols, "ldz must be >= ncols");
         require_dev(Z, "Z");

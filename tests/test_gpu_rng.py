@@ -42,6 +42,6 @@ def test_full_size_probe_block_on_sampled_rows(ctx):
 def test_rejects_bad_arguments(ctx):
     lib = pk.load()
     Z = torch.empty((4, 4), dtype=torch.float64, device="cuda")
-    for n, nc, ldz in ((0, 1, 1), (4, 0, 4), (4, 5, 4), (4, 4097, 4097)):
+    for n, nc, ldz in ((0, 1, 1), (4, 0, 4), (4, 5, 4), (4, 4097, 4097), (2**32 + 1, 1, 1)):
         assert lib.pkm_rademacher(ctx, n, nc, 0, pk._ptr(Z), ldz) == pk.PKM_ERR_INVALID
     assert lib.pkm_rademacher(ctx, 4, 4, 0, None, 4) == pk.PKM_ERR_INVALID
