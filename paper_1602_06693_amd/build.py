@@ -1,6 +1,6 @@
 """Build libpkm.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_1602_06693_amd.build [--jobs N] [--host-sanitize]
+    python -m paper_1602_06693_amd.build [--jobs N] [--host-sanitize | --host-tsan]
 
 Every translation unit under csrc/ is compiled to an object under _build/
 and linked into paper_1602_06693_amd/libpkm.so.  Always recompiles.
@@ -9,7 +9,9 @@ and linked into paper_1602_06693_amd/libpkm.so.  Always recompiles.
 code instrumented with AddressSanitizer and UndefinedBehaviorSanitizer
 (device code unchanged), for tests of the host-side logic on a machine
 without a GPU.  Load it with the compiler's ASan runtime preloaded
-(hostsan_runtime() names it).
+(hostsan_runtime() names it).  --host-tsan builds
+_build/hosttsan/libpkm_hosttsan.so with ThreadSanitizer in the host code,
+for a program built with -fsanitize=thread that links it.
 """
 from __future__ import annotations
 
@@ -48,6 +50,14 @@ HOSTSAN_FLAGS = [
 ]
 HOSTSAN_DIR = os.path.join(OBJ, "hostsan")
 HOSTSAN_LIB = os.path.join(HOSTSAN_DIR, "libpkm_hostsan.so")
+# ThreadSanitizer, also host code only (the eigensolver's worker threads);
+# the program that loads this library must itself be built with it
+HOSTTSAN_FLAGS = [
+    "-Xarch_host", "-fsanitize=thread", "-Xarch_host", "-fno-omit-frame-pointer",
+    "-Xarch_host", "-g",
+]
+HOSTTSAN_DIR = os.path.join(OBJ, "hosttsan")
+HOSTTSAN_LIB = os.path.join(HOSTTSAN_DIR, "libpkm_hosttsan.so")
 
 
 def hostsan_runtime():
@@ -74,10 +84,12 @@ def _compile(src, outdir=OBJ, extra=()):
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False, host_sanitize: bool = False) -> str:
-    outdir = HOSTSAN_DIR if host_sanitize else OBJ
-    lib = HOSTSAN_LIB if host_sanitize else LIB
-    extra = HOSTSAN_FLAGS if host_sanitize else ()
+def build(jobs: int | None = None, verbose: bool = False, host_sanitize: bool = False,
+          host_tsan: bool = False) -> str:
+    assert not (host_sanitize and host_tsan), "one sanitizer build at a time"
+    outdir = HOSTSAN_DIR if host_sanitize else HOSTTSAN_DIR if host_tsan else OBJ
+    lib = HOSTSAN_LIB if host_sanitize else HOSTTSAN_LIB if host_tsan else LIB
+    extra = HOSTSAN_FLAGS if host_sanitize else HOSTTSAN_FLAGS if host_tsan else ()
     os.makedirs(outdir, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 2) - 1), 16)
@@ -98,6 +110,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--host-sanitize", action="store_true")
+    ap.add_argument("--host-tsan", action="store_true")
     a = ap.parse_args()
-    build(a.jobs, verbose=True, host_sanitize=a.host_sanitize)
+    build(a.jobs, verbose=True, host_sanitize=a.host_sanitize, host_tsan=a.host_tsan)
     sys.exit(0)

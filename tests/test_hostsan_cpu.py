@@ -1,5 +1,5 @@
-"""The library's host code under AddressSanitizer and UndefinedBehaviorSanitizer
-(no GPU): a host-instrumented build (device code unchanged) is loaded in a
+"""The library's host code under AddressSanitizer and UndefinedBehaviorSanitizer,
+and its worker threads under ThreadSanitizer (no GPU): a host-instrumented build (device code unchanged) is loaded in a
 child process with the ASan runtime preloaded, and the host-only entry points
 run through their valid and invalid inputs -- ADAGRAD steps, tuning-cache
 files with malformed and oversized lines, error strings, object lifetimes
@@ -108,3 +108,37 @@ def test_host_entry_points_under_asan_and_ubsan():
     assert p.returncode == 0, p.stdout[-3000:] + p.stderr[-6000:]
     assert "host sanitizer run clean" in p.stdout
     assert "ERROR: AddressSanitizer" not in p.stderr and "runtime error" not in p.stderr
+
+
+def _tsan_stale():
+    lib = build.HOSTTSAN_LIB
+    if not os.path.exists(lib):
+        return True
+    t = os.path.getmtime(lib)
+    return any(os.path.getmtime(s) > t for s in build.sources()) or \
+        os.path.getmtime(os.path.join(ROOT, "include", "pkm.h")) > t
+
+
+def test_host_eigensolver_threads_under_tsan():
+    """The eigensolver's worker threads (the only threads the library starts)
+    under ThreadSanitizer: a host-instrumented libpkm driven by a small C++
+    program built with -fsanitize=thread (tests/tsan_eig_main.cpp), four
+    threads; any data-race report halts it."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(build.HIPCC)), "..", "llvm", "bin",
+                         "clang++")
+    if not os.path.exists(build.HIPCC) or not os.path.exists(clang):
+        pytest.skip("hipcc or clang++ is not installed")
+    if _tsan_stale():
+        build.build(host_tsan=True)
+    exe = os.path.join(build.HOSTTSAN_DIR, "tsan_eig")
+    cc = subprocess.run([clang, "-fsanitize=thread", "-g", "-O1", "-std=c++17",
+                         "-I", os.path.join(ROOT, "include"),
+                         os.path.join(ROOT, "tests", "tsan_eig_main.cpp"), "-o", exe,
+                         "-L", build.HOSTTSAN_DIR, "-lpkm_hosttsan",
+                         "-Wl,-rpath," + build.HOSTTSAN_DIR], capture_output=True, text=True)
+    assert cc.returncode == 0, cc.stderr[-3000:]
+    env = dict(os.environ, PKM_EIG_THREADS="4", TSAN_OPTIONS="halt_on_error=1")
+    p = subprocess.run([exe], env=env, capture_output=True, text=True, timeout=300)
+    assert p.returncode == 0, p.stdout[-3000:] + p.stderr[-6000:]
+    assert "tsan run clean" in p.stdout
+    assert "ThreadSanitizer" not in p.stderr, p.stderr[-6000:]
