@@ -49,7 +49,7 @@ ISSUE_MFMA_HALF, ISSUE_EXP, ISSUE_VALU, SIMDS, CLOCK_HZ = 8.5, 8.0, 4.0, 1024, 2
 # x 1.0): (workload, product, n, k) -> bytes.  Valid while the kernel is
 # unchanged since the counters were taken.
 RECORDED_TRAFFIC = {("block_fp32", "f16x3", 65536, 17): (41858.1 * 2.0 + 34816.0) * 1024,
-                    ("mixed", "i8x", 262144, 33): (6654787.0 * 2.0 + 540672.0) * 1024}
+                    ("mixed", "i8x", 262144, 33): (6650373.9 * 2.0 + 540672.0) * 1024}
 
 
 def _recorded_traffic(p, prec):

@@ -10,10 +10,11 @@
 //              xh = (x - mean) / l * sqrt(log2(e) / 2)), the cross term on
 //              16x16x4 FP64 MFMA (the j norms enter as the accumulator's
 //              initial value), the i norm subtracted in FP64;
-//   exp2       table-driven in FP64 (S = N / 256 + r, |r| <= 1/512; 2^(N / 256)
-//              from a 256-entry LDS table scaled by 2^30; 2^r - 1 by its cubic
-//              Taylor polynomial, truncation ~1e-13 relative), rounded to the
-//              nearest integer kint = rint(2^30 K / sigma2) in [0, 2^30];
+//   exp2       table-driven in FP64 (S = N / 4096 + r, |r| <= 1/8192;
+//              2^(N / 4096) from a 4096-entry LDS table scaled by 2^30; 2^r - 1
+//              by its quadratic Taylor polynomial, truncation ~1e-13
+//              relative), rounded to the nearest integer kint =
+//              rint(2^30 K / sigma2) in [0, 2^30];
 //   digits     kint and vint = rint(2^e V) (per column, max |V| 2^e in
 //              [2^29, 2^30)) written in signed base-256 digits s_0 .. s_3 in
 //              [-128, 127]: x + 0x80808080 has the bytes s_p + 128 (the
@@ -57,8 +58,8 @@ constexpr double kMagicDig = 6755399441055744.0 + 2155905152.0;  // + 0x80808080
 // ---------------------------------------------------------------------------
 // One thread per padded row: xj (16 xh) and xi (32 xh) in 16x16x4 lane order
 // (tile t, lane l, group s) <-> row 16 t + l % 16, slot 4 s + l / 16, with
-// SQ = dq / 4 groups; ni = 256 |xh_i|^2 (0 for padded rows).  The factor 256
-// (exact) makes the contraction 256 S, the form the exp2 rounds in.
+// SQ = dq / 4 groups; ni = 4096 |xh_i|^2 (0 for padded rows).  The factor
+// 4096 (exact) makes the contraction 4096 S, the form the exp2 rounds in.
 __global__ void k_prep_i8(const double* __restrict__ X, int64_t n, int64_t n_pad, int d, int SQ,
                           const double* __restrict__ inv_l, const double* __restrict__ mean,
                           double* __restrict__ xj, double* __restrict__ xi,
@@ -74,14 +75,14 @@ __global__ void k_prep_i8(const double* __restrict__ X, int64_t n, int64_t n_pad
         if (i < n && sl < d) v = (X[i * d + sl] - mean[sl]) * inv_l[sl] * c;
         nrm = fma(v, v, nrm);
         const int64_t at = (t * 64 + row + 16 * (sl & 3)) * SQ + (sl >> 2);
-        xj[at] = 16.0 * v;
-        xi[at] = 32.0 * v;
+        xj[at] = 64.0 * v;
+        xi[at] = 128.0 * v;
     }
-    ni[i] = 256.0 * nrm;
+    ni[i] = 4096.0 * nrm;
 }
 
 // Negated j norms in exponent-tile lane order: njl[(t * 64 + l) * 4 + r] =
-// -256 |xh_j|^2 for j = 16 t + l / 16 + 4 r; padded rows get -1e30 (K = 0).
+// -4096 |xh_j|^2 for j = 16 t + l / 16 + 4 r; padded rows get -1e30 (K = 0).
 // 256 entries per 16-row tile (each norm repeated for the 16 lanes of its
 // lane group): 16 n_pad doubles.
 __global__ void k_prep_njl(const double* __restrict__ ni, int64_t n, int64_t n_pad,
@@ -212,22 +213,23 @@ __device__ inline void transpose_digits(const uint32_t (&w)[4], uint32_t (&out)[
     out[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u) ^ 0x80808080u;
 }
 
-// kint + 0x80808080 (mod 2^32) for kint = rint(2^30 2^S), from S256 = 256 S
-// <= 0 (clamped at -80 x 256, where the value rounds to 0):
-//   N = rint(S256) (through the rounding constant), rr = S256 - N in [-1/2, 1/2],
-//   2^S = 2^(N >> 8) 2^((N & 255) / 256) 2^(rr / 256),
-// the middle factor from tab[m] = 2^30 2^(m / 256), the last as 1 + p with
-// p = q + q^2 / 2 + q^3 / 6, q = rr ln2 / 256 (truncation ~1e-13 relative).
+// kint + 0x80808080 (mod 2^32) for kint = rint(2^30 2^S), from S4 = 4096 S
+// <= 0 (clamped at -80 x 4096, where the value rounds to 0):
+//   N = rint(S4) (through the rounding constant), rr = S4 - N in [-1/2, 1/2],
+//   2^S = 2^(N >> 12) 2^((N & 4095) / 4096) 2^(rr / 4096),
+// the middle factor from tab[m] = 2^30 2^(m / 4096), the last as 1 + p with
+// p = q + q^2 / 2, q = rr ln2 / 4096 (truncation q^3 / 6 < 1.1e-13 relative;
+// a 256-entry table needs the cubic term and one more FMA per entry).
 // Every FP64 operation takes at most one constant that is not an inline one.
-__device__ inline uint32_t kfix_digits(double S256, const double* __restrict__ tab, double c1,
-                                       double c2, double c3) {
-    S256 = fmax(S256, -80.0 * 256.0);
-    const double y = S256 + kMagic;                 // rint(S256) + 1.5 2^52
+__device__ inline uint32_t kfix_digits(double S4, const double* __restrict__ tab, double c1,
+                                       double c2) {
+    S4 = fmax(S4, -80.0 * 4096.0);
+    const double y = S4 + kMagic;                    // rint(S4) + 1.5 2^52
     const int m = __double2loint(y);
-    const double rr = S256 - (y - kMagic);          // exact
-    const double p = rr * fma(rr, fma(rr, c3, c2), c1);
-    const double T = tab[m & 255];
-    const double kf = ldexp(fma(T, p, T), m >> 8);  // 2^30 2^S
+    const double rr = S4 - (y - kMagic);             // exact
+    const double p = rr * fma(rr, c2, c1);
+    const double T = tab[m & 4095];
+    const double kf = ldexp(fma(T, p, T), m >> 12);  // 2^30 2^S
     return uint32_t(__double2loint(kf + kMagicDig));
 }
 
@@ -238,8 +240,8 @@ __global__ __launch_bounds__(256) void k_mvm_i8(
     const v4i* __restrict__ vb, const v4i* __restrict__ vl, const int* __restrict__ ex,
     double* __restrict__ part, int64_t nchunk, int nrb, int jsplit, int64_t chunks_per_split,
     int64_t split_stride, int64_t n_out, int k, double s2) {
-    __shared__ double tab[256];
-    tab[threadIdx.x] = ldexp(exp2(double(threadIdx.x) / 256.0), 30);
+    __shared__ double tab[4096];   // 32 KiB
+    for (int e = threadIdx.x; e < 4096; e += 256) tab[e] = ldexp(exp2(double(e) / 4096.0), 30);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -251,9 +253,9 @@ __global__ __launch_bounds__(256) void k_mvm_i8(
     if (rb >= nrb) return;
     const int64_t itile0 = (int64_t(rb) * 4 + wave) * U;
     const int g = lane >> 4, cl = lane & 15;
-    // polynomial coefficients of 2^(rr / 256) - 1 in rr (held in registers)
-    constexpr double L = 0.6931471805599453 / 256.0;
-    const double c1 = L, c2 = L * L / 2.0, c3 = L * L * L / 6.0;
+    // polynomial coefficients of 2^(rr / 4096) - 1 in rr (held in registers)
+    constexpr double L = 0.6931471805599453 / 4096.0;
+    const double c1 = L, c2 = L * L / 2.0;
 
     double ai[U][SQ], nin[U];
 #pragma unroll
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(256) void k_mvm_i8(
                     st = __builtin_amdgcn_mfma_f64_16x16x4f64(bj[s], ai[u][s], st, 0, 0, 0);
                 uint32_t w[4], dg[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) w[r] = kfix_digits(st[r] - nin[u], tab, c1, c2, c3);
+                for (int r = 0; r < 4; ++r) w[r] = kfix_digits(st[r] - nin[u], tab, c1, c2);
                 transpose_digits(w, dg);
 #pragma unroll
                 for (int p = 0; p < 4; ++p) ka[u][p][jt] = dg[p];
